@@ -1,0 +1,401 @@
+"""Pins for the CPU oracle, independent of the oracle itself (CPU only).
+
+Each test ties the oracle to something it does not compute the same way:
+published generator outputs, closed forms on hand-built graphs, brute force
+over tiny graphs, the greedy approximation bound, monotonicity and
+submodularity of the coverage function, and the IC simulation estimator.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_4779_amd import graphgen as gg
+
+MASK64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------- generator
+
+
+def test_splitmix64_published_outputs():
+    # First outputs of SplitMix64 seeded with 0, as printed by the reference
+    # implementation accompanying Steele, Lea & Flood (OOPSLA 2014) and by
+    # Vigna's public splitmix64.c.
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    got = [oracle.splitmix64_output(0, i) for i in (1, 2, 3)]
+    assert got == expect
+
+
+def _py_live(seed, e, r, p):
+    # Independent big-integer reading of the edge generator rule:
+    # key = output e+1 of SplitMix64(seed); draw = top 32 bits of output r+1
+    # of SplitMix64(key); live iff draw < floor(p * 2^32).
+    def mix(z):
+        z &= MASK64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    gamma = 0x9E3779B97F4A7C15
+    key = mix(seed + (e + 1) * gamma)
+    draw = mix(key + (r + 1) * gamma) >> 32
+    thr = math.floor(float(np.float32(p)) * 2.0 ** 32)
+    return draw < thr
+
+
+def test_live_bits_match_bigint_rule():
+    rng = np.random.default_rng(7)
+    prob = rng.uniform(0, 1, 40).astype(np.float32)
+    prob[:3] = [0.0, 1.0, 0.5]
+    for seed in (1, 12345, 2 ** 63 + 11):
+        bits = oracle.live_bits(prob, 100, seed)
+        for e in range(len(prob)):
+            for r in range(100):
+                got = (int(bits[e, r // 64]) >> (r % 64)) & 1
+                assert got == _py_live(seed, e, r, prob[e]), (seed, e, r)
+
+
+def test_live_bits_padding_prefix_and_extremes():
+    prob = np.array([0.0, 1.0, 0.3, 0.7, 1e-9, 0.999999], dtype=np.float32)
+    b100 = oracle.live_bits(prob, 100, 5)
+    b256 = oracle.live_bits(prob, 256, 5)
+    b64 = oracle.live_bits(prob, 64, 5)
+    assert (b100[:, 1] >> np.uint64(36) == 0).all(), "bits r >= R must be zero"
+    assert (b256[:, 0] == b64[:, 0]).all() and (b256[:, 0] == b100[:, 0]).all()
+    low36 = np.uint64((1 << 36) - 1)
+    assert ((b256[:, 1] & low36) == b100[:, 1]).all(), "snapshots form a prefix family"
+    assert (b256[0] == 0).all(), "p = 0 is never live"
+    assert (b256[1] == np.uint64(MASK64)).all(), "p = 1 is always live"
+
+
+@pytest.mark.parametrize("p", [0.01, 0.05, 0.25, 0.5, 0.9])
+def test_live_bit_frequency(p):
+    m, R = 20000, 256
+    bits = oracle.live_bits(np.full(m, p, np.float32), R, 3)
+    ones = int(sum(bin(int(x)).count("1") for x in bits.ravel()))
+    N = m * R
+    sigma = math.sqrt(N * p * (1 - p))
+    assert abs(ones - N * p) < 5 * sigma
+
+
+def test_live_bits_pairwise_independence():
+    # Same arc, adjacent snapshots; adjacent arcs, same snapshot: the joint
+    # frequency of (1,1) matches p^2 within 5 sigma.
+    m, R, p = 20000, 128, 0.3
+    bits = oracle.live_bits(np.full(m, p, np.float32), R, 9)
+    mat = np.zeros((m, R), dtype=bool)
+    for w in range(2):
+        for b in range(64):
+            mat[:, 64 * w + b] = (bits[:, w] >> np.uint64(b)) & np.uint64(1)
+    for both in (mat[:, :-1] & mat[:, 1:], mat[:-1, :] & mat[1:, :]):
+        N = both.size
+        sigma = math.sqrt(N * p * p * (1 - p * p))
+        assert abs(both.sum() - N * p * p) < 5 * sigma
+
+
+# ---------------------------------------------------------------- brute force
+
+
+def _csr(n, arcs, p):
+    arcs = sorted(arcs)
+    row_ptr = np.zeros(n + 1, np.uint64)
+    for u, _ in arcs:
+        row_ptr[u + 1] += 1
+    row_ptr = np.cumsum(row_ptr).astype(np.uint64)
+    col = np.array([v for _, v in arcs], np.uint32)
+    prob = np.array(p if np.ndim(p) else [p] * len(arcs), np.float32)
+    return row_ptr, col, prob
+
+
+def _snapshots(row_ptr, col, prob, R, seed):
+    """Per snapshot adjacency lists, from the pinned live bits."""
+    n = len(row_ptr) - 1
+    bits = oracle.live_bits(prob, R, seed)
+    adj = [[[] for _ in range(n)] for _ in range(R)]
+    for u in range(n):
+        for e in range(int(row_ptr[u]), int(row_ptr[u + 1])):
+            for r in range(R):
+                if (int(bits[e, r // 64]) >> (r % 64)) & 1:
+                    adj[r][u].append(int(col[e]))
+    return adj
+
+
+def _reach(adj_r, srcs):
+    seen = set(srcs)
+    stack = list(srcs)
+    while stack:
+        x = stack.pop()
+        for v in adj_r[x]:
+            if v not in seen:
+                seen.add(v)
+                stack.append(v)
+    return seen
+
+
+def _f(adj, S):
+    return sum(len(_reach(a, S)) for a in adj) if S else 0
+
+
+def _greedy_by_definition(adj, n, k):
+    S, gains = [], []
+    fS = 0
+    for _ in range(k):
+        best, bestv = None, -1
+        for v in range(n):
+            if v in S:
+                continue
+            val = _f(adj, S + [v]) - fS
+            if val > bestv:
+                best, bestv = v, val
+        S.append(best)
+        gains.append(bestv)
+        fS += bestv
+    return S, gains
+
+
+def _random_graph(rng, n, m, pmin=0.05, pmax=0.9):
+    arcs = set()
+    while len(arcs) < m:
+        u, v = rng.integers(0, n, 2)
+        if u != v:
+            arcs.add((int(u), int(v)))
+    arcs = sorted(arcs)
+    p = rng.uniform(pmin, pmax, len(arcs)).astype(np.float32)
+    return _csr(n, arcs, p)
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_oracles_equal_bruteforce_greedy(case):
+    rng = np.random.default_rng(100 + case)
+    n = int(rng.integers(4, 13))
+    m = int(rng.integers(0, min(3 * n, n * (n - 1)) + 1))
+    R = int(rng.choice([1, 3, 64, 70]))
+    k = int(rng.integers(1, n + 1))
+    seed = int(rng.integers(0, 2 ** 63))
+    row_ptr, col, prob = _random_graph(rng, n, m)
+    adj = _snapshots(row_ptr, col, prob, R, seed)
+    S_ref, g_ref = _greedy_by_definition(adj, n, k)
+    s_du, g_du, tr, _ = oracle.select_du(row_ptr, col, prob, R, k, seed, trace=True)
+    s_a1, g_a1 = oracle.select_alg1(row_ptr, col, prob, R, k, seed)
+    s_cf, g_cf, _ = oracle.select_celf(row_ptr, col, prob, R, k, seed)
+    for s, g in ((s_du, g_du), (s_a1, g_a1), (s_cf, g_cf)):
+        assert list(s) == S_ref
+        assert list(g) == g_ref
+    # the DU trace holds the exact marginal gain of every node in every round
+    for t in range(k + 1):
+        S = S_ref[:t]
+        fS = _f(adj, S)
+        for u in range(n):
+            expect = 0 if u in S else _f(adj, S + [u]) - fS
+            assert int(tr[t, u]) == expect, (t, u)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_greedy_approximation_bound(case):
+    # Nemhauser et al.: greedy on a monotone submodular function reaches at
+    # least (1 - 1/e) of the optimum (Sec. 3.2). Exhaustive optimum, n <= 14.
+    rng = np.random.default_rng(200 + case)
+    n = int(rng.integers(6, 15))
+    row_ptr, col, prob = _random_graph(rng, n, int(rng.integers(n, 3 * n)), 0.1, 0.6)
+    R, k = 16, int(rng.integers(2, 5))
+    seeds, gains, _, _ = oracle.select_du(row_ptr, col, prob, R, k, 77)
+    adj = _snapshots(row_ptr, col, prob, R, 77)
+    opt = max(_f(adj, list(S)) for S in itertools.combinations(range(n), k))
+    got = int(gains.sum())
+    assert got == _f(adj, list(seeds))
+    assert got >= (1 - 1 / math.e) * opt
+    assert got <= opt
+
+
+def test_coverage_monotone_submodular():
+    rng = np.random.default_rng(5)
+    g = gg.chung_lu_graph(300, 1500, 2.5, 11, True, 0.2)
+    R, seed = 32, 4
+    for _ in range(20):
+        T = list(rng.choice(300, size=6, replace=False))
+        S = T[: int(rng.integers(0, 6))]
+        v = int(rng.integers(0, 300))
+        if v in T:
+            continue
+        fS = oracle.spread(g.row_ptr, g.col, g.prob, R, seed, S) if S else 0
+        fT = oracle.spread(g.row_ptr, g.col, g.prob, R, seed, T)
+        fSv = oracle.spread(g.row_ptr, g.col, g.prob, R, seed, S + [v])
+        fTv = oracle.spread(g.row_ptr, g.col, g.prob, R, seed, T + [v])
+        assert fSv >= fS and fTv >= fT and fT >= fS
+        assert fSv - fS >= fTv - fT
+
+
+# ---------------------------------------------------------------- closed forms
+
+
+def test_p_zero_everything_is_R():
+    n, R, k = 50, 100, 7
+    row_ptr, col, prob = _csr(n, [(i, (i * 7 + 3) % n) for i in range(n) if (i * 7 + 3) % n != i], 0.0)
+    seeds, gains, tr, _ = oracle.select_du(row_ptr, col, prob, R, k, 1, trace=True)
+    assert list(seeds) == list(range(k))
+    assert list(gains) == [R] * k
+    init, _ = oracle.initial_gains(row_ptr, col, prob, R, 1)
+    assert (init == R).all()
+
+
+def test_p_one_path():
+    n, R = 9, 70
+    row_ptr, col, prob = _csr(n, [(i, i + 1) for i in range(n - 1)], 1.0)
+    init, _ = oracle.initial_gains(row_ptr, col, prob, R, 3)
+    assert list(init) == [R * (n - u) for u in range(n)]
+    seeds, gains, _, _ = oracle.select_du(row_ptr, col, prob, R, 4, 3)
+    assert list(seeds) == [0, 1, 2, 3] and list(gains) == [R * n, 0, 0, 0]
+
+
+def test_p_one_star_and_components():
+    # star 0 -> 1..5, plus a separate path 6 -> 7 -> 8 and an isolated 9
+    arcs = [(0, i) for i in range(1, 6)] + [(6, 7), (7, 8)]
+    row_ptr, col, prob = _csr(10, arcs, 1.0)
+    R = 64
+    seeds, gains, _, _ = oracle.select_du(row_ptr, col, prob, R, 4, 9)
+    assert list(seeds) == [0, 6, 9, 1]
+    assert list(gains) == [6 * R, 3 * R, R, 0]
+
+
+def test_p_one_complete_digraph():
+    n, R = 8, 10
+    arcs = [(u, v) for u in range(n) for v in range(n) if u != v]
+    row_ptr, col, prob = _csr(n, arcs, 1.0)
+    seeds, gains, _, _ = oracle.select_du(row_ptr, col, prob, R, 3, 1)
+    assert list(seeds) == [0, 1, 2] and list(gains) == [n * R, 0, 0]
+
+
+@pytest.mark.parametrize("p", [0.0, 0.2, 0.5, 1.0])
+def test_two_node_arc(p):
+    R, seed = 200, 17
+    row_ptr, col, prob = _csr(2, [(0, 1)], p)
+    live = sum(_py_live(seed, 0, r, p) for r in range(R))
+    init, _ = oracle.initial_gains(row_ptr, col, prob, R, seed)
+    assert list(init) == [R + live, R]
+    seeds, gains, _, _ = oracle.select_du(row_ptr, col, prob, R, 2, seed)
+    assert list(seeds) == [0, 1]
+    assert list(gains) == [R + live, R - live]
+
+
+def test_reverse_count_equals_forward_count():
+    # sum_u |R_r(u)| = sum_x |U_r(x)|: both count reachable pairs.
+    rng = np.random.default_rng(31)
+    row_ptr, col, prob = _random_graph(rng, 12, 30, 0.2, 0.8)
+    R = 20
+    adj = _snapshots(row_ptr, col, prob, R, 2)
+    radj = [[[] for _ in range(12)] for _ in range(R)]
+    for r in range(R):
+        for u in range(12):
+            for v in adj[r][u]:
+                radj[r][v].append(u)
+    rev_total = sum(len(_reach(radj[r], [x])) for r in range(R) for x in range(12))
+    init, _ = oracle.initial_gains(row_ptr, col, prob, R, 2)
+    assert int(init.sum()) == rev_total
+
+
+# ---------------------------------------------------------------- workloads
+
+
+@pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
+def test_workload_invariants(name):
+    w = gg.WORKLOADS[name]
+    g = gg.workload_graph(name)
+    R, k, seed = w["R"], w["k"], w["seed"]
+    seeds, gains, tr, st = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    s_cf, g_cf, _ = oracle.select_celf(g.row_ptr, g.col, g.prob, R, k, seed)
+    assert (s_cf == seeds).all() and (g_cf == gains).all()
+    assert (np.diff(gains.astype(np.int64)) <= 0).all(), "gains never increase"
+    assert int(gains.sum()) == oracle.spread(g.row_ptr, g.col, g.prob, R, seed, seeds)
+    assert len(set(seeds.tolist())) == k
+    init, _ = oracle.initial_gains(g.row_ptr, g.col, g.prob, R, seed)
+    assert (tr[0] == init).all() and (init >= R).all()
+    for t in range(k):
+        assert tr[t, seeds[t]] == gains[t]
+        assert tr[t + 1, seeds[t]] == 0
+        assert (tr[t + 1] <= tr[t]).all(), "static snapshots keep gains submodular"
+        unsel = np.ones(g.n, bool)
+        unsel[seeds[:t]] = False
+        assert tr[t][unsel].max() == gains[t]
+        assert np.flatnonzero(unsel & (tr[t] == gains[t]))[0] == seeds[t]
+
+
+# ---------------------------------------------------------------- semantics
+
+
+def test_snapshot_estimate_matches_simulation():
+    # Sec. 3.1: the snapshot estimator and the round-by-round cascade
+    # simulation estimate the same I(S). Compare for single seeds.
+    g = gg.chung_lu_graph(200, 900, 2.5, 21, True, 0.15)
+    R = 4096
+    init, _ = oracle.initial_gains(g.row_ptr, g.col, g.prob, R, 8)
+    rng = np.random.default_rng(0)
+    sims = 4000
+    rp = g.row_ptr.astype(np.int64)
+    for s in (0, 5, 17, int(np.argmax(init))):
+        sizes = []
+        for _ in range(sims):
+            active = {s}
+            frontier = [s]
+            while frontier:
+                nxt = []
+                for u in frontier:
+                    for e in range(rp[u], rp[u + 1]):
+                        v = int(g.col[e])
+                        if v not in active and rng.random() < g.prob[e]:
+                            active.add(v)
+                            nxt.append(v)
+                frontier = nxt
+            sizes.append(len(active))
+        sizes = np.array(sizes, float)
+        est_snap = init[s] / R
+        se = math.sqrt(sizes.var() / sims + sizes.var() / R) + 1e-9
+        assert abs(sizes.mean() - est_snap) < 5 * se, (s, sizes.mean(), est_snap)
+
+
+def test_fresh_snapshots_break_submodularity_static_do_not():
+    # Sec. 3.2 / Fig. 1: estimating round 1 and round 2 on different
+    # snapshots can make a marginal gain grow; static snapshots never do.
+    arcs = [(0, 1), (1, 2), (3, 4), (4, 2), (2, 5), (5, 6)]
+    row_ptr, col, prob = _csr(7, arcs, 0.5)
+    R = 1
+    found = False
+    for s1 in range(1, 200):
+        a1 = _snapshots(row_ptr, col, prob, R, s1)
+        a2 = _snapshots(row_ptr, col, prob, R, s1 + 1000)
+        first = max(range(7), key=lambda v: _f(a1, [v]))
+        for v in range(7):
+            if v == first:
+                continue
+            g1 = _f(a1, [v])
+            g2 = _f(a2, [first, v]) - _f(a2, [first])
+            if g2 > g1:
+                found = True
+        for a in (a1, a2):
+            for v in range(7):
+                if v != first:
+                    assert _f(a, [first, v]) - _f(a, [first]) <= _f(a, [v])
+    assert found
+
+
+# ---------------------------------------------------------------- errors
+
+
+def test_oracle_rejects_bad_input():
+    row_ptr, col, prob = _csr(3, [(0, 1), (1, 2)], 0.5)
+    with pytest.raises(oracle.OracleError):
+        oracle.select_du(row_ptr, col, prob, 0, 1, 1)
+    with pytest.raises(oracle.OracleError):
+        oracle.select_du(row_ptr, col, prob, 64, 4, 1)
+    bad = prob.copy()
+    bad[0] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.select_du(row_ptr, col, bad, 64, 1, 1)
+    badc = col.copy()
+    badc[1] = 3
+    with pytest.raises(oracle.OracleError):
+        oracle.select_du(row_ptr, badc, prob, 64, 1, 1)
+    seeds, gains, _, _ = oracle.select_du(row_ptr, col, prob, 64, 0, 1)
+    assert len(seeds) == 0
