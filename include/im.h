@@ -1,0 +1,133 @@
+/*
+ * im.h -- C ABI of the MI355X StaticGreedy influence-maximization library.
+ *
+ * Problem (Cheng et al., CIKM 2013, Sec. 3.1): a directed graph G=(V,E)
+ * with a propagation probability p(u,v) on every arc, under the
+ * independent cascade model; find S, |S| <= k, maximising the spread.
+ * Method: StaticGreedy (Sec. 3.3, Algorithm 1) on R snapshots sampled once,
+ * with the marginal gains kept current by the dynamic update of Sec. 4
+ * (Algorithm 2).
+ *
+ * Result definition (exact, integer):
+ *   arc e is live in snapshot r iff draw(seed, e, r) < floor(p_e * 2^32),
+ *     draw = top 32 bits of SplitMix64 output r+1 from state key_e,
+ *     key_e = SplitMix64 output e+1 from state seed  (Steele et al. 2014);
+ *   R_r(u) = nodes reachable from u over live arcs of snapshot r, u included;
+ *   f(S) = sum_r |union_{s in S} R_r(s)|;
+ *   round i adds the unselected node with the largest f(S+u) - f(S), ties to
+ *   the lowest id, and reports that marginal gain (summed over snapshots,
+ *   not divided by R).
+ * Outputs depend only on (graph, prob, R, k, seed): not on the stream, the
+ * workspace, the launch schedule or which selection path is used.
+ *
+ * Memory: unless a parameter says "host", every pointer is a device pointer
+ * owned by the caller. The library keeps no pointer after a call's work on
+ * its stream has completed. Work is enqueued on `stream` (a hipStream_t
+ * passed as void*, NULL = default stream); calls return once the work is
+ * enqueued, except where marked "synchronous".
+ *
+ * Errors: every call returns IM_OK (0) or a negative IM_E* code;
+ * im_last_error() returns a thread-local message for the last failure.
+ * On a validation error nothing is written to the outputs.
+ */
+#ifndef IM_H
+#define IM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IM_OK         0
+#define IM_EINVAL    (-1)   /* bad argument or malformed graph            */
+#define IM_EOVERFLOW (-2)   /* n * R >= 2^32: gains would not fit 32 bits */
+#define IM_ENOMEM    (-3)   /* device allocation failed                   */
+#define IM_EHIP      (-4)   /* a HIP runtime call failed                  */
+
+#define IM_R_MAX 4096u
+
+/* Graph in CSR form, device-resident, caller-owned, read-only.
+ * Arc e (0 <= e < m) is the e-th entry of col; its tail is the u with
+ * row_ptr[u] <= e < row_ptr[u+1]. Duplicate arcs and self-loops are
+ * allowed; each stored arc is its own coin. */
+typedef struct im_graph {
+    uint32_t        n;        /* nodes 0..n-1                                  */
+    uint64_t        m;        /* arcs, < 2^32                                  */
+    const uint64_t *row_ptr;  /* [n+1], row_ptr[0]=0, non-decreasing, [n]=m   */
+    const uint32_t *col;      /* [m], each < n                                 */
+    const float    *prob;     /* [m], 0 <= p <= 1, no NaN                      */
+} im_graph;
+
+/* Opaque device workspace (library-owned). Grows on demand inside the
+ * calls below; one workspace must not be used by two calls at once. */
+typedef struct im_workspace im_workspace;
+
+int im_workspace_create(im_workspace **ws);
+int im_workspace_destroy(im_workspace *ws);
+
+/* Counters of the last call on a workspace (synchronous: waits for the
+ * stream of that call). Traversal counts follow the per-snapshot
+ * definition: the full out-degree (in-degree for reverse steps) of every
+ * node reached in every snapshot by every reachability task. */
+typedef struct im_stats {
+    uint64_t trav_init;        /* initial reach counts (Alg. 2 initial loop)      */
+    uint64_t trav_fwd;         /* forward steps from the chosen seeds             */
+    uint64_t trav_rev;         /* reverse decrement steps                         */
+    uint64_t relax_init;       /* sum over (source, word) tasks of the out-degree */
+                               /* of every node reached in that word              */
+    uint64_t reached_init;     /* number of (task, reached node) pairs            */
+    uint64_t relax_rev;        /* as relax_init, for the reverse tasks (in-deg)   */
+    uint64_t reached_rev;
+    uint64_t relax_fwd;
+    uint64_t arcs_read_init;   /* (arc, word) reads actually issued               */
+    uint64_t arcs_read_rev;
+    uint64_t ovf_init;         /* tasks moved to the block-wide engine            */
+    uint64_t ovf_rev;
+    uint64_t tasks_rev;        /* reverse tasks (newly covered (node, word) pairs)*/
+    uint64_t decrements;       /* sum of the decrements applied to gains          */
+    uint64_t celf_evals;       /* exact gain evaluations (lazy path)              */
+    uint64_t reserved[17];
+} im_stats;
+
+int im_stats_get(im_workspace *ws, im_stats *out);
+
+/* Thread-local message describing the last error. */
+const char *im_last_error(void);
+
+/* Validate a graph (synchronous). Checks row_ptr shape and monotonicity,
+ * col < n, 0 <= prob <= 1 (NaN rejected), m < 2^32, and, for R > 0, that
+ * 1 <= R <= IM_R_MAX and n*R < 2^32. Returns IM_OK or IM_EINVAL/IM_EOVERFLOW. */
+int im_validate(const im_graph *g, uint32_t R, void *stream);
+
+/* Snapshot masks (Sec. 3.3, Algorithm 1 sampling loop; Sec. 3.1 snapshot
+ * definition). mask_out: [W][m] uint64, W = ceil(R/64), word-major: word w
+ * of arc e at mask_out[w*m + e]; bit b = snapshot 64w+b; bits r >= R zero. */
+int im_snapshot_masks(const im_graph *g, uint32_t R, uint64_t seed,
+                      uint64_t *mask_out, im_workspace *ws, void *stream);
+
+/* Reverse graph used by U(G'_i, w) (Sec. 4): in_row_ptr [n+1] (uint32),
+ * in_col [m] = tail of each in-arc, in2out [m] = the arc id in the caller's
+ * CSR. Order inside a row is unspecified. */
+int im_transpose(const im_graph *g, uint32_t *in_row_ptr, uint32_t *in_col,
+                 uint32_t *in2out, im_workspace *ws, void *stream);
+
+/* Initial per-node reach counts (Algorithm 2, initial loop):
+ * gain_out[u] = sum_r |R_r(u)|, uint32 [n]. */
+int im_initial_gains(const im_graph *g, uint32_t R, uint64_t seed,
+                     uint32_t *gain_out, im_workspace *ws, void *stream);
+
+/* k-seed selection (Algorithm 2 with the exact-gain argmax of Algorithm 1).
+ * seeds_out [k] uint32, gains_out [k] uint64 (device). trace_out may be
+ * NULL; otherwise [k+1][n] uint32 receives the gain vector at the start of
+ * every round and after the last (the exact marginal gain of every
+ * unselected node; 0 for selected ones). k <= n; k = 0 writes nothing. */
+int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+              uint32_t *seeds_out, uint64_t *gains_out, uint32_t *trace_out,
+              im_workspace *ws, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IM_H */

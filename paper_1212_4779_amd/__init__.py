@@ -1,1 +1,8 @@
+"""StaticGreedy influence maximisation on one MI355X (gfx950).
 
+Cheng et al., "StaticGreedy: Solving the Scalability-Accuracy Dilemma in
+Influence Maximization", CIKM 2013 (arXiv 1212.4779). The selection runs in
+hand-written HIP kernels behind the C ABI of include/im.h; this package only
+passes torch tensors' device pointers and the current stream to it.
+"""
+from .api import Workspace, Graph, select, initial_gains, snapshot_masks, transpose, validate  # noqa: F401

@@ -1,0 +1,68 @@
+"""ctypes view of libim.so (the C ABI declared in include/im.h).
+
+Argument marshalling only: every step of the selection runs in the HIP
+kernels behind these entry points. There is no fallback; if the library is
+missing the import fails.
+"""
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libim.so")
+
+IM_OK, IM_EINVAL, IM_EOVERFLOW, IM_ENOMEM, IM_EHIP = 0, -1, -2, -3, -4
+IM_R_MAX = 4096
+
+EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_last_error",
+           "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select")
+
+
+class ImGraph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("prob", ctypes.c_void_p)]
+
+
+STAT_FIELDS = ("trav_init", "trav_fwd", "trav_rev", "relax_init", "reached_init", "relax_rev",
+               "reached_rev", "relax_fwd", "arcs_read_init", "arcs_read_rev", "ovf_init",
+               "ovf_rev", "tasks_rev", "decrements", "celf_evals")
+
+
+class ImStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in STAT_FIELDS] + [("reserved", ctypes.c_uint64 * 17)]
+
+
+class ImError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libim error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (paper_1212_4779_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        p, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        G = ctypes.POINTER(ImGraph)
+        L.im_workspace_create.argtypes = [ctypes.POINTER(p)]
+        L.im_workspace_destroy.argtypes = [p]
+        L.im_stats_get.argtypes = [p, ctypes.POINTER(ImStats)]
+        L.im_last_error.restype = ctypes.c_char_p
+        L.im_validate.argtypes = [G, u32, p]
+        L.im_snapshot_masks.argtypes = [G, u32, u64, p, p, p]
+        L.im_transpose.argtypes = [G, p, p, p, p, p]
+        L.im_initial_gains.argtypes = [G, u32, u64, p, p, p]
+        L.im_select.argtypes = [G, u32, u32, u64, p, p, p, p, p]
+        for name in EXPORTS:
+            getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != IM_OK:
+        raise ImError(rc, lib().im_last_error().decode())

@@ -1,0 +1,155 @@
+"""Python binding of the C ABI (include/im.h).
+
+torch supplies device memory and the current HIP stream; every step of the
+selection runs in libim's kernels. Tensors passed in must already live on
+the GPU; nothing here computes on the host.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _u32(t):
+    """int32 tensor holding uint32 bit patterns -> int64 values."""
+    return t.to(torch.int64) & 0xFFFFFFFF
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Graph:
+    """Device-resident CSR graph with one IC probability per stored arc.
+
+    row_ptr: int64 [n+1]; col: int32 or uint32 [m] (node ids < n);
+    prob: float32 [m]. Arc e is position e of col.
+    """
+
+    def __init__(self, row_ptr, col, prob):
+        if not (row_ptr.is_cuda and col.is_cuda and prob.is_cuda):
+            raise ValueError("graph tensors must be on the GPU")
+        if row_ptr.dtype not in (torch.int64, torch.uint64):
+            raise ValueError("row_ptr must be int64")
+        if col.dtype not in (torch.int32, torch.uint32):
+            raise ValueError("col must be int32 or uint32")
+        if prob.dtype != torch.float32:
+            raise ValueError("prob must be float32")
+        self.row_ptr = row_ptr.contiguous()
+        self.col = col.contiguous()
+        self.prob = prob.contiguous()
+        self.n = int(row_ptr.numel()) - 1
+        self.m = int(col.numel())
+        self.device = row_ptr.device
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col, prob, device="cuda"):
+        rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.uint64).view(np.int64))
+        c = torch.from_numpy(np.ascontiguousarray(col, dtype=np.uint32).view(np.int32))
+        p = torch.from_numpy(np.ascontiguousarray(prob, dtype=np.float32))
+        return cls(rp.to(device), c.to(device), p.to(device))
+
+    def c_struct(self):
+        return N.ImGraph(self.n, self.m, self.row_ptr.data_ptr(),
+                         self.col.data_ptr() if self.m else 0,
+                         self.prob.data_ptr() if self.m else 0)
+
+
+class Workspace:
+    """Library-owned device workspace; grows on demand, reused across calls."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        N.check(N.lib().im_workspace_create(ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            N.lib().im_workspace_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self):
+        st = N.ImStats()
+        N.check(N.lib().im_stats_get(self.handle, ctypes.byref(st)))
+        return {f: int(getattr(st, f)) for f in N.STAT_FIELDS}
+
+
+_default_ws = {}
+
+
+def _ws(ws, device):
+    if ws is not None:
+        return ws
+    key = torch.device(device).index or 0
+    if key not in _default_ws:
+        with torch.cuda.device(key):
+            _default_ws[key] = Workspace()
+    return _default_ws[key]
+
+
+def validate(graph, R=0):
+    g = graph.c_struct()
+    N.check(N.lib().im_validate(ctypes.byref(g), R, _stream(graph.device)))
+
+
+def snapshot_masks(graph, R, seed, ws=None):
+    """uint64 masks, word-major [W, m] (returned as int64 bit patterns)."""
+    W = (R + 63) // 64
+    out = torch.empty((W, graph.m), dtype=torch.int64, device=graph.device)
+    g = graph.c_struct()
+    ws = _ws(ws, graph.device)
+    N.check(N.lib().im_snapshot_masks(ctypes.byref(g), R, seed, _ptr(out), ws.handle,
+                                      _stream(graph.device)))
+    return out
+
+
+def transpose(graph, ws=None):
+    """Reverse CSR: (in_row_ptr [n+1], in_col [m], in2out [m]) as int32 tensors."""
+    dev = graph.device
+    in_row = torch.empty(graph.n + 1, dtype=torch.int32, device=dev)
+    in_col = torch.empty(graph.m, dtype=torch.int32, device=dev)
+    in2out = torch.empty(graph.m, dtype=torch.int32, device=dev)
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_transpose(ctypes.byref(g), _ptr(in_row), _ptr(in_col), _ptr(in2out),
+                                 ws.handle, _stream(dev)))
+    return in_row, in_col, in2out
+
+
+def initial_gains(graph, R, seed, ws=None):
+    """s_u = sum_r |R_r(u)| as an int64 tensor [n]."""
+    out = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+    g = graph.c_struct()
+    ws = _ws(ws, graph.device)
+    N.check(N.lib().im_initial_gains(ctypes.byref(g), R, seed, _ptr(out), ws.handle,
+                                     _stream(graph.device)))
+    return _u32(out)
+
+
+def select(graph, R, k, seed, ws=None, trace=False):
+    """k seeds and their marginal gains (summed over the R snapshots).
+
+    Returns (seeds int64 [k], gains int64 [k], trace int64 [k+1, n] or None).
+    """
+    dev = graph.device
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    gains = torch.empty(k, dtype=torch.int64, device=dev)
+    tr = torch.empty((k + 1, graph.n), dtype=torch.int32, device=dev) if trace else None
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_select(ctypes.byref(g), R, k, seed, _ptr(seeds), _ptr(gains),
+                              _ptr(tr) if trace else ctypes.c_void_p(0), ws.handle,
+                              _stream(dev)))
+    return _u32(seeds), gains, (_u32(tr) if trace else None)
