@@ -66,6 +66,19 @@ typedef struct im_workspace im_workspace;
 int im_workspace_create(im_workspace **ws);
 int im_workspace_destroy(im_workspace *ws);
 
+/* Execution options of a workspace. None of them changes any result; they
+ * only choose how the work is scheduled.
+ *   IM_OPT_HUB_DEGREE: nodes with at least this many arcs (in the direction
+ *     of a pass) are expanded through per-snapshot live lists instead of the
+ *     snapshot masks; 0 disables the lists; otherwise >= 16. Default 1024.
+ *   IM_OPT_COOP_GAIN: rounds whose seed gain (summed over snapshots) is at
+ *     least this value run the forward search on a cooperative grid of all
+ *     CUs; smaller rounds use one workgroup per snapshot word. 0: always
+ *     cooperative. Default: never (the per-word kernel
+ *     measured faster at every threshold on the million-node workload). */
+enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2 };
+int im_workspace_set(im_workspace *ws, int option, int64_t value);
+
 /* Counters of the last call on a workspace (synchronous: waits for the
  * stream of that call). Traversal counts follow the per-snapshot
  * definition: the full out-degree (in-degree for reverse steps) of every
@@ -74,23 +87,42 @@ typedef struct im_stats {
     uint64_t trav_init;        /* initial reach counts (Alg. 2 initial loop)      */
     uint64_t trav_fwd;         /* forward steps from the chosen seeds             */
     uint64_t trav_rev;         /* reverse decrement steps                         */
-    uint64_t relax_init;       /* sum over (source, word) tasks of the out-degree */
-                               /* of every node reached in that word              */
-    uint64_t reached_init;     /* number of (task, reached node) pairs            */
-    uint64_t relax_rev;        /* as relax_init, for the reverse tasks (in-deg)   */
-    uint64_t reached_rev;
-    uint64_t relax_fwd;
-    uint64_t arcs_read_init;   /* (arc, word) reads actually issued               */
-    uint64_t arcs_read_rev;
-    uint64_t ovf_init;         /* tasks moved to the block-wide engine            */
-    uint64_t ovf_rev;
+    uint64_t trav_eval;        /* exact gain evaluations of the lazy path         */
+    uint64_t relax_fwd;        /* sum of out-degrees of nodes newly covered       */
     uint64_t tasks_rev;        /* reverse tasks (newly covered (node, word) pairs)*/
     uint64_t decrements;       /* sum of the decrements applied to gains          */
     uint64_t celf_evals;       /* exact gain evaluations (lazy path)              */
-    uint64_t reserved[17];
+    /* Per pass p (0: initial counts, 1: reverse decrements, 2: exact
+     * evaluations) and engine tier t (0: per-wavefront LDS tables, 1:
+     * per-workgroup LDS tables, 2: per-workgroup dense global arrays):    */
+    uint64_t relax[3][3];      /* sum over (node, word) tasks of the degree of    */
+                               /* every node reached in that word                 */
+    uint64_t reached[3][3];    /* (task, reached node) pairs                      */
+    uint64_t arcs_read[3][3];  /* (arc, word) reads issued, re-expansions included*/
+    uint64_t handed_over[3][3];/* tasks passed on to the next tier                */
+    uint64_t reserved[20];
 } im_stats;
 
 int im_stats_get(im_workspace *ws, im_stats *out);
+
+/* Phase timers. When the bit (1 << phase) of `mask` is set, every later
+ * call on this workspace brackets that phase's kernel launches with HIP
+ * events on the call's stream. im_profile_get (synchronous) returns the
+ * summed milliseconds and launch counts since the previous get and resets
+ * them. Timing changes no result. */
+enum {
+    IM_PH_VALIDATE = 0, IM_PH_TRANSPOSE, IM_PH_MASK_GEN, IM_PH_MASK_GATHER,
+    IM_PH_INIT_T0, IM_PH_INIT_T1, IM_PH_INIT_T2, IM_PH_ARGMAX, IM_PH_FORWARD,
+    IM_PH_REV_T0, IM_PH_REV_T1, IM_PH_REV_T2, IM_PH_CLEAR, IM_PH_CALL, IM_PH_HUBS,
+    IM_PH_COUNT
+};
+typedef struct im_profile {
+    double   ms[16];
+    uint64_t launches[16];
+} im_profile;
+
+int im_profile_enable(im_workspace *ws, uint32_t mask);
+int im_profile_get(im_workspace *ws, im_profile *out);
 
 /* Thread-local message describing the last error. */
 const char *im_last_error(void);

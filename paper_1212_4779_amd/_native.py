@@ -14,7 +14,13 @@ IM_OK, IM_EINVAL, IM_EOVERFLOW, IM_ENOMEM, IM_EHIP = 0, -1, -2, -3, -4
 IM_R_MAX = 4096
 
 EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_last_error",
-           "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select")
+           "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select",
+           "im_profile_enable", "im_profile_get", "im_workspace_set")
+
+PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
+          "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs")
+IM_OPT_HUB_DEGREE = 1
+IM_OPT_COOP_GAIN = 2
 
 
 class ImGraph(ctypes.Structure):
@@ -22,13 +28,31 @@ class ImGraph(ctypes.Structure):
                 ("col", ctypes.c_void_p), ("prob", ctypes.c_void_p)]
 
 
-STAT_FIELDS = ("trav_init", "trav_fwd", "trav_rev", "relax_init", "reached_init", "relax_rev",
-               "reached_rev", "relax_fwd", "arcs_read_init", "arcs_read_rev", "ovf_init",
-               "ovf_rev", "tasks_rev", "decrements", "celf_evals")
+STAT_FIELDS = ("trav_init", "trav_fwd", "trav_rev", "trav_eval", "relax_fwd", "tasks_rev",
+               "decrements", "celf_evals")
+PASSES = ("init", "rev", "eval")
+TIER_FIELDS = ("relax", "reached", "arcs_read", "handed_over")
 
 
 class ImStats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_uint64) for f in STAT_FIELDS] + [("reserved", ctypes.c_uint64 * 17)]
+    _fields_ = ([(f, ctypes.c_uint64) for f in STAT_FIELDS] +
+                [(f, (ctypes.c_uint64 * 3) * 3) for f in TIER_FIELDS] +
+                [("reserved", ctypes.c_uint64 * 20)])
+
+    def as_dict(self):
+        d = {f: int(getattr(self, f)) for f in STAT_FIELDS}
+        for f in TIER_FIELDS:
+            arr = getattr(self, f)
+            for p, pn in enumerate(PASSES):
+                per = [int(arr[p][t]) for t in range(3)]
+                d[f"{f}_{pn}"] = sum(per)
+                for t in range(3):
+                    d[f"{f}_{pn}_t{t}"] = per[t]
+        return d
+
+
+class ImProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_uint64 * 16)]
 
 
 class ImError(RuntimeError):
@@ -57,6 +81,9 @@ def lib():
         L.im_transpose.argtypes = [G, p, p, p, p, p]
         L.im_initial_gains.argtypes = [G, u32, u64, p, p, p]
         L.im_select.argtypes = [G, u32, u32, u64, p, p, p, p, p]
+        L.im_profile_enable.argtypes = [p, u32]
+        L.im_workspace_set.argtypes = [p, ctypes.c_int, ctypes.c_int64]
+        L.im_profile_get.argtypes = [p, ctypes.POINTER(ImProfile)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

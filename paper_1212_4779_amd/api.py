@@ -80,10 +80,32 @@ class Workspace:
         except Exception:
             pass
 
+    def set_hub_degree(self, deg):
+        """Heavy-node threshold for per-snapshot live lists (0: off). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_HUB_DEGREE, int(deg)))
+
+    def set_coop_gain(self, gain):
+        """Rounds with seed gain >= gain use the grid-wide forward search. No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_COOP_GAIN, int(gain)))
+
+    def profile_enable(self, phases=None):
+        """Time the named phases (None: all) with HIP events from now on."""
+        names = N.PHASES if phases is None else phases
+        mask = 0
+        for nm in names:
+            mask |= 1 << N.PHASES.index(nm)
+        N.check(N.lib().im_profile_enable(self.handle, mask))
+
+    def profile(self):
+        """{phase: (total_ms, launches)} since the previous call (synchronous)."""
+        pr = N.ImProfile()
+        N.check(N.lib().im_profile_get(self.handle, ctypes.byref(pr)))
+        return {nm: (float(pr.ms[i]), int(pr.launches[i])) for i, nm in enumerate(N.PHASES)}
+
     def stats(self):
         st = N.ImStats()
         N.check(N.lib().im_stats_get(self.handle, ctypes.byref(st)))
-        return {f: int(getattr(st, f)) for f in N.STAT_FIELDS}
+        return st.as_dict()
 
 
 _default_ws = {}

@@ -24,6 +24,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
+
+#include <hip/hip_cooperative_groups.h>
 
 #include "im.h"
 #include "im_bfs.h"
@@ -108,11 +111,68 @@ __global__ void k_validate(const uint64_t *row_ptr, const uint32_t *col, const f
     if (e) atomicOr(err, e);
 }
 
-__global__ void k_hist(const uint32_t *col, uint64_t m, uint32_t *cnt)
+// Reverse-CSR construction. Arcs into one high in-degree node are spread over
+// the whole arc array, so plain per-arc global atomics on its counter
+// serialise. Each workgroup therefore first aggregates its contiguous slice of
+// arcs in an LDS hash table (head -> count) and touches each global counter
+// once per distinct head.
+constexpr int TR_NT = 256, TR_ARCS = 4096, TR_HT = 8192;
+
+struct TrLds {
+    uint32_t key[TR_HT];
+    uint32_t cnt[TR_HT];
+    uint32_t off[TR_HT];
+};
+
+__device__ __forceinline__ uint32_t tr_slot(TrLds &L, uint32_t v)
 {
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[col[e]], 1u);
+    uint32_t h = (v * 0x9E3779B1u) >> (32 - 13);
+    for (;;) {
+        uint32_t k = L.key[h];
+        if (k == v) return h;
+        if (k == IM_EMPTY) {
+            uint32_t old = atomicCAS(&L.key[h], IM_EMPTY, v);
+            if (old == IM_EMPTY || old == v) return h;
+        }
+        h = (h + 1) & (TR_HT - 1);
+    }
+}
+
+// pass 1: in-degree histogram. pass 2 (scatter): positions.
+template <bool SCATTER>
+__global__ __launch_bounds__(TR_NT) void k_transpose(const uint32_t *row32, const uint32_t *col,
+                                                     uint32_t n, uint64_t m, uint32_t *cnt,
+                                                     const uint32_t *in_row, uint32_t *in_col,
+                                                     uint32_t *in2out)
+{
+    __shared__ TrLds L;
+    const int tid = threadIdx.x;
+    const uint64_t e0 = (uint64_t)blockIdx.x * TR_ARCS;
+    const uint64_t e1 = e0 + TR_ARCS < m ? e0 + TR_ARCS : m;
+    for (int i = tid; i < TR_HT; i += TR_NT) { L.key[i] = IM_EMPTY; L.cnt[i] = 0; }
+    __syncthreads();
+    for (uint64_t e = e0 + tid; e < e1; e += TR_NT) atomicAdd(&L.cnt[tr_slot(L, col[e])], 1u);
+    __syncthreads();
+    for (int i = tid; i < TR_HT; i += TR_NT) {
+        uint32_t v = L.key[i];
+        if (v == IM_EMPTY) continue;
+        uint32_t base = atomicAdd(&cnt[v], L.cnt[i]);
+        if (SCATTER) { L.off[i] = in_row[v] + base; L.cnt[i] = 0; }
+    }
+    if (!SCATTER) return;
+    __syncthreads();
+    for (uint64_t e = e0 + tid; e < e1; e += TR_NT) {
+        uint32_t v = col[e];
+        uint32_t h = tr_slot(L, v);
+        uint32_t pos = L.off[h] + atomicAdd(&L.cnt[h], 1u);
+        uint32_t lo = 0, hi = n;  // tail: largest u with row32[u] <= e
+        while (hi - lo > 1) {
+            uint32_t mid = lo + (hi - lo) / 2;
+            if (row32[mid] <= (uint32_t)e) lo = mid; else hi = mid;
+        }
+        in_col[pos] = lo;
+        in2out[pos] = (uint32_t)e;
+    }
 }
 
 constexpr int SCAN_NT = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_NT * SCAN_IPT;
@@ -171,31 +231,6 @@ __global__ void k_scan_add(uint32_t *out, uint64_t len, const uint32_t *sums)
         out[i] += sums[i / SCAN_TILE];
 }
 
-// tail of arc e: largest u with row32[u] <= e
-__device__ __forceinline__ uint32_t arc_tail(const uint32_t *row32, uint32_t n, uint32_t e)
-{
-    uint32_t lo = 0, hi = n;  // row32[lo] <= e < row32[hi] (row32[n] = m > e)
-    while (hi - lo > 1) {
-        uint32_t mid = lo + (hi - lo) / 2;
-        if (row32[mid] <= e) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__global__ void k_scatter(const uint32_t *row32, const uint32_t *col, uint32_t n, uint64_t m,
-                          const uint32_t *in_row, uint32_t *cursor, uint32_t *in_col,
-                          uint32_t *in2out)
-{
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t u = arc_tail(row32, n, (uint32_t)e);
-        uint32_t v = col[e];
-        uint32_t pos = in_row[v] + atomicAdd(&cursor[v], 1u);
-        in_col[pos] = u;
-        in2out[pos] = (uint32_t)e;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // A2: snapshot masks
 // ---------------------------------------------------------------------------
@@ -236,6 +271,121 @@ __global__ __launch_bounds__(256) void k_mask_gather(const uint32_t *in2out, uin
 }
 
 // ---------------------------------------------------------------------------
+// Hub lists: per-snapshot live adjacency of heavy nodes (see HubLists)
+// ---------------------------------------------------------------------------
+constexpr int HB_NT = 256;
+
+__global__ void k_hub_mark(const uint32_t *row, uint32_t n, uint32_t hub_deg, uint32_t *slot,
+                           uint32_t *list, uint32_t *nhub)
+{
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        uint32_t d = row[x + 1] - row[x];
+        uint32_t h = IM_EMPTY;
+        if (hub_deg && d >= hub_deg) {
+            h = atomicAdd(nhub, 1u);
+            list[h] = x;
+        }
+        slot[x] = h;
+    }
+}
+
+// Count the live (arc, snapshot) pairs of hub h in word w per bit and reserve
+// their range of adj. One block per (hub, word). A hub whose lists would be
+// denser than a quarter of its masks, or would not fit, is expanded through
+// the masks instead (its slot is cleared).
+__global__ __launch_bounds__(HB_NT) void k_hub_count(const uint32_t *row, const uint64_t *mask,
+                                                     uint64_t m, uint32_t W, const uint32_t *list,
+                                                     const uint32_t *nhub, uint32_t *slot,
+                                                     uint32_t *hcnt, unsigned long long *hbase,
+                                                     unsigned long long *alloc, uint64_t cap)
+{
+    constexpr int U = 8;
+    __shared__ uint32_t cnt[64];
+    const uint32_t h = blockIdx.x, w = blockIdx.y;
+    if (h >= *nhub) return;
+    const int tid = threadIdx.x;
+    const uint32_t x = list[h], e0 = row[x], e1 = row[x + 1];
+    const uint64_t *mw = mask + (uint64_t)w * m;
+    if (tid < 64) cnt[tid] = 0;
+    __syncthreads();
+    for (uint32_t e = e0 + tid; e < e1; e += HB_NT * U) {
+        uint64_t b[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            uint32_t ee = e + (uint32_t)u * HB_NT;
+            b[u] = ee < e1 ? mw[ee] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            while (b[u]) {
+                atomicAdd(&cnt[__ffsll((unsigned long long)b[u]) - 1], 1u);
+                b[u] &= b[u] - 1;
+            }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        uint32_t c = cnt[tid];
+        hcnt[((uint64_t)h * W + w) * 64 + tid] = c;
+        uint32_t incl = wave_incl_scan(c);
+        if (tid == 63) {
+            bool use = (uint64_t)incl * 4 <= 64ull * (e1 - e0);
+            unsigned long long base = 0;
+            if (use) {
+                base = atomicAdd(alloc, (unsigned long long)incl);
+                use = base + incl <= cap;
+            }
+            hbase[(uint64_t)h * W + w] = base;
+            if (!use) slot[x] = IM_EMPTY;
+        }
+    }
+}
+
+__global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const uint32_t *col,
+                                                    const uint64_t *mask, uint64_t m, uint32_t W,
+                                                    const uint32_t *list, const uint32_t *nhub,
+                                                    const uint32_t *slot, const uint32_t *hcnt,
+                                                    const unsigned long long *hbase, uint32_t *hoff,
+                                                    uint32_t *hadj)
+{
+    constexpr int U = 8;
+    __shared__ uint32_t cur[64];
+    const uint32_t h = blockIdx.x, w = blockIdx.y;
+    if (h >= *nhub) return;
+    const uint32_t x = list[h];
+    if (slot[x] == IM_EMPTY) return;
+    const int tid = threadIdx.x;
+    const uint32_t e0 = row[x], e1 = row[x + 1];
+    const uint64_t *mw = mask + (uint64_t)w * m;
+    if (tid < 64) {
+        uint32_t c = hcnt[((uint64_t)h * W + w) * 64 + tid];
+        uint32_t incl = wave_incl_scan(c);
+        uint32_t o = (uint32_t)hbase[(uint64_t)h * W + w] + incl - c;
+        cur[tid] = o;
+        uint32_t *dst = hoff + ((uint64_t)h * W + w) * 65;
+        dst[tid] = o;
+        if (tid == 63) dst[64] = o + c;
+    }
+    __syncthreads();
+    for (uint32_t e = e0 + tid; e < e1; e += HB_NT * U) {
+        uint64_t b[U];
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            uint32_t ee = e + (uint32_t)u * HB_NT;
+            b[u] = ee < e1 ? mw[ee] : 0ull;
+            v[u] = ee < e1 ? col[ee] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            while (b[u]) {
+                uint32_t pos = atomicAdd(&cur[__ffsll((unsigned long long)b[u]) - 1], 1u);
+                hadj[pos] = v[u];
+                b[u] &= b[u] - 1;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // A4: argmax of (gain, lowest id) over unselected nodes
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint8_t *sel,
@@ -258,36 +408,221 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint
 }
 
 // ---------------------------------------------------------------------------
-// A5: forward search from the chosen seed, pruned at covered nodes
+// A5: forward search from the chosen seed, pruned at covered nodes.
+// One cooperative grid runs the searches of all W words together, level by
+// level: the frontier holds (word, node) entries, every workgroup expands
+// tiles of it, and grid-wide barriers separate the levels.
+// N[w][x] (newly) collects the newly covered bits; afterwards covered |= N and
+// tnodes[w] lists the nodes with N[w][x] != 0 (the reverse tasks).
 // ---------------------------------------------------------------------------
 struct FwdArgs {
     const uint32_t *row, *col;
     const uint64_t *mask;
+    HubLists hub;
     uint64_t m;
     uint32_t n, R, W;
     uint64_t *covered, *newly, *pend, *fdel;
-    uint32_t *qa, *qb, *tnodes, *tcounts;
+    uint64_t *fq0, *fq1;        // frontier entries (word << 32 | node), capacity W*n
+    uint32_t *bq0, *bq1;        // per-word frontier queues of the one-workgroup kernel [W][n]
+    uint64_t coop_gain;         // rounds whose seed gain reaches this use the cooperative kernel
+    uint32_t *cnt;              // [3] frontier counts (ring), [W] visit counts; zero on entry
+    uint32_t *tnodes, *tcounts;
     const unsigned long long *key;
+    uint32_t t;
     uint32_t *seeds_out;
     uint64_t *gains_out;
     uint8_t *sel;
     unsigned long long *stats;
 };
 
-constexpr int FWD_NT = 1024;
+constexpr int FWD_NT = 256, FWD_U = 8;
 
-__global__ __launch_bounds__(FWD_NT) void k_forward(FwdArgs a, uint32_t t)
+struct FwdLds {
+    uint32_t scan[FWD_NT];
+    uint32_t rs[FWD_NT];
+    uint32_t wd[FWD_NT];
+    uint64_t del[FWD_NT];
+    uint32_t wsum[FWD_NT / 64 + 1];
+    unsigned long long red[FWD_NT / 64];
+    HubBatch<FWD_NT, 16> H;
+};
+
+__device__ __forceinline__ uint32_t coherent_load(uint32_t *p) { return atomicAdd(p, 0u); }
+
+// relax (w, v) with `bits` (may be 0); every lane must call it
+__device__ __forceinline__ void fwd_relax(const FwdArgs &a, uint32_t w, uint32_t v, uint64_t bits,
+                                          uint64_t *nxt, uint32_t *ncnt)
 {
-    __shared__ BlockLds<FWD_NT> L;
+    const uint64_t off = (uint64_t)w * a.n;
+    bool first = false, push = false;
+    if (bits) bits &= ~a.covered[off + v];
+    if (bits) {
+        uint64_t old = atomicOr((unsigned long long *)&a.newly[off + v], (unsigned long long)bits);
+        uint64_t nb = bits & ~old;
+        if (nb) {
+            first = old == 0;
+            uint64_t op = atomicOr((unsigned long long *)&a.pend[off + v], (unsigned long long)nb);
+            push = op == 0;
+        }
+    }
+    // a node enters the visit list of its word once; the frontier once per level
+    for (uint32_t ww = 0; ww < a.W; ww++) {
+        uint32_t p = wave_append(first && w == ww, a.cnt + 3 + ww);
+        if (first && w == ww) a.tnodes[off + p] = v;
+    }
+    uint32_t q = wave_append(push, ncnt);
+    if (push) nxt[q] = ((uint64_t)w << 32) | v;
+}
+
+__global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
+{
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    __shared__ FwdLds L;
     const int tid = threadIdx.x;
-    const unsigned long long key = a.key[t];
-    if (key == 0) return;  // no unselected node (cannot happen for k <= n)
+    const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
+    const uint64_t gsize = (uint64_t)gridDim.x * FWD_NT;
+    const unsigned long long key = a.key[a.t];
+    if (key == 0) return;  // no unselected node (cannot happen for k <= n); uniform
+    if ((key >> 32) < a.coop_gain) return;  // a small round: k_forward_block runs it
+    const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+    if (blockIdx.x == 0) {
+        if (tid == 0) {
+            a.seeds_out[a.t] = v;
+            a.gains_out[a.t] = key >> 32;
+            a.sel[v] = 1;
+            L.H.n = 0;
+            uint32_t nf = 0;
+            for (uint32_t w = 0; w < a.W; w++) {
+                const uint64_t off = (uint64_t)w * a.n;
+                uint64_t start = im_valid_bits(a.R, w) & ~a.covered[off + v];
+                if (!start) continue;
+                a.newly[off + v] = start;
+                a.pend[off + v] = start;
+                a.fq0[nf] = ((uint64_t)w << 32) | v;
+                nf++;
+                a.tnodes[off] = v;
+                a.cnt[3 + w] = 1;
+            }
+            a.cnt[0] = nf;
+        }
+    } else if (tid == 0) {
+        L.H.n = 0;
+    }
+    grid.sync();
+    uint64_t arcs = 0;
+    for (uint32_t lev = 0;; lev++) {
+        const uint32_t nf = coherent_load(&a.cnt[lev % 3]);
+        if (nf == 0) break;
+        const uint64_t *cur = (lev & 1) ? a.fq1 : a.fq0;
+        uint64_t *nxt = (lev & 1) ? a.fq0 : a.fq1;
+        uint32_t *ncnt = &a.cnt[(lev + 1) % 3];
+        // the ring slot of level lev-1 was last read before the previous barrier
+        if (gtid == 0) a.cnt[(lev + 2) % 3] = 0;
+        for (uint32_t tile = blockIdx.x * FWD_NT; tile < nf; tile += gridDim.x * FWD_NT) {
+            const uint32_t i = tile + tid;
+            uint32_t deg = 0, rs = 0, w = 0;
+            uint64_t d = 0;
+            if (i < nf) {
+                uint64_t e = cur[i];
+                w = (uint32_t)(e >> 32);
+                uint32_t x = (uint32_t)e;
+                uint32_t hs = a.hub.slot[x];
+                rs = a.row[x];
+                deg = a.row[x + 1] - rs;
+                // bits gained since x was last expanded; later ones re-queue x
+                d = atomicExch((unsigned long long *)&a.pend[(uint64_t)w * a.n + x], 0ull);
+                if (hs != IM_EMPTY) {
+                    hub_push(L.H, hs, w, d);
+                    deg = 0; d = 0;
+                }
+            }
+            uint32_t total;
+            uint32_t ex = block_excl_scan<FWD_NT>(deg, L.wsum, &total);
+            L.scan[tid] = ex; L.rs[tid] = rs; L.del[tid] = d; L.wd[tid] = w;
+            __syncthreads();
+            const uint32_t nhub = L.H.n;
+            arcs += total;
+            for (uint32_t j0 = 0; j0 < total; j0 += FWD_NT * FWD_U) {
+                uint32_t kk[FWD_U], ee[FWD_U], vv[FWD_U];
+                uint64_t bb[FWD_U];
+#pragma unroll
+                for (int u = 0; u < FWD_U; u++) {
+                    uint32_t j = j0 + (uint32_t)tid + (uint32_t)u * FWD_NT;
+                    kk[u] = 0xFFFFFFFFu; ee[u] = 0; bb[u] = 0; vv[u] = 0;
+                    if (j < total) {
+                        int k = upper_index<FWD_NT>(L.scan, j);
+                        kk[u] = (uint32_t)k;
+                        ee[u] = L.rs[k] + (j - L.scan[k]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < FWD_U; u++)
+                    if (kk[u] != 0xFFFFFFFFu) {
+                        bb[u] = a.mask[(uint64_t)L.wd[kk[u]] * a.m + ee[u]];
+                        vv[u] = a.col[ee[u]];
+                    }
+#pragma unroll
+                for (int u = 0; u < FWD_U; u++) {
+                    uint32_t ww = kk[u] != 0xFFFFFFFFu ? L.wd[kk[u]] : 0u;
+                    uint64_t bits = kk[u] != 0xFFFFFFFFu ? (bb[u] & L.del[kk[u]]) : 0ull;
+                    fwd_relax(a, ww, vv[u], bits, nxt, ncnt);
+                }
+            }
+            __syncthreads();
+            if (nhub) {
+                auto word_of = [&](uint32_t own) { return own; };
+                auto relax = [&](uint32_t own, uint32_t hv, uint64_t bits) {
+                    fwd_relax(a, own, hv, bits, nxt, ncnt);
+                };
+                expand_hubs<FWD_NT, 16, FWD_U>(L.H, nhub, a.hub, a.W, word_of, relax, arcs);
+            }
+        }
+        grid.sync();
+    }
+    // covered |= newly for every visited node; statistics
+    uint64_t relax = 0, trav = 0;
+    for (uint32_t w = 0; w < a.W; w++) {
+        const uint64_t off = (uint64_t)w * a.n;
+        const uint32_t nv = coherent_load(&a.cnt[3 + w]);
+        for (uint64_t i = gtid; i < nv; i += gsize) {
+            uint32_t x = a.tnodes[off + i];
+            uint64_t b = a.newly[off + x];
+            a.covered[off + x] |= b;
+            uint32_t dg = a.row[x + 1] - a.row[x];
+            relax += dg;
+            trav += (uint64_t)__popcll(b) * dg;
+        }
+        if (gtid == 0) {
+            a.tcounts[w] = nv;
+            atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)nv);
+        }
+    }
+    relax = group_sum<FWD_NT>(relax, L.red);
+    trav = group_sum<FWD_NT>(trav, L.red);
+    if (tid == 0) {
+        atomicAdd(&a.stats[ST_RELAX_FWD], (unsigned long long)relax);
+        atomicAdd(&a.stats[ST_TRAV_FWD], (unsigned long long)trav);
+    }
+}
+
+// Rounds below the gain threshold: one workgroup per word runs its search
+// alone (no grid-wide barriers; per-level latency is what limits small searches).
+constexpr int FWB_NT = 1024;
+
+__global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
+{
+    __shared__ BlockLds<FWB_NT> L;
+    const int tid = threadIdx.x;
+    const unsigned long long key = a.key[a.t];
+    if (key == 0) return;
+    if ((key >> 32) >= a.coop_gain) return;  // the cooperative kernel runs this round
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
     const uint32_t w = blockIdx.x;
     const uint64_t off = (uint64_t)w * a.n;
     if (w == 0 && tid == 0) {
-        a.seeds_out[t] = v;
-        a.gains_out[t] = key >> 32;
+        a.seeds_out[a.t] = v;
+        a.gains_out[a.t] = key >> 32;
         a.sel[v] = 1;
     }
     const uint64_t start = im_valid_bits(a.R, w) & ~a.covered[off + v];
@@ -296,12 +631,12 @@ __global__ __launch_bounds__(FWD_NT) void k_forward(FwdArgs a, uint32_t t)
         return;
     }
     uint64_t arcs = 0;
-    block_bfs_run<FWD_NT, true>(L, v, start, a.row, a.col, a.mask + (uint64_t)w * a.m,
-                                a.covered + off, a.newly + off, a.pend + off, a.fdel + off,
-                                a.qa + off, a.qb + off, a.tnodes + off, arcs);
+    block_bfs_run<FWB_NT, 8, true>(L, v, start, a.row, a.col, a.mask + (uint64_t)w * a.m, a.hub,
+                                   a.W, w, a.covered + off, a.newly + off, a.pend + off, nullptr,
+                                   a.bq0 + off, a.bq1 + off, a.tnodes + off, arcs);
     const uint32_t nvis = L.nvis;
     uint64_t relax = 0, trav = 0;
-    for (uint32_t i = tid; i < nvis; i += FWD_NT) {
+    for (uint32_t i = tid; i < nvis; i += FWB_NT) {
         uint32_t x = a.tnodes[off + i];
         uint64_t b = a.newly[off + x];
         a.covered[off + x] |= b;
@@ -309,15 +644,13 @@ __global__ __launch_bounds__(FWD_NT) void k_forward(FwdArgs a, uint32_t t)
         relax += dg;
         trav += (uint64_t)__popcll(b) * dg;
     }
-    relax = wave_sum_u64(relax);
-    trav = wave_sum_u64(trav);
-    if ((tid & 63) == 0) {
-        atomicAdd(&a.stats[ST_RELAX_FWD], (unsigned long long)relax);
-        atomicAdd(&a.stats[ST_TRAV_FWD], (unsigned long long)trav);
-    }
+    relax = group_sum<FWB_NT>(relax, L.red);
+    trav = group_sum<FWB_NT>(trav, L.red);
     if (tid == 0) {
         a.tcounts[w] = nvis;
         atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)nvis);
+        atomicAdd(&a.stats[ST_RELAX_FWD], (unsigned long long)relax);
+        atomicAdd(&a.stats[ST_TRAV_FWD], (unsigned long long)trav);
     }
 }
 
@@ -345,9 +678,17 @@ __global__ void k_copy_u32(const uint32_t *src, uint32_t *dst, uint64_t cnt)
 // ---------------------------------------------------------------------------
 // wavefront engine: T tasks per wavefront, CS table entries per task,
 // LIM entries before hand-over, DMAX largest degree expanded in LDS
-constexpr int WV_T = 8, WV_CS = 32, WV_LIM = 24, WV_DMAX = 1024;
-constexpr int BLK_NT = 256;
-constexpr int PH_CTRS = 4;  // per-phase counters: grab, ovf_n, bgrab, spare
+// tier 0: 64 lanes, T0_T tasks of up to T0_LIM nodes, degrees <= T0_DMAX
+constexpr int T0_T = 8, T0_CS = 32, T0_LIM = 24, T0_U = 8;
+constexpr uint32_t T0_DMAX = 1024;
+// tier 1: 256 lanes, T1_T tasks of up to T1_LIM nodes, any degree
+constexpr int T1_NT = 256, T1_T = 1, T1_CS = 1024, T1_LIM = 768, T1_U = 8;
+// tier 2: dense global arrays
+constexpr int T2_NT = 256, T2_U = 8;
+// per-phase device counters: grab0, n1, grab1, n2, grab2
+constexpr int PH_CTRS = 8;
+// per-round forward counters: 3 frontier counts + one visit count per word
+constexpr int FWD_CTRS = 3 + 64;
 
 // ---------------------------------------------------------------------------
 // workspace
@@ -365,10 +706,22 @@ struct im_workspace {
     uint32_t *gain = nullptr;
     uint8_t *sel = nullptr;
     uint64_t *covered = nullptr, *newly = nullptr, *fpend = nullptr, *ffdel = nullptr;
-    uint32_t *fqa = nullptr, *fqb = nullptr, *tnodes = nullptr, *tcounts = nullptr;
+    uint64_t *fqa = nullptr, *fqb = nullptr;
+    uint32_t *bqa = nullptr, *bqb = nullptr;
+    uint64_t coop_gain = ~0ull;  // cooperative forward search off by default
+    uint32_t *tnodes = nullptr, *tcounts = nullptr;
+    uint32_t *fctr = nullptr;  // [k][FWD_CTRS] forward-search counters
+    unsigned fwd_grid = 0;
     unsigned long long *keys = nullptr;
-    uint32_t *ovf_q = nullptr;
+    uint32_t *ovf_q = nullptr, *ovf_q2 = nullptr;
     uint32_t *ctrs = nullptr;
+    // hub lists per direction (0: forward arcs, 1: reverse arcs)
+    uint32_t hub_deg = 1024;
+    uint64_t cap_hub = 0, cap_hadj = 0;
+    uint32_t *hslot[2] = {}, *hlist[2] = {}, *hcnt[2] = {}, *hoff[2] = {}, *hadj[2] = {};
+    unsigned long long *hbase[2] = {};
+    uint32_t *hnum = nullptr;            // [2] hub counts
+    unsigned long long *halloc = nullptr;  // [2] allocation counters
     // block engine slots
     uint64_t *b_reach = nullptr, *b_pend = nullptr, *b_fdel = nullptr;
     uint32_t *b_qa = nullptr, *b_qb = nullptr, *b_vis = nullptr;
@@ -378,6 +731,39 @@ struct im_workspace {
     uint32_t *host_err = nullptr;
     unsigned long long *host_stats = nullptr;
     hipStream_t last_stream = nullptr;
+    // phase timers
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev[IM_PH_COUNT];
+    size_t ev_used[IM_PH_COUNT] = {};
+    int open_phase = -1;
+};
+
+// bracket a phase's launches with events (only for phases enabled in prof_mask)
+struct PhaseTimer {
+    im_workspace *ws;
+    int ph;
+    hipStream_t s;
+    bool on;
+    PhaseTimer(im_workspace *w, int p, hipStream_t st) : ws(w), ph(p), s(st)
+    {
+        on = (ws->prof_mask >> ph) & 1u;
+        if (on) record();
+    }
+    ~PhaseTimer()
+    {
+        if (on) record();
+    }
+    void record()
+    {
+        std::vector<hipEvent_t> &v = ws->ev[ph];
+        size_t &u = ws->ev_used[ph];
+        if (u == v.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+            v.push_back(e);
+        }
+        (void)hipEventRecord(v[u++], s);
+    }
 };
 
 template <typename Tv>
@@ -410,6 +796,12 @@ extern "C" int im_workspace_create(im_workspace **out)
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, ws->device));
     ws->num_cu = prop.multiProcessorCount;
+    {
+        int b = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_forward_coop, FWD_NT, 0));
+        if (b < 1) b = 1;
+        ws->fwd_grid = (unsigned)ws->num_cu;  // one workgroup per CU: cheaper grid barriers
+    }
     int rc;
     if ((rc = dalloc(&ws->stats, ST_COUNT))) { delete ws; return rc; }
     if ((rc = dalloc(&ws->err, 1))) { delete ws; return rc; }
@@ -428,13 +820,20 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->row32); dfree(ws->in_row); dfree(ws->in_col); dfree(ws->in2out);
     dfree(ws->cnt); dfree(ws->scan_sums); dfree(ws->mask_out); dfree(ws->mask_in);
     dfree(ws->gain); dfree(ws->sel); dfree(ws->covered); dfree(ws->newly);
-    dfree(ws->fpend); dfree(ws->ffdel); dfree(ws->fqa); dfree(ws->fqb);
-    dfree(ws->tnodes); dfree(ws->tcounts); dfree(ws->keys); dfree(ws->ovf_q); dfree(ws->ctrs);
+    dfree(ws->fpend); dfree(ws->ffdel); dfree(ws->fqa); dfree(ws->fqb); dfree(ws->bqa); dfree(ws->bqb); dfree(ws->fctr);
+    dfree(ws->tnodes); dfree(ws->tcounts); dfree(ws->keys); dfree(ws->ovf_q); dfree(ws->ovf_q2); dfree(ws->ctrs);
     dfree(ws->b_reach); dfree(ws->b_pend); dfree(ws->b_fdel);
     dfree(ws->b_qa); dfree(ws->b_qb); dfree(ws->b_vis);
+    for (int d = 0; d < 2; d++) {
+        dfree(ws->hslot[d]); dfree(ws->hlist[d]); dfree(ws->hcnt[d]); dfree(ws->hoff[d]);
+        dfree(ws->hadj[d]); dfree(ws->hbase[d]);
+    }
+    dfree(ws->hnum); dfree(ws->halloc);
     dfree(ws->stats); dfree(ws->err);
     if (ws->host_err) (void)hipHostFree(ws->host_err);
     if (ws->host_stats) (void)hipHostFree(ws->host_stats);
+    for (int p = 0; p < IM_PH_COUNT; p++)
+        for (hipEvent_t e : ws->ev[p]) (void)hipEventDestroy(e);
     delete ws;
     return IM_OK;
 }
@@ -465,9 +864,12 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
             (rc = dalloc(&ws->covered, nW)) || (rc = dalloc(&ws->newly, nW)) ||
             (rc = dalloc(&ws->fpend, nW)) || (rc = dalloc(&ws->ffdel, nW)) ||
             (rc = dalloc(&ws->fqa, nW)) || (rc = dalloc(&ws->fqb, nW)) ||
+            (rc = dalloc(&ws->bqa, nW)) || (rc = dalloc(&ws->bqb, nW)) ||
             (rc = dalloc(&ws->tnodes, nW)) || (rc = dalloc(&ws->tcounts, 64)) ||
-            (rc = dalloc(&ws->ovf_q, nW)))
+            (rc = dalloc(&ws->ovf_q, nW)) || (rc = dalloc(&ws->ovf_q2, nW)))
             return rc;
+        for (int d = 0; d < 2; d++)
+            if ((rc = dalloc(&ws->hslot[d], cn))) return rc;
         HIPCHK(hipMemset(ws->newly, 0, nW * sizeof(uint64_t)));
         HIPCHK(hipMemset(ws->fpend, 0, nW * sizeof(uint64_t)));
         uint32_t slots = slots_for(cn);
@@ -485,12 +887,29 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
         if ((rc = dalloc(&ws->in_col, cm)) || (rc = dalloc(&ws->in2out, cm)) ||
             (rc = dalloc(&ws->mask_out, cm * cW)) || (rc = dalloc(&ws->mask_in, cm * cW)))
             return rc;
+        uint64_t cap = std::min<uint64_t>(2ull * cm * cW, 0x7FFFFFFFull);
+        for (int d = 0; d < 2; d++)
+            if ((rc = dalloc(&ws->hadj[d], cap))) return rc;
+        if ((rc = dalloc(&ws->hnum, 2)) || (rc = dalloc(&ws->halloc, 2))) return rc;
+        ws->cap_hadj = cap;
+        ws->cap_hub = 0;
         ws->cap_m = cm;
     }
     ws->cap_W = cW;
+    // hub tables: at most m / hub_deg hubs
+    const uint64_t maxh = cm / std::max<uint32_t>(ws->hub_deg, 16u) + 1;
+    if (grow_m || grow_n || maxh > ws->cap_hub) {
+        const uint64_t ch = std::max<uint64_t>(maxh, ws->cap_hub);
+        for (int d = 0; d < 2; d++)
+            if ((rc = dalloc(&ws->hlist[d], ch)) || (rc = dalloc(&ws->hbase[d], ch * cW)) ||
+                (rc = dalloc(&ws->hcnt[d], ch * cW * 64)) || (rc = dalloc(&ws->hoff[d], ch * cW * 65)))
+                return rc;
+        ws->cap_hub = ch;
+    }
     if (k + 1 > ws->cap_k) {
         uint32_t ck = k + 1;
-        if ((rc = dalloc(&ws->keys, ck)) || (rc = dalloc(&ws->ctrs, (uint64_t)(ck + 1) * PH_CTRS)))
+        if ((rc = dalloc(&ws->keys, ck)) || (rc = dalloc(&ws->ctrs, (uint64_t)(ck + 1) * PH_CTRS)) ||
+            (rc = dalloc(&ws->fctr, (uint64_t)ck * FWD_CTRS)))
             return rc;
         ws->cap_k = ck;
     }
@@ -514,6 +933,7 @@ static int check_args(const im_graph *g, uint32_t R)
 
 static int validate(const im_graph *g, im_workspace *ws, hipStream_t s, uint32_t *row32)
 {
+    PhaseTimer pt(ws, IM_PH_VALIDATE, s);
     HIPCHK(hipMemsetAsync(ws->err, 0, sizeof(uint32_t), s));
     uint64_t lim = std::max<uint64_t>((uint64_t)g->n + 1, g->m);
     k_validate<<<grid_for(lim, 256), 256, 0, s>>>(g->row_ptr, g->col, g->prob, g->n, g->m,
@@ -544,12 +964,17 @@ static void build_reverse(const im_graph *g, im_workspace *ws, hipStream_t s)
 {
     uint32_t n = g->n;
     uint64_t m = g->m;
+    PhaseTimer pt(ws, IM_PH_TRANSPOSE, s);
+    const unsigned tblocks = (unsigned)((m + TR_ARCS - 1) / TR_ARCS);
     fill<uint32_t>(ws->cnt, (uint64_t)n + 1, 0u, s);
-    if (m) k_hist<<<grid_for(m, 256), 256, 0, s>>>(g->col, m, ws->cnt);
+    if (m)
+        k_transpose<false><<<tblocks, TR_NT, 0, s>>>(ws->row32, g->col, n, m, ws->cnt, nullptr,
+                                                     nullptr, nullptr);
     exclusive_scan(ws->cnt, ws->in_row, (uint64_t)n + 1, ws->scan_sums, s);
     fill<uint32_t>(ws->cnt, (uint64_t)n + 1, 0u, s);
-    if (m) k_scatter<<<grid_for(m, 256), 256, 0, s>>>(ws->row32, g->col, n, m, ws->in_row, ws->cnt,
-                                                      ws->in_col, ws->in2out);
+    if (m)
+        k_transpose<true><<<tblocks, TR_NT, 0, s>>>(ws->row32, g->col, n, m, ws->cnt, ws->in_row,
+                                                    ws->in_col, ws->in2out);
 }
 
 // A2: masks for both directions
@@ -560,27 +985,94 @@ static void build_masks(const im_graph *g, uint32_t R, uint64_t seed, im_workspa
     uint64_t m = g->m;
     if (m == 0) return;
     dim3 grid((unsigned)((m + 255) / 256), W);
-    k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, mask_out);
-    if (reverse) k_mask_gather<<<grid, 256, 0, s>>>(ws->in2out, m, mask_out, ws->mask_in);
+    {
+        PhaseTimer pt(ws, IM_PH_MASK_GEN, s);
+        k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, mask_out);
+    }
+    if (reverse) {
+        PhaseTimer pt(ws, IM_PH_MASK_GATHER, s);
+        k_mask_gather<<<grid, 256, 0, s>>>(ws->in2out, m, mask_out, ws->mask_in);
+    }
+}
+
+// A2b: hub lists for one direction (after that direction's masks exist)
+static void build_hubs(int d, const uint32_t *row, const uint32_t *col, const uint64_t *mask,
+                       uint32_t n, uint64_t m, uint32_t W, im_workspace *ws, hipStream_t s)
+{
+    if (n == 0) return;
+    fill<uint32_t>(ws->hnum + d, 1, 0u, s);
+    fill<unsigned long long>(ws->halloc + d, 1, 0ull, s);
+    k_hub_mark<<<grid_for(n, 256, 4096), 256, 0, s>>>(row, n, ws->hub_deg, ws->hslot[d],
+                                                       ws->hlist[d], ws->hnum + d);
+    if (m == 0 || ws->hub_deg == 0) return;
+    const unsigned maxh = (unsigned)std::min<uint64_t>(m / ws->hub_deg + 1, ws->cap_hub);
+    dim3 grid(maxh, W);
+    k_hub_count<<<grid, HB_NT, 0, s>>>(row, mask, m, W, ws->hlist[d], ws->hnum + d, ws->hslot[d],
+                                       ws->hcnt[d], ws->hbase[d], ws->halloc + d, ws->cap_hadj);
+    k_hub_fill<<<grid, HB_NT, 0, s>>>(row, col, mask, m, W, ws->hlist[d], ws->hnum + d,
+                                      ws->hslot[d], ws->hcnt[d], ws->hbase[d], ws->hoff[d],
+                                      ws->hadj[d]);
+}
+
+static HubLists hub_lists(im_workspace *ws, int d)
+{
+    HubLists h;
+    h.slot = ws->hslot[d];
+    h.off = ws->hoff[d];
+    h.adj = ws->hadj[d];
+    return h;
 }
 
 static BfsArgs bfs_args(im_workspace *ws, const uint32_t *row, const uint32_t *col,
-                        const uint64_t *mask, uint64_t m, uint32_t n, uint32_t R, uint32_t W,
-                        uint32_t *ctr)
+                        const uint64_t *mask, uint64_t m, uint32_t n, uint32_t R, uint32_t W)
 {
     BfsArgs a;
     memset(&a, 0, sizeof(a));
     a.row = row; a.col = col; a.mask = mask; a.m = m; a.n = n; a.R = R; a.W = W;
     a.gain = ws->gain;
-    a.grab = ctr + 0; a.ovf_n = ctr + 1; a.bgrab = ctr + 2;
-    a.ovf_q = ws->ovf_q;
     a.b_reach = ws->b_reach; a.b_pend = ws->b_pend; a.b_fdel = ws->b_fdel;
     a.b_qa = ws->b_qa; a.b_qb = ws->b_qb; a.b_vis = ws->b_vis;
     a.stats = ws->stats;
     return a;
 }
 
-static unsigned wave_grid(im_workspace *ws) { return (unsigned)ws->num_cu * 12u; }
+// resident blocks per CU of a kernel (at least 1)
+template <typename K>
+static unsigned per_cu(K kernel, int nt)
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, nt, 0) != hipSuccess || b < 1) b = 1;
+    return (unsigned)b;
+}
+
+// Run every task of `a` through the three engine tiers. ctr: this phase's
+// zeroed counters. ph0: phase-timer id of tier 0 (ph0+1, ph0+2: tiers 1, 2).
+template <int MODE, bool PRUNE>
+static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipStream_t s)
+{
+    a.in_q = nullptr; a.in_n = nullptr;
+    a.out_q = ws->ovf_q; a.out_n = ctr + 1; a.grab = ctr + 0; a.tier = 0;
+    {
+        PhaseTimer pt(ws, ph0, s);
+        auto k0 = k_lds_bfs<MODE, 64, T0_T, T0_CS, T0_LIM, T0_DMAX, T0_U, PRUNE>;
+        static const unsigned g0 = per_cu(k0, 64);
+        k0<<<(unsigned)ws->num_cu * g0, 64, 0, s>>>(a);
+    }
+    a.in_q = ws->ovf_q; a.in_n = ctr + 1;
+    a.out_q = ws->ovf_q2; a.out_n = ctr + 3; a.grab = ctr + 2; a.tier = 1;
+    {
+        PhaseTimer pt(ws, ph0 + 1, s);
+        auto k1 = k_lds_bfs<MODE, T1_NT, T1_T, T1_CS, T1_LIM, 0xFFFFFFFFu, T1_U, PRUNE>;
+        static const unsigned g1 = per_cu(k1, T1_NT);
+        k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
+    }
+    a.in_q = ws->ovf_q2; a.in_n = ctr + 3;
+    a.out_q = nullptr; a.out_n = nullptr; a.grab = ctr + 4; a.tier = 2;
+    {
+        PhaseTimer pt(ws, ph0 + 2, s);
+        k_block_bfs<MODE, T2_NT, T2_U, PRUNE><<<ws->slots, T2_NT, 0, s>>>(a);
+    }
+}
 
 // A3: initial gains (gain must be zero on entry)
 static void initial_gains(const im_graph *g, uint32_t R, im_workspace *ws, uint32_t *ctr,
@@ -588,37 +1080,55 @@ static void initial_gains(const im_graph *g, uint32_t R, im_workspace *ws, uint3
 {
     uint32_t n = g->n, W = (R + 63) / 64;
     if (n == 0) return;
-    BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W, ctr);
+    BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W);
     a.ntasks = n * W;
-    a.st_trav = ST_TRAV_INIT; a.st_relax = ST_RELAX_INIT; a.st_reached = ST_REACHED_INIT;
-    a.st_arcs = ST_ARCS_INIT; a.st_ovf = ST_OVF_INIT;
-    k_wave_bfs<MODE_COUNT, WV_T, WV_CS, WV_LIM, WV_DMAX, false><<<wave_grid(ws), 64, 0, s>>>(a);
-    k_block_bfs<MODE_COUNT, BLK_NT, false><<<ws->slots, BLK_NT, 0, s>>>(a);
+    a.hub = hub_lists(ws, 0);
+    a.pass = PASS_INIT;
+    a.st_trav = ST_TRAV_INIT;
+    run_tiers<MODE_COUNT, false>(a, ws, ctr, IM_PH_INIT_T0, s);
 }
 
 // A4-A6: one greedy round
-static void greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seeds_out,
-                         uint64_t *gains_out, im_workspace *ws, uint32_t *ctr, hipStream_t s)
+static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seeds_out,
+                        uint64_t *gains_out, im_workspace *ws, uint32_t *ctr, hipStream_t s)
 {
     uint32_t n = g->n, W = (R + 63) / 64;
-    k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys + t);
+    {
+        PhaseTimer pt(ws, IM_PH_ARGMAX, s);
+        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys + t);
+    }
 
     FwdArgs f;
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
+    f.hub = hub_lists(ws, 0);
     f.n = n; f.R = R; f.W = W;
     f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend; f.fdel = ws->ffdel;
-    f.qa = ws->fqa; f.qb = ws->fqb; f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
-    f.key = ws->keys; f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
+    f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
+    f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain;
+    f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
+    f.key = ws->keys; f.t = t; f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
     f.stats = ws->stats;
-    k_forward<<<W, FWD_NT, 0, s>>>(f, t);
+    {
+        PhaseTimer pt(ws, IM_PH_FORWARD, s);
+        k_forward_block<<<W, FWB_NT, 0, s>>>(f);
+        void *args[] = {&f};
+        hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(ws->fwd_grid),
+                                                  dim3(FWD_NT), args, 0, s);
+        if (e != hipSuccess)
+            return fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
+    }
 
-    BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W, ctr);
+    BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W);
     a.tnodes = ws->tnodes; a.tcounts = ws->tcounts; a.tbits = ws->newly;
-    a.st_trav = ST_TRAV_REV; a.st_relax = ST_RELAX_REV; a.st_reached = ST_REACHED_REV;
-    a.st_arcs = ST_ARCS_REV; a.st_ovf = ST_OVF_REV;
-    k_wave_bfs<MODE_DEC, WV_T, WV_CS, WV_LIM, WV_DMAX, false><<<wave_grid(ws), 64, 0, s>>>(a);
-    k_block_bfs<MODE_DEC, BLK_NT, false><<<ws->slots, BLK_NT, 0, s>>>(a);
-    k_clear_newly<<<grid_for(n, 256, 1024), 256, 0, s>>>(ws->newly, ws->tnodes, ws->tcounts, n, W);
+    a.hub = hub_lists(ws, 1);
+    a.pass = PASS_REV;
+    a.st_trav = ST_TRAV_REV;
+    run_tiers<MODE_DEC, false>(a, ws, ctr, IM_PH_REV_T0, s);
+    {
+        PhaseTimer pt(ws, IM_PH_CLEAR, s);
+        k_clear_newly<<<grid_for(n, 256, 1024), 256, 0, s>>>(ws->newly, ws->tnodes, ws->tcounts, n, W);
+    }
+    return IM_OK;
 }
 
 // everything up to (and including) the initial gains
@@ -632,11 +1142,17 @@ static int prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k, im_
     HIPCHK(hipMemsetAsync(ws->stats, 0, ST_COUNT * sizeof(unsigned long long), s));
     fill<uint32_t>(ws->ctrs, (uint64_t)(k + 1) * PH_CTRS, 0u, s);
     fill<unsigned long long>(ws->keys, (uint64_t)k + 1, 0ull, s);
+    fill<uint32_t>(ws->fctr, (uint64_t)(k ? k : 1) * FWD_CTRS, 0u, s);
     fill<uint32_t>(ws->gain, n, 0u, s);
     fill<uint8_t>(ws->sel, n, (uint8_t)0, s);
     fill<uint64_t>(ws->covered, (uint64_t)n * W, 0ull, s);
     build_reverse(g, ws, s);
     build_masks(g, R, seed, ws, ws->mask_out, true, s);
+    {
+        PhaseTimer pt(ws, IM_PH_HUBS, s);
+        build_hubs(0, ws->row32, g->col, ws->mask_out, n, g->m, W, ws, s);
+        build_hubs(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
+    }
     initial_gains(g, R, ws, ws->ctrs, s);
     HIPCHK(hipGetLastError());
     ws->last_stream = s;
@@ -669,18 +1185,18 @@ extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
     out->trav_init = h[ST_TRAV_INIT];
     out->trav_fwd = h[ST_TRAV_FWD];
     out->trav_rev = h[ST_TRAV_REV];
-    out->relax_init = h[ST_RELAX_INIT];
-    out->reached_init = h[ST_REACHED_INIT];
-    out->relax_rev = h[ST_RELAX_REV];
-    out->reached_rev = h[ST_REACHED_REV];
+    out->trav_eval = h[ST_TRAV_EVAL];
     out->relax_fwd = h[ST_RELAX_FWD];
-    out->arcs_read_init = h[ST_ARCS_INIT];
-    out->arcs_read_rev = h[ST_ARCS_REV];
-    out->ovf_init = h[ST_OVF_INIT];
-    out->ovf_rev = h[ST_OVF_REV];
     out->tasks_rev = h[ST_TASKS_REV];
     out->decrements = h[ST_DECREMENTS];
     out->celf_evals = h[ST_CELF_EVALS];
+    for (int p = 0; p < 3; p++)
+        for (int t = 0; t < 3; t++) {
+            out->relax[p][t] = h[st_tier(p, t, F_RELAX)];
+            out->reached[p][t] = h[st_tier(p, t, F_REACHED)];
+            out->arcs_read[p][t] = h[st_tier(p, t, F_ARCS)];
+            out->handed_over[p][t] = h[st_tier(p, t, F_OVF)];
+        }
     return IM_OK;
 }
 
@@ -745,15 +1261,65 @@ extern "C" int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t see
     if (k > g->n) return fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
     if (k && (!seeds_out || !gains_out)) return fail(IM_EINVAL, "null seeds or gains output");
     hipStream_t s = (hipStream_t)stream;
+    PhaseTimer pt(ws, IM_PH_CALL, s);
     if ((rc = prepare(g, R, seed, k, ws, s))) return rc;
     uint32_t n = g->n;
     for (uint32_t t = 0; t < k; t++) {
         if (trace_out)
             k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, trace_out + (uint64_t)t * n, n);
-        greedy_round(g, R, t, seeds_out, gains_out, ws, ws->ctrs + (uint64_t)(t + 1) * PH_CTRS, s);
+        if ((rc = greedy_round(g, R, t, seeds_out, gains_out, ws,
+                               ws->ctrs + (uint64_t)(t + 1) * PH_CTRS, s)))
+            return rc;
     }
     if (trace_out && n)
         k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, trace_out + (uint64_t)k * n, n);
     HIPCHK(hipGetLastError());
     return IM_OK;
+}
+
+extern "C" int im_profile_enable(im_workspace *ws, uint32_t mask)
+{
+    if (!ws) return fail(IM_EINVAL, "null workspace");
+    ws->prof_mask = mask;
+    for (int p = 0; p < IM_PH_COUNT; p++) ws->ev_used[p] = 0;
+    return IM_OK;
+}
+
+extern "C" int im_profile_get(im_workspace *ws, im_profile *out)
+{
+    if (!ws || !out) return fail(IM_EINVAL, "null argument");
+    memset(out, 0, sizeof(*out));
+    HIPCHK(hipStreamSynchronize(ws->last_stream));
+    HIPCHK(hipDeviceSynchronize());
+    for (int p = 0; p < IM_PH_COUNT; p++) {
+        size_t u = ws->ev_used[p] & ~(size_t)1;
+        double tot = 0;
+        for (size_t i = 0; i < u; i += 2) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, ws->ev[p][i], ws->ev[p][i + 1]));
+            tot += ms;
+        }
+        out->ms[p] = tot;
+        out->launches[p] = u / 2;
+        ws->ev_used[p] = 0;
+    }
+    return IM_OK;
+}
+
+extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
+{
+    if (!ws) return fail(IM_EINVAL, "null workspace");
+    switch (option) {
+    case IM_OPT_HUB_DEGREE:
+        if (value != 0 && (value < 16 || value > 0x7FFFFFFF))
+            return fail(IM_EINVAL, "hub degree must be 0 (off) or in [16, 2^31)");
+        ws->hub_deg = (uint32_t)value;
+        return IM_OK;
+    case IM_OPT_COOP_GAIN:
+        if (value < 0) return fail(IM_EINVAL, "cooperative gain threshold must be >= 0");
+        ws->coop_gain = (uint64_t)value;
+        return IM_OK;
+    default:
+        return fail(IM_EINVAL, "unknown option %d", option);
+    }
 }

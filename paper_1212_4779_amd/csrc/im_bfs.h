@@ -10,13 +10,16 @@
 // one 8-byte mask read per arc. Results depend only on the fixpoint, never on
 // the order in which lanes apply their atomic ORs.
 //
-// Two engines share this definition:
-//   * the wavefront engine keeps T tasks per wavefront, each in an
-//     LDS-resident open-addressing table of CS entries; a task whose table
-//     fills, or which meets a node with degree > DMAX, is handed over whole
-//     to the overflow queue;
-//   * the block engine keeps one task per workgroup in dense per-slot global
-//     arrays of length n (reach, pending bits, frontier queues, visit list).
+// Three engine tiers share this definition and hand tasks down a chain of
+// queues:
+//   tier 0  k_lds_bfs with a 64-lane workgroup: T small tasks per
+//           wavefront, each in an LDS open-addressing table of CS entries;
+//   tier 1  k_lds_bfs with a 256-lane workgroup and larger tables, no degree
+//           limit (hub expansions stream through all lanes);
+//   tier 2  k_block_bfs: one task per workgroup in dense per-slot global
+//           arrays of length n (no size limit).
+// A task that fills its table (more than LIM entries) or meets a node of
+// degree > DMAX is abandoned whole and queued for the next tier.
 #pragma once
 
 #include "im_device.h"
@@ -25,10 +28,27 @@ enum { MODE_COUNT = 0, MODE_DEC = 1 };
 
 // statistics slots (uint64 counters in device memory)
 enum {
-    ST_TRAV_INIT = 0, ST_TRAV_FWD, ST_TRAV_REV,
-    ST_RELAX_INIT, ST_REACHED_INIT, ST_RELAX_REV, ST_REACHED_REV, ST_RELAX_FWD,
-    ST_ARCS_INIT, ST_ARCS_REV, ST_OVF_INIT, ST_OVF_REV, ST_TASKS_REV, ST_DECREMENTS,
-    ST_CELF_EVALS, ST_COUNT = 32
+    ST_TRAV_INIT = 0, ST_TRAV_FWD, ST_TRAV_REV, ST_TRAV_EVAL,
+    ST_RELAX_FWD, ST_TASKS_REV, ST_DECREMENTS, ST_CELF_EVALS,
+    ST_TIER_BASE = 8,   // + pass*12 + tier*4 + field
+    ST_COUNT = 64
+};
+enum { PASS_INIT = 0, PASS_REV = 1, PASS_EVAL = 2 };
+enum { F_RELAX = 0, F_REACHED = 1, F_ARCS = 2, F_OVF = 3 };
+
+__host__ __device__ constexpr int st_tier(int pass, int tier, int field)
+{
+    return ST_TIER_BASE + pass * 12 + tier * 4 + field;
+}
+
+// Per-snapshot adjacency of heavy nodes (degree >= the hub threshold), for
+// expanding them with a sparse delta: for hub index h and word w, the heads of
+// the arcs live in snapshot 64w+b are adj[off[(h*W+w)*65+b] .. off[(h*W+w)*65+b+1]).
+// slot[x] is x's hub index, or IM_EMPTY for nodes expanded through the masks.
+struct HubLists {
+    const uint32_t *slot;   // [n], nullptr: no hub lists
+    const uint32_t *off;    // [nhub][W][65]
+    const uint32_t *adj;
 };
 
 struct BfsArgs {
@@ -38,25 +58,31 @@ struct BfsArgs {
     const uint64_t *mask;     // [W][m], word-major
     uint64_t m;
     uint32_t n, R, W;
+    HubLists hub;
     const uint64_t *prune;    // [W][n] or nullptr
     uint32_t *gain;           // [n]
-    // task source
-    uint32_t ntasks;          // MODE_COUNT: n*W (task t -> word t/n, node t%n)
-    const uint32_t *tnodes;   // MODE_DEC: per-word node lists [W][n]
-    const uint32_t *tcounts;  // MODE_DEC: [W] list lengths
-    const uint64_t *tbits;    // MODE_DEC: start bits [W][n]
-    // scheduling counters (zero before launch)
-    uint32_t *grab;           // wavefront engine task counter
-    uint32_t *ovf_q;          // overflow queue of task ids
-    uint32_t *ovf_n;          // its length
-    uint32_t *bgrab;          // block engine task counter
-    // block engine slots
+    // task ids: MODE_COUNT: t in [0, n*W) -> word t/n, node t%n (or, when
+    // cand != nullptr, t in [0, ncand*W) -> word t/ncand, node cand[t%ncand]);
+    // MODE_DEC: t indexes the per-word node lists tnodes[w][0..tcounts[w])
+    uint32_t ntasks;
+    const uint32_t *cand;
+    uint32_t ncand;
+    const uint32_t *tnodes;   // [W][n]
+    const uint32_t *tcounts;  // [W]
+    const uint64_t *tbits;    // start bits [W][n]
+    // this tier's input queue (nullptr: all task ids) and output queue
+    const uint32_t *in_q;
+    const uint32_t *in_n;
+    uint32_t *out_q;
+    uint32_t *out_n;
+    uint32_t *grab;           // task counter of this launch (zero before launch)
+    // global-engine slots
     uint64_t *b_reach, *b_pend, *b_fdel;   // [slots][n]
     uint32_t *b_qa, *b_qb, *b_vis;         // [slots][n]
     unsigned long long *stats;
-    int st_trav, st_relax, st_reached, st_arcs, st_ovf;
+    int pass, tier;
+    int st_trav;
 };
-
 
 // Decode a task id into (start node, word, start bits). Returns false when
 // the task has nothing to propagate.
@@ -65,8 +91,13 @@ __device__ __forceinline__ bool decode_task(const BfsArgs &a, int mode, uint32_t
                                             uint32_t &w, uint64_t &bits)
 {
     if (mode == MODE_COUNT) {
-        w = t / a.n;
-        src = t - w * a.n;
+        if (a.cand) {
+            w = t / a.ncand;
+            src = a.cand[t - w * a.ncand];
+        } else {
+            w = t / a.n;
+            src = t - w * a.n;
+        }
         bits = im_valid_bits(a.R, w);
         if (a.prune) bits &= ~a.prune[(uint64_t)w * a.n + src];
     } else {
@@ -78,54 +109,226 @@ __device__ __forceinline__ bool decode_task(const BfsArgs &a, int mode, uint32_t
     return bits != 0;
 }
 
+__device__ __forceinline__ void fill_wpre(const BfsArgs &a, uint32_t *wpre)
+{
+    uint32_t s = 0;
+    for (uint32_t w = 0; w < a.W; w++) { wpre[w] = s; s += a.tcounts[w]; }
+    wpre[a.W] = s;
+}
+
+template <int NT>
+__device__ __forceinline__ uint32_t group_excl_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    if constexpr (NT == 64) {
+        uint32_t incl = wave_incl_scan(v);
+        *total = __shfl(incl, 63, 64);
+        return incl - v;
+    } else {
+        return block_excl_scan<NT>(v, wsum, total);
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t group_sum(uint64_t v, unsigned long long *red)
+{
+    v = wave_sum_u64(v);
+    if constexpr (NT == 64) {
+        return v;
+    } else {
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        uint64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; i++) s += red[i];
+        __syncthreads();
+        return s;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Wavefront engine
+// Hub expansions. Frontier nodes with hub lists are collected per chunk and
+// expanded afterwards in batches of HB items, flattened over (item, snapshot
+// bit, listed head) so that all lanes share the work of a few huge items as
+// well as of many small ones. Each listed head receives its single bit.
 // ---------------------------------------------------------------------------
-template <int T, int CS>
-struct WaveLds {
+template <int NT, int HB>
+struct HubBatch {
+    uint32_t hub[NT];       // hub index of item q
+    uint32_t own[NT];       // owner of item q (table entry, or unused)
+    uint64_t del[NT];       // delta bits of item q
+    uint32_t pre[HB][64];   // per batch item: exclusive prefix of per-bit counts
+    uint32_t off[HB][64];   // per batch item: start of each bit's list
+    uint32_t ipre[HB];      // exclusive prefix of item totals (total past the batch)
+    uint32_t tot[HB];
+    uint32_t n, total;
+};
+
+template <int NT, int HB>
+__device__ __forceinline__ void hub_push(HubBatch<NT, HB> &H, uint32_t hs, uint32_t own, uint64_t d)
+{
+    uint32_t q = atomicAdd(&H.n, 1u);
+    H.hub[q] = hs; H.own[q] = own; H.del[q] = d;
+}
+
+// word_of(own) -> snapshot word of an item; relax(own, v, bits) applies one relaxation
+// nh: number of collected items, read by every thread between the barrier that
+// follows their collection and the next collection
+template <int NT, int HB, int U, typename WordOf, typename Relax>
+__device__ void expand_hubs(HubBatch<NT, HB> &H, uint32_t nh, const HubLists &hub, uint32_t W,
+                            WordOf word_of, Relax relax, uint64_t &arcs)
+{
+    static_assert((HB & (HB - 1)) == 0, "HB must be a power of two");
+    constexpr int NWAVE = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (uint32_t base = 0; base < nh; base += HB) {
+        const uint32_t nb = min((uint32_t)HB, nh - base);
+        for (uint32_t q = wid; q < nb; q += NWAVE) {
+            const uint32_t it = base + q;
+            const uint32_t *o = hub.off + ((uint64_t)H.hub[it] * W + word_of(H.own[it])) * 65;
+            uint32_t lo = o[lane], hi = o[lane + 1];
+            uint32_t c = ((H.del[it] >> lane) & 1ull) ? hi - lo : 0u;
+            uint32_t incl = wave_incl_scan(c);
+            H.pre[q][lane] = incl - c;
+            H.off[q][lane] = lo;
+            if (lane == 63) H.tot[q] = incl;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            for (uint32_t q = 0; q < (uint32_t)HB; q++) {
+                H.ipre[q] = acc;
+                if (q < nb) acc += H.tot[q];
+            }
+            H.total = acc;
+        }
+        __syncthreads();
+        const uint32_t total = H.total;
+        arcs += total;
+        // uniform trip count: every lane calls relax() the same number of times
+        for (uint32_t j0 = 0; j0 < total; j0 += NT * U) {
+            uint32_t vv[U], qq[U];
+            uint64_t bb[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                uint32_t j = j0 + (uint32_t)tid + (uint32_t)u * NT;
+                bb[u] = 0; vv[u] = 0; qq[u] = 0;
+                if (j < total) {
+                    int q = upper_index<HB>(H.ipre, j);
+                    uint32_t r = j - H.ipre[q];
+                    int b = upper_index<64>(H.pre[q], r);
+                    vv[u] = hub.adj[H.off[q][b] + (r - H.pre[q][b])];
+                    bb[u] = 1ull << b;
+                    qq[u] = base + (uint32_t)q;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) relax(H.own[qq[u]], vv[u], bb[u]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) H.n = 0;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// LDS engine (tiers 0 and 1)
+// ---------------------------------------------------------------------------
+template <int NT, int T, int CS>
+struct LdsState {
     uint32_t keys[T * CS];
     uint64_t reach[T * CS];
     uint64_t pend[T * CS];
-    uint64_t fdel[T * CS];
     uint32_t deg[T * CS];
     uint32_t fr[2][T * CS];
-    uint32_t c_excl[64];
-    uint32_t c_rs[64];
-    uint32_t c_idx[64];
-    uint64_t c_del[64];
-    uint32_t s_task[T], s_src[T], s_word[T], s_cnt[T], s_next[T], s_ovf[T], s_act[T];
+    uint32_t c_excl[NT];
+    uint32_t c_rs[NT];
+    uint32_t c_idx[NT];
+    uint64_t c_del[NT];
+    uint32_t wsum[NT / 64 + 1];
+    unsigned long long red[NT / 64];
+    uint32_t s_task[T], s_src[T], s_word[T], s_cnt[T], s_next[T], s_ovf[T], s_act[T], s_new[T];
     uint32_t wpre[65];
+    HubBatch<NT, (NT == 64 ? 2 : 16)> H;
     uint32_t nf, nn, tnext, tend, ntasks, done;
 };
 
+// insert v into slot s's table (if absent) and OR in `bits`; push the entry
+// onto the next frontier when its pending bits become non-zero
+template <int NT, int T, int CS, int LIM>
+__device__ __forceinline__ void lds_relax(LdsState<NT, T, CS> &L, uint32_t s, uint32_t v,
+                                          uint64_t bits, int nxt)
+{
+    constexpr int LOG_CS = __builtin_ctz(CS);
+    if (L.s_ovf[s]) return;  // abandoned: stop touching its full table
+    uint32_t h = (v * 0x9E3779B1u) >> (32 - LOG_CS);
+    int found = -1;
+    for (int p = 0; p < CS; p++) {
+        uint32_t pos = s * CS + h;
+        uint32_t key = L.keys[pos];
+        if (key == v) { found = (int)pos; break; }
+        if (key == IM_EMPTY) {
+            uint32_t old = atomicCAS(&L.keys[pos], IM_EMPTY, v);
+            if (old == IM_EMPTY) {
+                uint32_t c = atomicAdd(&L.s_cnt[s], 1u);
+                if (c + 1 > (uint32_t)LIM) L.s_ovf[s] = 1;
+                found = (int)pos;
+                break;
+            }
+            if (old == v) { found = (int)pos; break; }
+        }
+        h = (h + 1) & (CS - 1);
+    }
+    if (found < 0) { L.s_ovf[s] = 1; return; }
+    uint64_t old = atomicOr((unsigned long long *)&L.reach[found], (unsigned long long)bits);
+    uint64_t nb = bits & ~old;
+    if (nb) {
+        uint64_t op = atomicOr((unsigned long long *)&L.pend[found], (unsigned long long)nb);
+        if (op == 0) {
+            uint32_t q = atomicAdd(&L.nn, 1u);
+            L.fr[nxt][q] = (uint32_t)found;
+            atomicAdd(&L.s_next[s], 1u);
+        }
+    }
+}
+
 __device__ __forceinline__ uint32_t slot_hash(uint32_t v) { return v * 0x9E3779B1u; }
 
-template <int MODE, int T, int CS, int LIM, int DMAX, bool PRUNE>
-__global__ __launch_bounds__(64) void k_wave_bfs(BfsArgs a)
+// Append from the lanes where pred holds with one atomic per wavefront. Every
+// lane of the wavefront must call it. Returns each appending lane's position.
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *counter)
+{
+    const uint64_t bal = __ballot(pred);
+    if (!bal) return 0;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(bal));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+}
+
+template <int MODE, int NT, int T, int CS, int LIM, uint32_t DMAX, int U, bool PRUNE>
+__global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
 {
     static_assert((CS & (CS - 1)) == 0, "CS must be a power of two");
+    static_assert(LIM < CS, "LIM must leave free table entries");
     constexpr int LOG_CS = __builtin_ctz(CS);
     constexpr int N = T * CS;
-    constexpr uint32_t CHUNK = 16;
-    __shared__ WaveLds<T, CS> L;
-    const int lane = threadIdx.x;
+    constexpr uint32_t CHUNK = 8;
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    __shared__ LdsState<NT, T, CS> L;
+    const int tid = threadIdx.x;
 
-    for (int i = lane; i < N; i += 64) {
+    for (int i = tid; i < N; i += NT) {
         L.keys[i] = IM_EMPTY; L.reach[i] = 0; L.pend[i] = 0; L.deg[i] = 0;
     }
-    if (lane < T) {
-        L.s_act[lane] = 0; L.s_cnt[lane] = 0; L.s_next[lane] = 0; L.s_ovf[lane] = 0;
+    if (tid < T) {
+        L.s_act[tid] = 0; L.s_cnt[tid] = 0; L.s_next[tid] = 0; L.s_ovf[tid] = 0;
     }
-    if (lane == 0) {
-        L.nf = 0; L.nn = 0; L.tnext = 0; L.tend = 0; L.done = 0;
-        if (MODE == MODE_COUNT) {
-            L.ntasks = a.ntasks;
-        } else {
-            uint32_t s = 0;
-            for (uint32_t w = 0; w < a.W; w++) { L.wpre[w] = s; s += a.tcounts[w]; }
-            L.wpre[a.W] = s;
-            L.ntasks = s;
-        }
+    if (tid == 0) {
+        L.nf = 0; L.nn = 0; L.tnext = 0; L.tend = 0; L.done = 0; L.H.n = 0;
+        if (MODE == MODE_DEC) fill_wpre(a, L.wpre);
+        L.ntasks = a.in_q ? *a.in_n : (MODE == MODE_COUNT ? a.ntasks : L.wpre[a.W]);
     }
     __syncthreads();
 
@@ -133,135 +336,154 @@ __global__ __launch_bounds__(64) void k_wave_bfs(BfsArgs a)
     int cur = 0;
 
     for (;;) {
-        // ---- refill idle slots with new tasks (lane 0 grabs, all lanes wait)
-        if (lane == 0 && !L.done) {
+        // ---- refill: thread 0 hands task indices to idle slots
+        if (tid == 0) {
+            L.nn = 0;
             for (int s = 0; s < T; s++) {
-                if (L.s_act[s]) continue;
-                for (;;) {
-                    if (L.tnext == L.tend) {
-                        uint32_t b = atomicAdd(a.grab, CHUNK);
-                        if (b >= L.ntasks) { L.done = 1; break; }
-                        L.tnext = b;
-                        L.tend = min(b + CHUNK, L.ntasks);
-                    }
-                    uint32_t t = L.tnext++;
-                    uint32_t src, w;
-                    uint64_t bits;
-                    if (!decode_task(a, MODE, t, L.wpre, src, w, bits)) continue;
-                    uint32_t idx = s * CS + (slot_hash(src) >> (32 - LOG_CS));
-                    L.keys[idx] = src;
-                    L.reach[idx] = bits;
-                    L.pend[idx] = bits;
-                    L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w;
-                    L.s_cnt[s] = 1; L.s_ovf[s] = 0; L.s_next[s] = 0; L.s_act[s] = 1;
-                    L.fr[cur][L.nf++] = idx;
-                    break;
+                L.s_next[s] = 0;
+                L.s_new[s] = NONE;
+                if (L.s_act[s] || L.done) continue;
+                if (L.tnext == L.tend) {
+                    uint32_t b = atomicAdd(a.grab, CHUNK);
+                    if (b >= L.ntasks) { L.done = 1; continue; }
+                    L.tnext = b;
+                    L.tend = min(b + CHUNK, L.ntasks);
                 }
-                if (L.done) break;
+                L.s_new[s] = L.tnext++;
+            }
+        }
+        __syncthreads();
+        if (tid < T && L.s_new[tid] != NONE) {
+            const int s = tid;
+            uint32_t t = a.in_q ? a.in_q[L.s_new[s]] : L.s_new[s];
+            uint32_t src, w;
+            uint64_t bits;
+            if (decode_task(a, MODE, t, L.wpre, src, w, bits)) {
+                uint32_t idx = s * CS + (slot_hash(src) >> (32 - LOG_CS));
+                L.keys[idx] = src;
+                L.reach[idx] = bits;
+                L.pend[idx] = bits;
+                L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w;
+                L.s_cnt[s] = 1; L.s_ovf[s] = 0; L.s_act[s] = 1;
+                L.fr[cur][atomicAdd(&L.nf, 1u)] = idx;
             }
         }
         __syncthreads();
         const uint32_t nf = L.nf;
-        if (nf == 0) break;
-
-        // ---- phase A: take the pending bits of every frontier entry
-        for (uint32_t i = lane; i < nf; i += 64) {
-            uint32_t idx = L.fr[cur][i];
-            L.fdel[i] = L.pend[idx];
-            L.pend[idx] = 0;
+        if (nf == 0) {
+            if (L.done) break;
+            continue;
         }
-        if (lane < T) L.s_next[lane] = 0;
-        if (lane == 0) L.nn = 0;
-        __syncthreads();
 
-        // ---- phase B: expand, 64 frontier entries per chunk, arcs spread over lanes
-        for (uint32_t base = 0; base < nf; base += 64) {
-            uint32_t i = base + lane;
+        // ---- phase B: expand NT frontier entries per chunk, arcs spread over lanes
+        for (uint32_t base = 0; base < nf; base += NT) {
+            uint32_t i = base + tid;
             uint32_t deg = 0, rs = 0, idx = 0;
             uint64_t d = 0;
             if (i < nf) {
                 idx = L.fr[cur][i];
                 uint32_t s = idx >> LOG_CS;
                 if (!L.s_ovf[s]) {
+                    // take the bits gained since the last expansion; bits that
+                    // arrive later re-queue the entry for the next level
+                    const uint64_t delta = atomicExch((unsigned long long *)&L.pend[idx], 0ull);
                     uint32_t x = L.keys[idx];
+                    uint32_t hs = a.hub.slot ? a.hub.slot[x] : IM_EMPTY;
                     rs = a.row[x];
                     deg = a.row[x + 1] - rs;
-                    if (deg > (uint32_t)DMAX) { L.s_ovf[s] = 1; deg = 0; }
-                    else { L.deg[idx] = deg; d = L.fdel[i]; }
+                    L.deg[idx] = deg;
+                    if (hs != IM_EMPTY) {
+                        hub_push(L.H, hs, idx, delta);
+                        deg = 0;
+                    } else if (deg > DMAX) {
+                        L.s_ovf[s] = 1; deg = 0;
+                    } else {
+                        d = delta;
+                    }
                 }
             }
-            uint32_t incl = wave_incl_scan(deg);
-            uint32_t total = __shfl(incl, 63, 64);
-            L.c_excl[lane] = incl - deg;
-            L.c_rs[lane] = rs;
-            L.c_idx[lane] = idx;
-            L.c_del[lane] = d;
+            uint32_t total;
+            uint32_t ex = group_excl_scan<NT>(deg, L.wsum, &total);
+            L.c_excl[tid] = ex;
+            L.c_rs[tid] = rs;
+            L.c_idx[tid] = idx;
+            L.c_del[tid] = d;
             __syncthreads();
+            const uint32_t nhub = L.H.n;
             st_arcs += total;
-            for (uint32_t j = lane; j < total; j += 64) {
-                int k = upper_index<64>(L.c_excl, j);
-                uint32_t e = L.c_rs[k] + (j - L.c_excl[k]);
-                uint32_t cidx = L.c_idx[k];
-                uint32_t s = cidx >> LOG_CS;
-                uint64_t w = L.s_word[s];
-                uint64_t bits = L.c_del[k] & a.mask[w * a.m + e];
-                if (!bits) continue;
-                uint32_t v = a.col[e];
+            for (uint32_t j0 = tid; j0 < total; j0 += NT * U) {
+                uint32_t kk[U], ee[U], vv[U];
+                uint64_t bb[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    uint32_t j = j0 + (uint32_t)u * NT;
+                    kk[u] = NONE;
+                    ee[u] = 0;
+                    if (j < total) {
+                        int k = upper_index<NT>(L.c_excl, j);
+                        kk[u] = (uint32_t)k;
+                        ee[u] = L.c_rs[k] + (j - L.c_excl[k]);
+                    }
+                }
+                // mask word and head id are independent loads: issue all of them
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    bb[u] = 0;
+                    vv[u] = 0;
+                    if (kk[u] != NONE && !L.s_ovf[L.c_idx[kk[u]] >> LOG_CS]) {
+                        uint64_t w = L.s_word[L.c_idx[kk[u]] >> LOG_CS];
+                        bb[u] = a.mask[w * a.m + ee[u]];
+                        vv[u] = a.col[ee[u]];
+                    } else {
+                        kk[u] = NONE;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    if (kk[u] != NONE) bb[u] &= L.c_del[kk[u]];
                 if (PRUNE) {
-                    bits &= ~a.prune[w * a.n + v];
-                    if (!bits) continue;
-                }
-                // find or insert v in slot s
-                uint32_t h = slot_hash(v) >> (32 - LOG_CS);
-                int found = -1;
-                for (int p = 0; p < CS; p++) {
-                    uint32_t pos = s * CS + h;
-                    uint32_t kk = L.keys[pos];
-                    if (kk == v) { found = (int)pos; break; }
-                    if (kk == IM_EMPTY) {
-                        uint32_t old = atomicCAS(&L.keys[pos], IM_EMPTY, v);
-                        if (old == IM_EMPTY) {
-                            uint32_t c = atomicAdd(&L.s_cnt[s], 1u);
-                            if (c + 1 > (uint32_t)LIM) L.s_ovf[s] = 1;
-                            found = (int)pos;
-                            break;
+#pragma unroll
+                    for (int u = 0; u < U; u++)
+                        if (bb[u]) {
+                            uint64_t w = L.s_word[L.c_idx[kk[u]] >> LOG_CS];
+                            bb[u] &= ~a.prune[w * a.n + vv[u]];
                         }
-                        if (old == v) { found = (int)pos; break; }
-                    }
-                    h = (h + 1) & (CS - 1);
                 }
-                if (found < 0) { L.s_ovf[s] = 1; continue; }
-                uint64_t old = atomicOr((unsigned long long *)&L.reach[found], (unsigned long long)bits);
-                uint64_t nb = bits & ~old;
-                if (nb) {
-                    uint64_t op = atomicOr((unsigned long long *)&L.pend[found], (unsigned long long)nb);
-                    if (op == 0) {
-                        uint32_t q = atomicAdd(&L.nn, 1u);
-                        L.fr[cur ^ 1][q] = (uint32_t)found;
-                        atomicAdd(&L.s_next[s], 1u);
-                    }
-                }
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    if (bb[u]) lds_relax<NT, T, CS, LIM>(L, L.c_idx[kk[u]] >> LOG_CS, vv[u], bb[u], cur ^ 1);
             }
             __syncthreads();
+            // hub expansions of this chunk: only the arcs live in the delta's snapshots
+            if (nhub) {
+                auto word_of = [&](uint32_t own) { return L.s_word[own >> LOG_CS]; };
+                auto relax = [&](uint32_t own, uint32_t v, uint64_t bits) {
+                    if (!bits) return;
+                    const uint32_t s = own >> LOG_CS;
+                    if (PRUNE) bits &= ~a.prune[(uint64_t)L.s_word[s] * a.n + v];
+                    if (bits) lds_relax<NT, T, CS, LIM>(L, s, v, bits, cur ^ 1);
+                };
+                expand_hubs<NT, (NT == 64 ? 2 : 16), U>(L.H, nhub, a.hub, a.W, word_of, relax, st_arcs);
+            }
         }
 
         // ---- finish slots whose search ended or overflowed
         bool any_ovf_fin = false;
         for (int s = 0; s < T; s++) {
             if (!L.s_act[s]) continue;
-            bool ovf = L.s_ovf[s] != 0;
+            const bool ovf = L.s_ovf[s] != 0;
             if (!ovf && L.s_next[s] != 0) continue;
-            uint32_t base = s * CS;
+            const uint32_t base = s * CS;
             if (ovf) {
                 any_ovf_fin = true;
-                if (lane == 0) {
-                    uint32_t q = atomicAdd(a.ovf_n, 1u);
-                    a.ovf_q[q] = L.s_task[s];
+                if (tid == 0) {
+                    uint32_t q = atomicAdd(a.out_n, 1u);
+                    a.out_q[q] = L.s_task[s];
+                    st_ovf += 1;
                 }
-                st_ovf += (lane == 0);
             } else {
                 uint64_t cnt = 0;
-                for (int i = lane; i < CS; i += 64) {
+                for (int i = tid; i < CS; i += NT) {
                     uint32_t key = L.keys[base + i];
                     if (key == IM_EMPTY) continue;
                     uint32_t pc = (uint32_t)__popcll(L.reach[base + i]);
@@ -273,60 +495,61 @@ __global__ __launch_bounds__(64) void k_wave_bfs(BfsArgs a)
                     else { atomicSub(&a.gain[key], pc); st_dec += pc; }
                 }
                 if (MODE == MODE_COUNT) {
-                    cnt = wave_sum_u64(cnt);
-                    if (lane == 0) atomicAdd(&a.gain[L.s_src[s]], (uint32_t)cnt);
+                    cnt = group_sum<NT>(cnt, L.red);
+                    if (tid == 0) atomicAdd(&a.gain[L.s_src[s]], (uint32_t)cnt);
                 }
             }
-            for (int i = lane; i < CS; i += 64) {
+            for (int i = tid; i < CS; i += NT) {
                 L.keys[base + i] = IM_EMPTY; L.reach[base + i] = 0;
                 L.pend[base + i] = 0; L.deg[base + i] = 0;
             }
             __syncthreads();
-            if (lane == 0) { L.s_act[s] = 0; L.s_cnt[s] = 0; L.s_ovf[s] = 0; }
+            if (tid == 0) { L.s_act[s] = 0; L.s_cnt[s] = 0; L.s_ovf[s] = 0; }
             __syncthreads();
         }
 
         // ---- drop next-frontier entries that belong to slots just handed over
         uint32_t nn = L.nn;
         if (any_ovf_fin) {
-            uint32_t w = 0;
-            for (uint32_t base = 0; base < nn; base += 64) {
-                uint32_t i = base + lane;
+            uint32_t wpos = 0;
+            for (uint32_t base = 0; base < nn; base += NT) {
+                uint32_t i = base + tid;
                 uint32_t idx = i < nn ? L.fr[cur ^ 1][i] : 0;
-                bool keep = i < nn && L.s_act[idx >> LOG_CS];
-                uint64_t bal = __ballot(keep);
-                uint32_t before = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                uint32_t keep = (i < nn && L.s_act[idx >> LOG_CS]) ? 1u : 0u;
+                uint32_t tot;
+                uint32_t before = group_excl_scan<NT>(keep, L.wsum, &tot);
                 __syncthreads();
-                if (keep) L.fr[cur ^ 1][w + before] = idx;
-                w += (uint32_t)__popcll(bal);
+                if (keep) L.fr[cur ^ 1][wpos + before] = idx;
+                wpos += tot;
                 __syncthreads();
             }
-            nn = w;
+            nn = wpos;
         }
         __syncthreads();
-        if (lane == 0) L.nf = nn;
+        if (tid == 0) L.nf = nn;
         cur ^= 1;
         __syncthreads();
     }
 
-    // ---- per-wavefront statistics
-    st_relax = wave_sum_u64(st_relax);
-    st_reached = wave_sum_u64(st_reached);
-    st_trav = wave_sum_u64(st_trav);
-    st_dec = wave_sum_u64(st_dec);
-    if (lane == 0) {
+    // ---- statistics: one atomic per counter per workgroup
+    st_relax = group_sum<NT>(st_relax, L.red);
+    st_reached = group_sum<NT>(st_reached, L.red);
+    st_trav = group_sum<NT>(st_trav, L.red);
+    st_dec = group_sum<NT>(st_dec, L.red);
+    st_ovf = group_sum<NT>(st_ovf, L.red);
+    if (tid == 0) {
         if (MODE == MODE_DEC) atomicAdd(&a.stats[ST_DECREMENTS], (unsigned long long)st_dec);
-        atomicAdd(&a.stats[a.st_relax], (unsigned long long)st_relax);
-        atomicAdd(&a.stats[a.st_reached], (unsigned long long)st_reached);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_RELAX)], (unsigned long long)st_relax);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)st_reached);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_ARCS)], (unsigned long long)st_arcs);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_OVF)], (unsigned long long)st_ovf);
         atomicAdd(&a.stats[a.st_trav], (unsigned long long)st_trav);
-        atomicAdd(&a.stats[a.st_arcs], (unsigned long long)st_arcs);
-        atomicAdd(&a.stats[a.st_ovf], (unsigned long long)st_ovf);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Block engine: one task per workgroup, dense arrays of length n per slot.
-// reach and pend are all-zero on entry and are left all-zero on exit.
+// Global engine (last tier): one task per workgroup, dense arrays of length n
+// per slot. reach and pend are all-zero on entry and are left all-zero.
 // ---------------------------------------------------------------------------
 template <int NT>
 struct BlockLds {
@@ -336,49 +559,60 @@ struct BlockLds {
     uint32_t wsum[NT / 64 + 1];
     uint32_t nf, nn, nvis, task;
     unsigned long long red[NT / 64];
+    HubBatch<NT, 16> H;
 };
+
+__device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, uint32_t *vis,
+                                             uint32_t *nxt, uint32_t *nvis, uint32_t *nn,
+                                             uint32_t v, uint64_t bits)
+{
+    uint64_t old = atomicOr((unsigned long long *)&reach[v], (unsigned long long)bits);
+    uint64_t nb = bits & ~old;
+    if (!nb) return;
+    if (old == 0) vis[atomicAdd(nvis, 1u)] = v;
+    uint64_t op = atomicOr((unsigned long long *)&pend[v], (unsigned long long)nb);
+    if (op == 0) nxt[atomicAdd(nn, 1u)] = v;
+}
 
 // Run one task to its fixpoint; afterwards vis[0..L.nvis) lists every node
 // with reach != 0.
-template <int NT, bool PRUNE>
+template <int NT, int U, bool PRUNE>
 __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                               const uint32_t *row, const uint32_t *col, const uint64_t *mask,
+                              const HubLists &hub, uint32_t W, uint32_t w,
                               const uint64_t *prune, uint64_t *reach, uint64_t *pend,
                               uint64_t *fdel, uint32_t *qa, uint32_t *qb, uint32_t *vis,
                               uint64_t &arcs)
 {
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
     const int tid = threadIdx.x;
     if (tid == 0) {
         reach[src] = start;
-        fdel[0] = start;
+        pend[src] = start;
         qa[0] = src;
         vis[0] = src;
-        L.nf = 1; L.nn = 0; L.nvis = 1;
+        L.nf = 1; L.nn = 0; L.nvis = 1; L.H.n = 0;
     }
     __syncthreads();
     uint32_t *cur = qa, *nxt = qb;
-    bool first = true;
     for (;;) {
         const uint32_t nf = L.nf;
         if (nf == 0) break;
-        if (!first) {
-            for (uint32_t i = tid; i < nf; i += NT) {
-                uint32_t x = cur[i];
-                fdel[i] = pend[x];
-                pend[x] = 0;
-            }
-        }
-        first = false;
-        __syncthreads();
         for (uint32_t tile = 0; tile < nf; tile += NT) {
             uint32_t i = tile + tid;
             uint32_t deg = 0, rs = 0;
             uint64_t d = 0;
             if (i < nf) {
                 uint32_t x = cur[i];
+                uint32_t hs = hub.slot ? hub.slot[x] : IM_EMPTY;
                 rs = row[x];
                 deg = row[x + 1] - rs;
-                d = fdel[i];
+                // bits gained since the last expansion (later ones re-queue x)
+                d = atomicExch((unsigned long long *)&pend[x], 0ull);
+                if (hs != IM_EMPTY) {
+                    hub_push(L.H, hs, 0u, d);
+                    deg = 0; d = 0;
+                }
             }
             uint32_t total;
             uint32_t ex = block_excl_scan<NT>(deg, L.wsum, &total);
@@ -386,25 +620,50 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
             L.rs[tid] = rs;
             L.del[tid] = d;
             __syncthreads();
+            const uint32_t nhub = L.H.n;
             arcs += total;
-            for (uint32_t j = tid; j < total; j += NT) {
-                int k = upper_index<NT>(L.scan, j);
-                uint32_t e = L.rs[k] + (j - L.scan[k]);
-                uint64_t bits = L.del[k] & mask[e];
-                if (!bits) continue;
-                uint32_t v = col[e];
-                if (PRUNE) {
-                    bits &= ~prune[v];
-                    if (!bits) continue;
+            for (uint32_t j0 = tid; j0 < total; j0 += NT * U) {
+                uint32_t kk[U], ee[U], vv[U];
+                uint64_t bb[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    uint32_t j = j0 + (uint32_t)u * NT;
+                    kk[u] = NONE;
+                    ee[u] = 0;
+                    if (j < total) {
+                        int k = upper_index<NT>(L.scan, j);
+                        kk[u] = (uint32_t)k;
+                        ee[u] = L.rs[k] + (j - L.scan[k]);
+                    }
                 }
-                uint64_t old = atomicOr((unsigned long long *)&reach[v], (unsigned long long)bits);
-                uint64_t nb = bits & ~old;
-                if (!nb) continue;
-                if (old == 0) vis[atomicAdd(&L.nvis, 1u)] = v;
-                uint64_t op = atomicOr((unsigned long long *)&pend[v], (unsigned long long)nb);
-                if (op == 0) nxt[atomicAdd(&L.nn, 1u)] = v;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    bb[u] = kk[u] != NONE ? mask[ee[u]] : 0ull;
+                    vv[u] = kk[u] != NONE ? col[ee[u]] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    if (kk[u] != NONE) bb[u] &= L.del[kk[u]];
+                if (PRUNE) {
+#pragma unroll
+                    for (int u = 0; u < U; u++)
+                        if (bb[u]) bb[u] &= ~prune[vv[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    if (bb[u]) global_relax(reach, pend, vis, nxt, &L.nvis, &L.nn, vv[u], bb[u]);
             }
             __syncthreads();
+            // hub expansions of this tile: only the arcs live in the delta's snapshots
+            if (nhub) {
+                auto word_of = [&](uint32_t) { return w; };
+                auto relax = [&](uint32_t, uint32_t v, uint64_t bits) {
+                    if (!bits) return;
+                    if (PRUNE) bits &= ~prune[v];
+                    if (bits) global_relax(reach, pend, vis, nxt, &L.nvis, &L.nn, v, bits);
+                };
+                expand_hubs<NT, 16, U>(L.H, nhub, hub, W, word_of, relax, arcs);
+            }
         }
         if (tid == 0) { L.nf = L.nn; L.nn = 0; }
         uint32_t *t = cur; cur = nxt; nxt = t;
@@ -412,7 +671,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
     }
 }
 
-template <int MODE, int NT, bool PRUNE>
+template <int MODE, int NT, int U, bool PRUNE>
 __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
 {
     __shared__ BlockLds<NT> L;
@@ -425,27 +684,23 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     uint32_t *qa = a.b_qa + slot * a.n;
     uint32_t *qb = a.b_qb + slot * a.n;
     uint32_t *vis = a.b_vis + slot * a.n;
-    if (tid == 0 && MODE == MODE_DEC) {
-        uint32_t s = 0;
-        for (uint32_t w = 0; w < a.W; w++) { wpre[w] = s; s += a.tcounts[w]; }
-        wpre[a.W] = s;
-    }
+    if (tid == 0 && MODE == MODE_DEC) fill_wpre(a, wpre);
     __syncthreads();
-    const uint32_t nq = *a.ovf_n;
+    const uint32_t nq = *a.in_n;
     uint64_t arcs = 0, relax = 0, reached = 0, trav = 0, dec = 0;
     for (;;) {
-        if (tid == 0) L.task = atomicAdd(a.bgrab, 1u);
+        if (tid == 0) L.task = atomicAdd(a.grab, 1u);
         __syncthreads();
         const uint32_t q = L.task;
         __syncthreads();
         if (q >= nq) break;
         uint32_t src, w;
         uint64_t bits;
-        if (!decode_task(a, MODE, a.ovf_q[q], wpre, src, w, bits)) continue;
+        if (!decode_task(a, MODE, a.in_q[q], wpre, src, w, bits)) continue;
         const uint64_t *mask = a.mask + (uint64_t)w * a.m;
         const uint64_t *prune = PRUNE ? a.prune + (uint64_t)w * a.n : nullptr;
-        block_bfs_run<NT, PRUNE>(L, src, bits, a.row, a.col, mask, prune, reach, pend, fdel,
-                                 qa, qb, vis, arcs);
+        block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.W, w, prune, reach,
+                                    pend, fdel, qa, qb, vis, arcs);
         const uint32_t nvis = L.nvis;
         uint64_t cnt = 0;
         for (uint32_t i = tid; i < nvis; i += NT) {
@@ -460,27 +715,20 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
             reach[x] = 0;
         }
         if (MODE == MODE_COUNT) {
-            cnt = wave_sum_u64(cnt);
-            if ((tid & 63) == 0) L.red[tid >> 6] = cnt;
-            __syncthreads();
-            if (tid == 0) {
-                uint64_t s = 0;
-                for (int i = 0; i < NT / 64; i++) s += L.red[i];
-                atomicAdd(&a.gain[src], (uint32_t)s);
-            }
+            cnt = group_sum<NT>(cnt, L.red);
+            if (tid == 0) atomicAdd(&a.gain[src], (uint32_t)cnt);
         }
         __syncthreads();
     }
-    arcs = (tid == 0) ? arcs : 0;  // arcs is uniform across the block
-    relax = wave_sum_u64(relax);
-    reached = wave_sum_u64(reached);
-    trav = wave_sum_u64(trav);
-    dec = wave_sum_u64(dec);
-    if ((tid & 63) == 0) {
+    relax = group_sum<NT>(relax, L.red);
+    reached = group_sum<NT>(reached, L.red);
+    trav = group_sum<NT>(trav, L.red);
+    dec = group_sum<NT>(dec, L.red);
+    if (tid == 0) {
         if (MODE == MODE_DEC) atomicAdd(&a.stats[ST_DECREMENTS], (unsigned long long)dec);
-        atomicAdd(&a.stats[a.st_relax], (unsigned long long)relax);
-        atomicAdd(&a.stats[a.st_reached], (unsigned long long)reached);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_RELAX)], (unsigned long long)relax);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)reached);
+        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_ARCS)], (unsigned long long)arcs);
         atomicAdd(&a.stats[a.st_trav], (unsigned long long)trav);
-        if (tid == 0) atomicAdd(&a.stats[a.st_arcs], (unsigned long long)arcs);
     }
 }

@@ -120,6 +120,47 @@ def test_select_full_trace(im, case):
         assert gs[a] == st[b], a
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[6]], ids=["tiny_uic", "dense_p30", "hub_star"])
+def test_schedule_invariance_hub_lists(im, case):
+    # the heavy-node threshold only changes how nodes are expanded, never results
+    _, g, R, k, seed = case
+    d = _dev(im, g)
+    ref = None
+    for deg in (0, 16, 64, 256, 1 << 20):
+        ws = im.Workspace()
+        ws.set_hub_degree(deg)
+        seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
+        got = (seeds.cpu().numpy(), gains.cpu().numpy(), tr.cpu().numpy(), ws.stats())
+        if ref is None:
+            ref = got
+            s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
+            assert np.array_equal(got[0], s_ref.astype(np.int64))
+            continue
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+        assert np.array_equal(got[2], ref[2])
+        for key in ("trav_init", "trav_fwd", "trav_rev", "decrements", "relax_init", "relax_rev"):
+            assert got[3][key] == ref[3][key], (deg, key)
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6]], ids=["nethept_wc", "dense_p30", "hub_star"])
+def test_schedule_invariance_forward(im, case):
+    # grid-wide or per-word forward search: identical results
+    _, g, R, k, seed = case
+    d = _dev(im, g)
+    outs = []
+    for gain in (0, 1 << 62, 2000):
+        ws = im.Workspace()
+        ws.set_coop_gain(gain)
+        seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
+        outs.append((seeds.cpu().numpy(), gains.cpu().numpy(), tr.cpu().numpy(), ws.stats()))
+    s_ref, g_ref, _, st = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
+    for o in outs:
+        assert np.array_equal(o[0], s_ref.astype(np.int64))
+        assert np.array_equal(o[1], g_ref.astype(np.int64))
+        assert np.array_equal(o[2], outs[0][2])
+        assert o[3]["trav_fwd"] == st["trav_fwd"]
+
+
 def test_repeat_and_workspace_reuse(im):
     g1 = gg.workload_graph("nethept_wc")
     g2 = gg.workload_graph("tiny_uic")
