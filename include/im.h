@@ -72,10 +72,9 @@ int im_workspace_destroy(im_workspace *ws);
  *     of a pass) are expanded through per-snapshot live lists instead of the
  *     snapshot masks; 0 disables the lists; otherwise >= 16. Default 1024.
  *   IM_OPT_COOP_GAIN: rounds whose seed gain (summed over snapshots) is at
- *     least this value run the forward search on a cooperative grid of all
- *     CUs; smaller rounds use one workgroup per snapshot word. 0: always
- *     cooperative. Default: never (the per-word kernel
- *     measured faster at every threshold on the million-node workload). */
+ *     least this value run the forward search on a cooperative grid (about
+ *     16 workgroups per snapshot word); smaller rounds use one workgroup per
+ *     word. Default 0 (always the cooperative grid). */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
@@ -100,7 +99,9 @@ typedef struct im_stats {
     uint64_t reached[3][3];    /* (task, reached node) pairs                      */
     uint64_t arcs_read[3][3];  /* (arc, word) reads issued, re-expansions included*/
     uint64_t handed_over[3][3];/* tasks passed on to the next tier                */
-    uint64_t reserved[20];
+    uint64_t fwd_levels;       /* levels of the forward searches (sum over words) */
+    uint64_t fwd_entries;      /* frontier entries expanded by them               */
+    uint64_t reserved[18];
 } im_stats;
 
 int im_stats_get(im_workspace *ws, im_stats *out);
@@ -114,7 +115,7 @@ enum {
     IM_PH_VALIDATE = 0, IM_PH_TRANSPOSE, IM_PH_MASK_GEN, IM_PH_MASK_GATHER,
     IM_PH_INIT_T0, IM_PH_INIT_T1, IM_PH_INIT_T2, IM_PH_ARGMAX, IM_PH_FORWARD,
     IM_PH_REV_T0, IM_PH_REV_T1, IM_PH_REV_T2, IM_PH_CLEAR, IM_PH_CALL, IM_PH_HUBS,
-    IM_PH_COUNT
+    IM_PH_PACK, IM_PH_COUNT
 };
 typedef struct im_profile {
     double   ms[16];
@@ -123,6 +124,11 @@ typedef struct im_profile {
 
 int im_profile_enable(im_workspace *ws, uint32_t mask);
 int im_profile_get(im_workspace *ws, im_profile *out);
+/* Host pointers: the individual launch durations (ms) of one phase as
+ * collected by the last im_profile_get; *count gets their number, at most
+ * `max` are written to ms_out. */
+int im_profile_launches(im_workspace *ws, int phase, float *ms_out, uint32_t max,
+                        uint32_t *count);
 
 /* Thread-local message describing the last error. */
 const char *im_last_error(void);

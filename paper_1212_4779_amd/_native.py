@@ -15,10 +15,11 @@ IM_R_MAX = 4096
 
 EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_last_error",
            "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select",
-           "im_profile_enable", "im_profile_get", "im_workspace_set")
+           "im_profile_enable", "im_profile_get", "im_workspace_set", "im_profile_launches")
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
-          "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs")
+          "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs",
+          "pack")
 IM_OPT_HUB_DEGREE = 1
 IM_OPT_COOP_GAIN = 2
 
@@ -37,10 +38,11 @@ TIER_FIELDS = ("relax", "reached", "arcs_read", "handed_over")
 class ImStats(ctypes.Structure):
     _fields_ = ([(f, ctypes.c_uint64) for f in STAT_FIELDS] +
                 [(f, (ctypes.c_uint64 * 3) * 3) for f in TIER_FIELDS] +
-                [("reserved", ctypes.c_uint64 * 20)])
+                [("fwd_levels", ctypes.c_uint64), ("fwd_entries", ctypes.c_uint64),
+                 ("reserved", ctypes.c_uint64 * 18)])
 
     def as_dict(self):
-        d = {f: int(getattr(self, f)) for f in STAT_FIELDS}
+        d = {f: int(getattr(self, f)) for f in STAT_FIELDS + ("fwd_levels", "fwd_entries")}
         for f in TIER_FIELDS:
             arr = getattr(self, f)
             for p, pn in enumerate(PASSES):
@@ -83,6 +85,7 @@ def lib():
         L.im_select.argtypes = [G, u32, u32, u64, p, p, p, p, p]
         L.im_profile_enable.argtypes = [p, u32]
         L.im_workspace_set.argtypes = [p, ctypes.c_int, ctypes.c_int64]
+        L.im_profile_launches.argtypes = [p, ctypes.c_int, p, u32, ctypes.POINTER(u32)]
         L.im_profile_get.argtypes = [p, ctypes.POINTER(ImProfile)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p

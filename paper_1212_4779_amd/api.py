@@ -102,6 +102,16 @@ class Workspace:
         N.check(N.lib().im_profile_get(self.handle, ctypes.byref(pr)))
         return {nm: (float(pr.ms[i]), int(pr.launches[i])) for i, nm in enumerate(N.PHASES)}
 
+    def launches(self, phase):
+        """Per-launch milliseconds of `phase` from the last profile() call."""
+        cnt = ctypes.c_uint32(0)
+        N.check(N.lib().im_profile_launches(self.handle, N.PHASES.index(phase), None, 0,
+                                            ctypes.byref(cnt)))
+        buf = (ctypes.c_float * max(1, cnt.value))()
+        N.check(N.lib().im_profile_launches(self.handle, N.PHASES.index(phase), buf, cnt.value,
+                                            ctypes.byref(cnt)))
+        return [float(buf[i]) for i in range(cnt.value)]
+
     def stats(self):
         st = N.ImStats()
         N.check(N.lib().im_stats_get(self.handle, ctypes.byref(st)))

@@ -389,9 +389,12 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
 // A4: argmax of (gain, lowest id) over unselected nodes
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint8_t *sel,
-                                                uint32_t n, unsigned long long *key)
+                                                uint32_t n, unsigned long long *key,
+                                                uint32_t *zero, uint32_t nzero)
 {
     __shared__ unsigned long long red[4];
+    // also clear this round's reverse-task packing counters
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < nzero; i += gridDim.x * 256u) zero[i] = 0;
     unsigned long long best = 0;
     for (uint32_t u = blockIdx.x * 256u + threadIdx.x; u < n; u += gridDim.x * 256u)
         if (!sel[u]) {
@@ -425,7 +428,9 @@ struct FwdArgs {
     uint64_t *fq0, *fq1;        // frontier entries (word << 32 | node), capacity W*n
     uint32_t *bq0, *bq1;        // per-word frontier queues of the one-workgroup kernel [W][n]
     uint64_t coop_gain;         // rounds whose seed gain reaches this use the cooperative kernel
-    uint32_t *cnt;              // [3] frontier counts (ring), [W] visit counts; zero on entry
+    uint32_t *cnt;              // [3] frontier counts (ring), [3] visit count, [4..4+W) per-word
+                                // visit counts; zero on entry
+    uint64_t *vis;              // visited (word << 32 | node), capacity W*n
     uint32_t *tnodes, *tcounts;
     const unsigned long long *key;
     uint32_t t;
@@ -445,33 +450,54 @@ struct FwdLds {
     uint32_t wsum[FWD_NT / 64 + 1];
     unsigned long long red[FWD_NT / 64];
     HubBatch<FWD_NT, 16> H;
+    uint32_t bcast;
+    uint32_t p0[256];   // level 0: prefix of the seed's per-(word, bit) list lengths
+    uint32_t o0[256];   // level 0: start of each (word, bit) list
 };
 
 __device__ __forceinline__ uint32_t coherent_load(uint32_t *p) { return atomicAdd(p, 0u); }
 
-// relax (w, v) with `bits` (may be 0); every lane must call it
+// one coherent read per workgroup, broadcast through LDS (all threads call)
+__device__ __forceinline__ uint32_t group_load(uint32_t *p, uint32_t *slot)
+{
+    if (threadIdx.x == 0) *slot = coherent_load(p);
+    __syncthreads();
+    const uint32_t v = *slot;
+    __syncthreads();
+    return v;
+}
+
+// One relaxation (w, v, bits) per lane and unrolled step; bits may be 0.
+// Returns whether (w, v) became visited and whether it joins the next frontier.
 __device__ __forceinline__ void fwd_relax(const FwdArgs &a, uint32_t w, uint32_t v, uint64_t bits,
-                                          uint64_t *nxt, uint32_t *ncnt)
+                                          bool &first, bool &push)
 {
     const uint64_t off = (uint64_t)w * a.n;
-    bool first = false, push = false;
+    first = false;
+    push = false;
     if (bits) bits &= ~a.covered[off + v];
-    if (bits) {
-        uint64_t old = atomicOr((unsigned long long *)&a.newly[off + v], (unsigned long long)bits);
-        uint64_t nb = bits & ~old;
-        if (nb) {
-            first = old == 0;
-            uint64_t op = atomicOr((unsigned long long *)&a.pend[off + v], (unsigned long long)nb);
-            push = op == 0;
-        }
-    }
-    // a node enters the visit list of its word once; the frontier once per level
-    for (uint32_t ww = 0; ww < a.W; ww++) {
-        uint32_t p = wave_append(first && w == ww, a.cnt + 3 + ww);
-        if (first && w == ww) a.tnodes[off + p] = v;
-    }
-    uint32_t q = wave_append(push, ncnt);
-    if (push) nxt[q] = ((uint64_t)w << 32) | v;
+    if (!bits) return;
+    uint64_t old = atomicOr((unsigned long long *)&a.newly[off + v], (unsigned long long)bits);
+    uint64_t nb = bits & ~old;
+    if (!nb) return;
+    first = old == 0;
+    uint64_t op = atomicOr((unsigned long long *)&a.pend[off + v], (unsigned long long)nb);
+    push = op == 0;
+}
+
+// Append up to U entries per lane with one atomic per wavefront: every lane
+// of the wavefront must call it with its count and entries.
+template <int U>
+__device__ __forceinline__ void wave_append_n(uint32_t cnt, const uint64_t *ent, uint32_t *counter,
+                                              uint64_t *list)
+{
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t tot = __shfl(incl, 63, 64);
+    if (tot == 0) return;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 63) base = atomicAdd(counter, tot);
+    base = __shfl(base, 63, 64) + incl - cnt;
+    for (uint32_t i = 0; i < cnt; i++) list[base + i] = ent[i];
 }
 
 __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
@@ -486,6 +512,9 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     if (key == 0) return;  // no unselected node (cannot happen for k <= n); uniform
     if ((key >> 32) < a.coop_gain) return;  // a small round: k_forward_block runs it
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+    // a hub seed (W <= 4) is expanded by the whole grid at level 0
+    const uint32_t hs0 = a.hub.slot[v];
+    const bool split0 = hs0 != IM_EMPTY && a.W <= 4;
     if (blockIdx.x == 0) {
         if (tid == 0) {
             a.seeds_out[a.t] = v;
@@ -498,21 +527,71 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 uint64_t start = im_valid_bits(a.R, w) & ~a.covered[off + v];
                 if (!start) continue;
                 a.newly[off + v] = start;
-                a.pend[off + v] = start;
-                a.fq0[nf] = ((uint64_t)w << 32) | v;
+                a.vis[nf] = ((uint64_t)w << 32) | v;
+                if (!split0) {
+                    a.pend[off + v] = start;
+                    a.fq0[nf] = ((uint64_t)w << 32) | v;
+                }
                 nf++;
-                a.tnodes[off] = v;
-                a.cnt[3 + w] = 1;
             }
-            a.cnt[0] = nf;
+            a.cnt[0] = split0 ? 0u : nf;
+            a.cnt[3] = nf;
         }
     } else if (tid == 0) {
         L.H.n = 0;
     }
-    grid.sync();
     uint64_t arcs = 0;
-    for (uint32_t lev = 0;; lev++) {
-        const uint32_t nf = coherent_load(&a.cnt[lev % 3]);
+    uint32_t lev0 = 0;
+    // the seed's visit entries and counts above must be in place before any
+    // workgroup appends to the same lists
+    grid.sync();
+    if (split0) {
+        // every workgroup builds the prefix over (word, bit) of the seed's
+        // live-list lengths restricted to its uncovered bits, then takes an
+        // interleaved share of the flattened (word, bit, head) range
+        const uint32_t w = tid / 64, b = tid % 64;
+        uint32_t c = 0, o = 0;
+        if (w < a.W) {
+            const uint64_t start = im_valid_bits(a.R, w) & ~a.covered[(uint64_t)w * a.n + v];
+            const uint32_t *ho = a.hub.off + ((uint64_t)hs0 * a.W + w) * 65;
+            o = ho[b];
+            c = ((start >> b) & 1ull) ? ho[b + 1] - o : 0u;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<FWD_NT>(c, L.wsum, &tot);
+        L.p0[tid] = ex;
+        L.o0[tid] = o;
+        __syncthreads();
+        uint32_t *ncnt = &a.cnt[1];
+        for (uint32_t j0 = blockIdx.x * FWD_NT * FWD_U; j0 < tot; j0 += gridDim.x * FWD_NT * FWD_U) {
+            uint64_t vis_e[FWD_U], nxt_e[FWD_U];
+            uint32_t nvis = 0, nnxt = 0;
+#pragma unroll
+            for (int u = 0; u < FWD_U; u++) {
+                const uint32_t j = j0 + (uint32_t)u * FWD_NT + tid;
+                uint32_t ww = 0, hv = 0;
+                uint64_t bits = 0;
+                if (j < tot) {
+                    const int k = upper_index<FWD_NT>(L.p0, j);
+                    ww = (uint32_t)k / 64;
+                    hv = a.hub.adj[L.o0[k] + (j - L.p0[k])];
+                    bits = 1ull << (k % 64);
+                }
+                bool first, push;
+                fwd_relax(a, ww, hv, bits, first, push);
+                const uint64_t ent = ((uint64_t)ww << 32) | hv;
+                if (first) vis_e[nvis++] = ent;
+                if (push) nxt_e[nnxt++] = ent;
+            }
+            wave_append_n<FWD_U>(nvis, vis_e, a.cnt + 3, a.vis);
+            wave_append_n<FWD_U>(nnxt, nxt_e, ncnt, a.fq1);
+        }
+        arcs += tot;
+        lev0 = 1;
+    }
+    grid.sync();
+    for (uint32_t lev = lev0;; lev++) {
+        const uint32_t nf = group_load(&a.cnt[lev % 3], &L.bcast);
         if (nf == 0) break;
         const uint64_t *cur = (lev & 1) ? a.fq1 : a.fq0;
         uint64_t *nxt = (lev & 1) ? a.fq0 : a.fq1;
@@ -562,41 +641,79 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                         bb[u] = a.mask[(uint64_t)L.wd[kk[u]] * a.m + ee[u]];
                         vv[u] = a.col[ee[u]];
                     }
+                uint64_t vis_e[FWD_U], nxt_e[FWD_U];
+                uint32_t nvis = 0, nnxt = 0;
 #pragma unroll
                 for (int u = 0; u < FWD_U; u++) {
                     uint32_t ww = kk[u] != 0xFFFFFFFFu ? L.wd[kk[u]] : 0u;
                     uint64_t bits = kk[u] != 0xFFFFFFFFu ? (bb[u] & L.del[kk[u]]) : 0ull;
-                    fwd_relax(a, ww, vv[u], bits, nxt, ncnt);
+                    bool first, push;
+                    fwd_relax(a, ww, vv[u], bits, first, push);
+                    const uint64_t ent = ((uint64_t)ww << 32) | vv[u];
+                    if (first) vis_e[nvis++] = ent;
+                    if (push) nxt_e[nnxt++] = ent;
                 }
+                wave_append_n<FWD_U>(nvis, vis_e, a.cnt + 3, a.vis);
+                wave_append_n<FWD_U>(nnxt, nxt_e, ncnt, nxt);
             }
             __syncthreads();
             if (nhub) {
                 auto word_of = [&](uint32_t own) { return own; };
+                uint64_t vis_e[FWD_U], nxt_e[FWD_U];
+                uint32_t nvis = 0, nnxt = 0;
                 auto relax = [&](uint32_t own, uint32_t hv, uint64_t bits) {
-                    fwd_relax(a, own, hv, bits, nxt, ncnt);
+                    bool first, push;
+                    fwd_relax(a, own, hv, bits, first, push);
+                    const uint64_t ent = ((uint64_t)own << 32) | hv;
+                    if (first) vis_e[nvis++] = ent;
+                    if (push) nxt_e[nnxt++] = ent;
                 };
-                expand_hubs<FWD_NT, 16, FWD_U>(L.H, nhub, a.hub, a.W, word_of, relax, arcs);
+                auto flush = [&]() {
+                    wave_append_n<FWD_U>(nvis, vis_e, a.cnt + 3, a.vis);
+                    wave_append_n<FWD_U>(nnxt, nxt_e, ncnt, nxt);
+                    nvis = 0;
+                    nnxt = 0;
+                };
+                expand_hubs<FWD_NT, 16, FWD_U>(L.H, nhub, a.hub, a.W, word_of, relax, flush, arcs);
             }
         }
         grid.sync();
     }
-    // covered |= newly for every visited node; statistics
+    // covered |= newly for every visited (word, node); per-word visit lists
+    // (the reverse tasks) are built from the unified list, one atomic per
+    // (workgroup, word) and chunk
     uint64_t relax = 0, trav = 0;
-    for (uint32_t w = 0; w < a.W; w++) {
-        const uint64_t off = (uint64_t)w * a.n;
-        const uint32_t nv = coherent_load(&a.cnt[3 + w]);
-        for (uint64_t i = gtid; i < nv; i += gsize) {
-            uint32_t x = a.tnodes[off + i];
+    const uint32_t nv = group_load(&a.cnt[3], &L.bcast);
+    uint32_t *wcnt = L.scan;  // reused: per-word counts of this chunk (W <= 64)
+    uint32_t *wbase = L.rs;
+    for (uint32_t base = blockIdx.x * FWD_NT; base < nv; base += gridDim.x * FWD_NT) {
+        if (tid < 64) wcnt[tid] = 0;
+        __syncthreads();
+        const uint32_t i = base + tid;
+        uint32_t w = 0, x = 0, r = 0;
+        if (i < nv) {
+            uint64_t e = a.vis[i];
+            w = (uint32_t)(e >> 32);
+            x = (uint32_t)e;
+            const uint64_t off = (uint64_t)w * a.n;
             uint64_t b = a.newly[off + x];
             a.covered[off + x] |= b;
             uint32_t dg = a.row[x + 1] - a.row[x];
             relax += dg;
             trav += (uint64_t)__popcll(b) * dg;
+            r = atomicAdd(&wcnt[w], 1u);
         }
-        if (gtid == 0) {
-            a.tcounts[w] = nv;
-            atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)nv);
-        }
+        __syncthreads();
+        if (tid < 64 && tid < (int)a.W && wcnt[tid]) wbase[tid] = atomicAdd(&a.cnt[4 + tid], wcnt[tid]);
+        __syncthreads();
+        if (i < nv) a.tnodes[(uint64_t)w * a.n + wbase[w] + r] = x;
+        __syncthreads();
+    }
+    grid.sync();
+    if (gtid < a.W) {
+        const uint32_t c = coherent_load(&a.cnt[4 + gtid]);
+        a.tcounts[gtid] = c;
+        atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)c);
     }
     relax = group_sum<FWD_NT>(relax, L.red);
     trav = group_sum<FWD_NT>(trav, L.red);
@@ -631,7 +748,7 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
         return;
     }
     uint64_t arcs = 0;
-    block_bfs_run<FWB_NT, 8, true>(L, v, start, a.row, a.col, a.mask + (uint64_t)w * a.m, a.hub,
+    block_bfs_run<FWB_NT, 8, true>(L, v, tid == 0 ? start : 0ull, a.row, a.col, a.mask + (uint64_t)w * a.m, a.hub,
                                    a.W, w, a.covered + off, a.newly + off, a.pend + off, nullptr,
                                    a.bq0 + off, a.bq1 + off, a.tnodes + off, arcs);
     const uint32_t nvis = L.nvis;
@@ -648,9 +765,93 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
     trav = group_sum<FWB_NT>(trav, L.red);
     if (tid == 0) {
         a.tcounts[w] = nvis;
+        atomicAdd(&a.stats[ST_FWD_LEVELS], (unsigned long long)L.levels);
+        atomicAdd(&a.stats[ST_FWD_ENTRIES], (unsigned long long)L.entries);
         atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)nvis);
         atomicAdd(&a.stats[ST_RELAX_FWD], (unsigned long long)relax);
         atomicAdd(&a.stats[ST_TRAV_FWD], (unsigned long long)trav);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse-task packing. Decrements from sources whose start bits are disjoint
+// can share one reverse search: a node's bit r can then only come from the
+// one source that owns r, so popcount(bits) at that node is the sum of the
+// per-source decrements. Sources newly covered in a single snapshot of the
+// word are sorted by that snapshot's bit; group g takes the g-th source of
+// every bit. Sources covered in several snapshots stay separate tasks.
+// ---------------------------------------------------------------------------
+constexpr int PK_NT = 256;
+constexpr int PK_ZERO = 64 * 64 * 2 + 128;  // bcnt, bcur [W][64]; gcnt, mcnt [64]
+
+__global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, const uint32_t *tcounts,
+                                                      const uint64_t *newly, uint32_t n,
+                                                      uint32_t *bcnt, uint32_t *mcnt, uint32_t *mlist)
+{
+    __shared__ uint32_t cnt[64];
+    const uint32_t w = blockIdx.y;
+    const uint64_t off = (uint64_t)w * n;
+    const uint32_t c = tcounts[w];
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t base = blockIdx.x * PK_NT; base < c; base += gridDim.x * PK_NT) {
+        const uint32_t i = base + threadIdx.x;
+        bool multi = false;
+        uint32_t x = 0;
+        if (i < c) {
+            x = tnodes[off + i];
+            const uint64_t b = newly[off + x];
+            if (__popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
+            else multi = true;
+        }
+        const uint32_t p = wave_append(multi, &mcnt[w]);
+        if (multi) mlist[off + p] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && cnt[threadIdx.x]) atomicAdd(&bcnt[w * 64 + threadIdx.x], cnt[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(64) void k_pack_scan(const uint32_t *bcnt, uint32_t *boff, uint32_t *gcnt)
+{
+    const uint32_t w = blockIdx.x, lane = threadIdx.x;
+    const uint32_t c = bcnt[w * 64 + lane];
+    const uint32_t incl = wave_incl_scan(c);
+    boff[w * 64 + lane] = incl - c;
+    uint32_t mx = c;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+    if (lane == 0) gcnt[w] = mx;
+}
+
+__global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, const uint32_t *tcounts,
+                                                     const uint64_t *newly, uint32_t n,
+                                                     const uint32_t *boff, uint32_t *bcur,
+                                                     uint32_t *plist)
+{
+    __shared__ uint32_t cnt[64], base0[64];
+    const uint32_t w = blockIdx.y;
+    const uint64_t off = (uint64_t)w * n;
+    const uint32_t c = tcounts[w];
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * PK_NT + threadIdx.x; i < c; i += gridDim.x * PK_NT) {
+        const uint64_t b = newly[off + tnodes[off + i]];
+        if (__popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t k = cnt[threadIdx.x];
+        base0[threadIdx.x] = k ? atomicAdd(&bcur[w * 64 + threadIdx.x], k) : 0u;
+        cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * PK_NT + threadIdx.x; i < c; i += gridDim.x * PK_NT) {
+        const uint32_t x = tnodes[off + i];
+        const uint64_t b = newly[off + x];
+        if (__popcll(b) != 1) continue;
+        const uint32_t r = __ffsll((unsigned long long)b) - 1;
+        const uint32_t pos = boff[w * 64 + r] + base0[r] + atomicAdd(&cnt[r], 1u);
+        plist[off + pos] = x;
     }
 }
 
@@ -688,7 +889,7 @@ constexpr int T2_NT = 256, T2_U = 8;
 // per-phase device counters: grab0, n1, grab1, n2, grab2
 constexpr int PH_CTRS = 8;
 // per-round forward counters: 3 frontier counts + one visit count per word
-constexpr int FWD_CTRS = 3 + 64;
+constexpr int FWD_CTRS = 4 + 64;
 
 // ---------------------------------------------------------------------------
 // workspace
@@ -706,11 +907,14 @@ struct im_workspace {
     uint32_t *gain = nullptr;
     uint8_t *sel = nullptr;
     uint64_t *covered = nullptr, *newly = nullptr, *fpend = nullptr, *ffdel = nullptr;
-    uint64_t *fqa = nullptr, *fqb = nullptr;
+    uint64_t *fqa = nullptr, *fqb = nullptr, *fvis = nullptr;
     uint32_t *bqa = nullptr, *bqb = nullptr;
-    uint64_t coop_gain = ~0ull;  // cooperative forward search off by default
+    uint64_t coop_gain = 0;  // every round uses the cooperative forward search
     uint32_t *tnodes = nullptr, *tcounts = nullptr;
     uint32_t *fctr = nullptr;  // [k][FWD_CTRS] forward-search counters
+    uint32_t *pk = nullptr;    // packing counters: bcnt, bcur [64][64], gcnt, mcnt [64]
+    uint32_t *boff = nullptr;  // [64][64]
+    uint32_t *plist = nullptr, *mlist = nullptr;  // [W][n]
     unsigned fwd_grid = 0;
     unsigned long long *keys = nullptr;
     uint32_t *ovf_q = nullptr, *ovf_q2 = nullptr;
@@ -735,6 +939,7 @@ struct im_workspace {
     uint32_t prof_mask = 0;
     std::vector<hipEvent_t> ev[IM_PH_COUNT];
     size_t ev_used[IM_PH_COUNT] = {};
+    std::vector<float> last_ms[IM_PH_COUNT];  // per-launch durations of the last get
     int open_phase = -1;
 };
 
@@ -800,7 +1005,8 @@ extern "C" int im_workspace_create(im_workspace **out)
         int b = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_forward_coop, FWD_NT, 0));
         if (b < 1) b = 1;
-        ws->fwd_grid = (unsigned)ws->num_cu;  // one workgroup per CU: cheaper grid barriers
+        // 16 workgroups per snapshot word at most: grid barriers stay cheap
+        ws->fwd_grid = std::min<unsigned>((unsigned)b * (unsigned)ws->num_cu, 16u * 64u);
     }
     int rc;
     if ((rc = dalloc(&ws->stats, ST_COUNT))) { delete ws; return rc; }
@@ -820,7 +1026,8 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->row32); dfree(ws->in_row); dfree(ws->in_col); dfree(ws->in2out);
     dfree(ws->cnt); dfree(ws->scan_sums); dfree(ws->mask_out); dfree(ws->mask_in);
     dfree(ws->gain); dfree(ws->sel); dfree(ws->covered); dfree(ws->newly);
-    dfree(ws->fpend); dfree(ws->ffdel); dfree(ws->fqa); dfree(ws->fqb); dfree(ws->bqa); dfree(ws->bqb); dfree(ws->fctr);
+    dfree(ws->fpend); dfree(ws->ffdel); dfree(ws->fqa); dfree(ws->fqb); dfree(ws->fvis); dfree(ws->bqa); dfree(ws->bqb); dfree(ws->fctr);
+    dfree(ws->pk); dfree(ws->boff); dfree(ws->plist); dfree(ws->mlist);
     dfree(ws->tnodes); dfree(ws->tcounts); dfree(ws->keys); dfree(ws->ovf_q); dfree(ws->ovf_q2); dfree(ws->ctrs);
     dfree(ws->b_reach); dfree(ws->b_pend); dfree(ws->b_fdel);
     dfree(ws->b_qa); dfree(ws->b_qb); dfree(ws->b_vis);
@@ -863,8 +1070,10 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
             (rc = dalloc(&ws->gain, cn)) || (rc = dalloc(&ws->sel, cn)) ||
             (rc = dalloc(&ws->covered, nW)) || (rc = dalloc(&ws->newly, nW)) ||
             (rc = dalloc(&ws->fpend, nW)) || (rc = dalloc(&ws->ffdel, nW)) ||
-            (rc = dalloc(&ws->fqa, nW)) || (rc = dalloc(&ws->fqb, nW)) ||
+            (rc = dalloc(&ws->fqa, nW)) || (rc = dalloc(&ws->fqb, nW)) || (rc = dalloc(&ws->fvis, nW)) ||
             (rc = dalloc(&ws->bqa, nW)) || (rc = dalloc(&ws->bqb, nW)) ||
+            (rc = dalloc(&ws->plist, nW)) || (rc = dalloc(&ws->mlist, nW)) ||
+            (rc = dalloc(&ws->pk, PK_ZERO)) || (rc = dalloc(&ws->boff, 64 * 64)) ||
             (rc = dalloc(&ws->tnodes, nW)) || (rc = dalloc(&ws->tcounts, 64)) ||
             (rc = dalloc(&ws->ovf_q, nW)) || (rc = dalloc(&ws->ovf_q2, nW)))
             return rc;
@@ -1095,7 +1304,8 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     uint32_t n = g->n, W = (R + 63) / 64;
     {
         PhaseTimer pt(ws, IM_PH_ARGMAX, s);
-        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys + t);
+        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys + t, ws->pk,
+                                                         (uint32_t)PK_ZERO);
     }
 
     FwdArgs f;
@@ -1104,7 +1314,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     f.n = n; f.R = R; f.W = W;
     f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend; f.fdel = ws->ffdel;
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
-    f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain;
+    f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
     f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
     f.key = ws->keys; f.t = t; f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
     f.stats = ws->stats;
@@ -1112,14 +1322,26 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
         k_forward_block<<<W, FWB_NT, 0, s>>>(f);
         void *args[] = {&f};
-        hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(ws->fwd_grid),
+        const unsigned fg = std::min<unsigned>(ws->fwd_grid, 16u * W);
+        hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
                                                   dim3(FWD_NT), args, 0, s);
         if (e != hipSuccess)
             return fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
     }
 
+    uint32_t *bcnt = ws->pk, *bcur = ws->pk + 64 * 64, *gcnt = ws->pk + 2 * 64 * 64,
+             *mcnt = gcnt + 64;
+    {
+        PhaseTimer pt(ws, IM_PH_PACK, s);
+        dim3 pg(grid_for(n, PK_NT, 64), W);
+        k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist);
+        k_pack_scan<<<W, 64, 0, s>>>(bcnt, ws->boff, gcnt);
+        k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, ws->boff, bcur,
+                                         ws->plist);
+    }
     BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W);
-    a.tnodes = ws->tnodes; a.tcounts = ws->tcounts; a.tbits = ws->newly;
+    a.gcnt = gcnt; a.mcnt = mcnt; a.bcnt = bcnt; a.boff = ws->boff;
+    a.plist = ws->plist; a.mlist = ws->mlist; a.tbits = ws->newly;
     a.hub = hub_lists(ws, 1);
     a.pass = PASS_REV;
     a.st_trav = ST_TRAV_REV;
@@ -1190,6 +1412,8 @@ extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
     out->tasks_rev = h[ST_TASKS_REV];
     out->decrements = h[ST_DECREMENTS];
     out->celf_evals = h[ST_CELF_EVALS];
+    out->fwd_levels = h[ST_FWD_LEVELS];
+    out->fwd_entries = h[ST_FWD_ENTRIES];
     for (int p = 0; p < 3; p++)
         for (int t = 0; t < 3; t++) {
             out->relax[p][t] = h[st_tier(p, t, F_RELAX)];
@@ -1294,10 +1518,12 @@ extern "C" int im_profile_get(im_workspace *ws, im_profile *out)
     for (int p = 0; p < IM_PH_COUNT; p++) {
         size_t u = ws->ev_used[p] & ~(size_t)1;
         double tot = 0;
+        ws->last_ms[p].clear();
         for (size_t i = 0; i < u; i += 2) {
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, ws->ev[p][i], ws->ev[p][i + 1]));
             tot += ms;
+            ws->last_ms[p].push_back(ms);
         }
         out->ms[p] = tot;
         out->launches[p] = u / 2;
@@ -1322,4 +1548,14 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
     default:
         return fail(IM_EINVAL, "unknown option %d", option);
     }
+}
+
+extern "C" int im_profile_launches(im_workspace *ws, int phase, float *ms_out, uint32_t max,
+                                   uint32_t *count)
+{
+    if (!ws || !count || phase < 0 || phase >= IM_PH_COUNT) return fail(IM_EINVAL, "bad argument");
+    const std::vector<float> &v = ws->last_ms[phase];
+    *count = (uint32_t)v.size();
+    for (uint32_t i = 0; i < max && i < v.size(); i++) ms_out[i] = v[i];
+    return IM_OK;
 }

@@ -31,6 +31,7 @@ enum {
     ST_TRAV_INIT = 0, ST_TRAV_FWD, ST_TRAV_REV, ST_TRAV_EVAL,
     ST_RELAX_FWD, ST_TASKS_REV, ST_DECREMENTS, ST_CELF_EVALS,
     ST_TIER_BASE = 8,   // + pass*12 + tier*4 + field
+    ST_FWD_LEVELS = 44, ST_FWD_ENTRIES = 45, ST_REV_TASKS_RUN = 46,
     ST_COUNT = 64
 };
 enum { PASS_INIT = 0, PASS_REV = 1, PASS_EVAL = 2 };
@@ -63,13 +64,19 @@ struct BfsArgs {
     uint32_t *gain;           // [n]
     // task ids: MODE_COUNT: t in [0, n*W) -> word t/n, node t%n (or, when
     // cand != nullptr, t in [0, ncand*W) -> word t/ncand, node cand[t%ncand]);
-    // MODE_DEC: t indexes the per-word node lists tnodes[w][0..tcounts[w])
+    // one source with all of the word's bits (minus pruned ones).
+    // MODE_DEC, per word w: first gcnt[w] groups of single-snapshot sources
+    // (the sources whose only bit is b are plist[w*n + boff[w*64+b] + i],
+    // i < bcnt[w*64+b]; group g takes the g-th source of every bit, each with
+    // its own bit, so the group's start bits are disjoint), then mcnt[w]
+    // multi-snapshot sources mlist[w*n + i] with bits tbits[w*n + node].
     uint32_t ntasks;
     const uint32_t *cand;
     uint32_t ncand;
-    const uint32_t *tnodes;   // [W][n]
-    const uint32_t *tcounts;  // [W]
-    const uint64_t *tbits;    // start bits [W][n]
+    const uint32_t *gcnt, *mcnt;    // [W]
+    const uint32_t *bcnt, *boff;    // [W][64]
+    const uint32_t *plist, *mlist;  // [W][n]
+    const uint64_t *tbits;          // [W][n]
     // this tier's input queue (nullptr: all task ids) and output queue
     const uint32_t *in_q;
     const uint32_t *in_n;
@@ -84,12 +91,14 @@ struct BfsArgs {
     int st_trav;
 };
 
-// Decode a task id into (start node, word, start bits). Returns false when
-// the task has nothing to propagate.
-__device__ __forceinline__ bool decode_task(const BfsArgs &a, int mode, uint32_t t,
-                                            const uint32_t *wpre, uint32_t &src,
-                                            uint32_t &w, uint64_t &bits)
+// Source `lane` (0..63) of task t: sets the task's word w (every lane) and,
+// when the lane has a source, its node and start bits (bits = 0 otherwise).
+__device__ __forceinline__ void task_source(const BfsArgs &a, int mode, uint32_t t,
+                                            const uint32_t *wpre, uint32_t lane, uint32_t &w,
+                                            uint32_t &src, uint64_t &bits)
 {
+    bits = 0;
+    src = 0;
     if (mode == MODE_COUNT) {
         if (a.cand) {
             w = t / a.ncand;
@@ -98,21 +107,33 @@ __device__ __forceinline__ bool decode_task(const BfsArgs &a, int mode, uint32_t
             w = t / a.n;
             src = t - w * a.n;
         }
-        bits = im_valid_bits(a.R, w);
-        if (a.prune) bits &= ~a.prune[(uint64_t)w * a.n + src];
-    } else {
-        w = 0;
-        while (w + 1 < a.W && wpre[w + 1] <= t) w++;
-        src = a.tnodes[(uint64_t)w * a.n + (t - wpre[w])];
+        if (lane == 0) {
+            bits = im_valid_bits(a.R, w);
+            if (a.prune) bits &= ~a.prune[(uint64_t)w * a.n + src];
+        }
+        return;
+    }
+    w = 0;
+    while (w + 1 < a.W && wpre[w + 1] <= t) w++;
+    const uint32_t tl = t - wpre[w];
+    const uint32_t g = a.gcnt[w];
+    if (tl < g) {
+        const uint32_t c = a.bcnt[w * 64 + lane];
+        if (tl < c) {
+            src = a.plist[(uint64_t)w * a.n + a.boff[w * 64 + lane] + tl];
+            bits = 1ull << lane;
+        }
+    } else if (lane == 0) {
+        src = a.mlist[(uint64_t)w * a.n + (tl - g)];
         bits = a.tbits[(uint64_t)w * a.n + src];
     }
-    return bits != 0;
 }
 
+// exclusive prefix over words of the task counts (MODE_DEC)
 __device__ __forceinline__ void fill_wpre(const BfsArgs &a, uint32_t *wpre)
 {
     uint32_t s = 0;
-    for (uint32_t w = 0; w < a.W; w++) { wpre[w] = s; s += a.tcounts[w]; }
+    for (uint32_t w = 0; w < a.W; w++) { wpre[w] = s; s += a.gcnt[w] + a.mcnt[w]; }
     wpre[a.W] = s;
 }
 
@@ -172,10 +193,12 @@ __device__ __forceinline__ void hub_push(HubBatch<NT, HB> &H, uint32_t hs, uint3
 
 // word_of(own) -> snapshot word of an item; relax(own, v, bits) applies one relaxation
 // nh: number of collected items, read by every thread between the barrier that
-// follows their collection and the next collection
-template <int NT, int HB, int U, typename WordOf, typename Relax>
+// follows their collection and the next collection. relax(own, v, bits) is
+// called by every lane for every unrolled step (bits may be 0), flush() once
+// per unrolled group of steps.
+template <int NT, int HB, int U, typename WordOf, typename Relax, typename Flush>
 __device__ void expand_hubs(HubBatch<NT, HB> &H, uint32_t nh, const HubLists &hub, uint32_t W,
-                            WordOf word_of, Relax relax, uint64_t &arcs)
+                            WordOf word_of, Relax relax, Flush flush, uint64_t &arcs)
 {
     static_assert((HB & (HB - 1)) == 0, "HB must be a power of two");
     constexpr int NWAVE = NT / 64;
@@ -223,6 +246,7 @@ __device__ void expand_hubs(HubBatch<NT, HB> &H, uint32_t nh, const HubLists &hu
             }
 #pragma unroll
             for (int u = 0; u < U; u++) relax(H.own[qq[u]], vv[u], bb[u]);
+            flush();
         }
         __syncthreads();
     }
@@ -253,10 +277,11 @@ struct LdsState {
 };
 
 // insert v into slot s's table (if absent) and OR in `bits`; push the entry
-// onto the next frontier when its pending bits become non-zero
+// onto frontier list `lst` when its pending bits become non-zero (the next
+// frontier during expansion, the current one while seeding a task)
 template <int NT, int T, int CS, int LIM>
 __device__ __forceinline__ void lds_relax(LdsState<NT, T, CS> &L, uint32_t s, uint32_t v,
-                                          uint64_t bits, int nxt)
+                                          uint64_t bits, int nxt, bool seeding = false)
 {
     constexpr int LOG_CS = __builtin_ctz(CS);
     if (L.s_ovf[s]) return;  // abandoned: stop touching its full table
@@ -284,9 +309,13 @@ __device__ __forceinline__ void lds_relax(LdsState<NT, T, CS> &L, uint32_t s, ui
     if (nb) {
         uint64_t op = atomicOr((unsigned long long *)&L.pend[found], (unsigned long long)nb);
         if (op == 0) {
-            uint32_t q = atomicAdd(&L.nn, 1u);
-            L.fr[nxt][q] = (uint32_t)found;
-            atomicAdd(&L.s_next[s], 1u);
+            if (seeding) {
+                L.fr[nxt][atomicAdd(&L.nf, 1u)] = (uint32_t)found;
+            } else {
+                uint32_t q = atomicAdd(&L.nn, 1u);
+                L.fr[nxt][q] = (uint32_t)found;
+                atomicAdd(&L.s_next[s], 1u);
+            }
         }
     }
 }
@@ -350,22 +379,23 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                     L.tend = min(b + CHUNK, L.ntasks);
                 }
                 L.s_new[s] = L.tnext++;
+                L.s_cnt[s] = 0;
+                L.s_ovf[s] = 0;
             }
         }
         __syncthreads();
-        if (tid < T && L.s_new[tid] != NONE) {
-            const int s = tid;
-            uint32_t t = a.in_q ? a.in_q[L.s_new[s]] : L.s_new[s];
-            uint32_t src, w;
-            uint64_t bits;
-            if (decode_task(a, MODE, t, L.wpre, src, w, bits)) {
-                uint32_t idx = s * CS + (slot_hash(src) >> (32 - LOG_CS));
-                L.keys[idx] = src;
-                L.reach[idx] = bits;
-                L.pend[idx] = bits;
-                L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w;
-                L.s_cnt[s] = 1; L.s_ovf[s] = 0; L.s_act[s] = 1;
-                L.fr[cur][atomicAdd(&L.nf, 1u)] = idx;
+        // ---- seed the new tasks: lane l of the first wavefront inserts source l
+        for (int s = 0; s < T; s++) {
+            if (L.s_new[s] == NONE) continue;
+            if (tid < 64) {
+                const uint32_t t = a.in_q ? a.in_q[L.s_new[s]] : L.s_new[s];
+                uint32_t w, src;
+                uint64_t bits;
+                task_source(a, MODE, t, L.wpre, (uint32_t)tid, w, src, bits);
+                if (tid == 0) {
+                    L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w; L.s_act[s] = 1;
+                }
+                if (bits) lds_relax<NT, T, CS, LIM>(L, s, src, bits, cur, true);
             }
         }
         __syncthreads();
@@ -463,7 +493,8 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                     if (PRUNE) bits &= ~a.prune[(uint64_t)L.s_word[s] * a.n + v];
                     if (bits) lds_relax<NT, T, CS, LIM>(L, s, v, bits, cur ^ 1);
                 };
-                expand_hubs<NT, (NT == 64 ? 2 : 16), U>(L.H, nhub, a.hub, a.W, word_of, relax, st_arcs);
+                expand_hubs<NT, (NT == 64 ? 2 : 16), U>(L.H, nhub, a.hub, a.W, word_of, relax, [] {},
+                                                         st_arcs);
             }
         }
 
@@ -557,7 +588,7 @@ struct BlockLds {
     uint32_t rs[NT];
     uint64_t del[NT];
     uint32_t wsum[NT / 64 + 1];
-    uint32_t nf, nn, nvis, task;
+    uint32_t nf, nn, nvis, task, levels, entries;
     unsigned long long red[NT / 64];
     HubBatch<NT, 16> H;
 };
@@ -575,7 +606,8 @@ __device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, ui
 }
 
 // Run one task to its fixpoint; afterwards vis[0..L.nvis) lists every node
-// with reach != 0.
+// with reach != 0. Each thread passes its own seed (src, start); start = 0
+// means none. All threads of the workgroup must call it.
 template <int NT, int U, bool PRUNE>
 __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                               const uint32_t *row, const uint32_t *col, const uint64_t *mask,
@@ -586,13 +618,10 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
 {
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        reach[src] = start;
-        pend[src] = start;
-        qa[0] = src;
-        vis[0] = src;
-        L.nf = 1; L.nn = 0; L.nvis = 1; L.H.n = 0;
-    }
+    if (tid == 0) { L.nf = 0; L.nn = 0; L.nvis = 0; L.H.n = 0; L.levels = 0; L.entries = 0; }
+    __syncthreads();
+    // seeds: every lane with start bits (lanes 0..63 for multi-source tasks)
+    if (start) global_relax(reach, pend, vis, qa, &L.nvis, &L.nf, src, start);
     __syncthreads();
     uint32_t *cur = qa, *nxt = qb;
     for (;;) {
@@ -662,10 +691,10 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                     if (PRUNE) bits &= ~prune[v];
                     if (bits) global_relax(reach, pend, vis, nxt, &L.nvis, &L.nn, v, bits);
                 };
-                expand_hubs<NT, 16, U>(L.H, nhub, hub, W, word_of, relax, arcs);
+                expand_hubs<NT, 16, U>(L.H, nhub, hub, W, word_of, relax, [] {}, arcs);
             }
         }
-        if (tid == 0) { L.nf = L.nn; L.nn = 0; }
+        if (tid == 0) { L.levels++; L.entries += nf; L.nf = L.nn; L.nn = 0; }
         uint32_t *t = cur; cur = nxt; nxt = t;
         __syncthreads();
     }
@@ -694,9 +723,18 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         const uint32_t q = L.task;
         __syncthreads();
         if (q >= nq) break;
-        uint32_t src, w;
-        uint64_t bits;
-        if (!decode_task(a, MODE, a.in_q[q], wpre, src, w, bits)) continue;
+        uint32_t src = 0, w = 0;
+        uint64_t bits = 0;
+        {
+            uint32_t ww, ss;
+            uint64_t bb;
+            task_source(a, MODE, a.in_q[q], wpre, (uint32_t)(tid & 63), ww, ss, bb);
+            w = ww;
+            if (tid < 64) { src = ss; bits = bb; }
+            if (tid == 0) L.task = ss;  // COUNT tasks have one source, on lane 0
+        }
+        __syncthreads();
+        const uint32_t src0 = L.task;
         const uint64_t *mask = a.mask + (uint64_t)w * a.m;
         const uint64_t *prune = PRUNE ? a.prune + (uint64_t)w * a.n : nullptr;
         block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.W, w, prune, reach,
@@ -716,7 +754,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         }
         if (MODE == MODE_COUNT) {
             cnt = group_sum<NT>(cnt, L.red);
-            if (tid == 0) atomicAdd(&a.gain[src], (uint32_t)cnt);
+            if (tid == 0) atomicAdd(&a.gain[src0], (uint32_t)cnt);
         }
         __syncthreads();
     }

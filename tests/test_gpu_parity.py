@@ -138,7 +138,8 @@ def test_schedule_invariance_hub_lists(im, case):
             continue
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
         assert np.array_equal(got[2], ref[2])
-        for key in ("trav_init", "trav_fwd", "trav_rev", "decrements", "relax_init", "relax_rev"):
+        # relax_rev counts word-level work of packed task groups: schedule dependent
+        for key in ("trav_init", "trav_fwd", "trav_rev", "decrements", "relax_init"):
             assert got[3][key] == ref[3][key], (deg, key)
 
 
