@@ -165,6 +165,20 @@ def main():
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "avg_launch_ms": round(avg_launch_ms, 4)}
 
+    # the same selection captured into one HIP graph (device-resident round loop)
+    plan = im.Plan(dg, R, k, seed)
+    plan.launch()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.launch()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    graph_same = (plan.seeds.cpu().tolist() == seeds.cpu().tolist() and
+                  plan.gains.cpu().tolist() == gains.cpu().tolist())
+    plan.close()
+
     gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
     parity = None
     if os.path.exists(gold_path):
@@ -188,6 +202,8 @@ def main():
                    "p": w["p"] if w["p"] is not None else "weighted cascade",
                    "gamma": w["gamma"], "directed": w["directed"], "path": "dynamic update"},
         "selection_ms": ms_per_step,
+        "graph_replay_ms": graph_ms,
+        "graph_replay_same_output": graph_same,
         "traversals_per_step": trav,
         "phase_ms": {p: round(prof[p][0], 4) for p in prof},
         "counters": st,

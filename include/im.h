@@ -164,6 +164,21 @@ int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
               uint32_t *seeds_out, uint64_t *gains_out, uint32_t *trace_out,
               im_workspace *ws, void *stream);
 
+/* Plans (device-resident round loop). im_plan_create validates the graph
+ * (synchronous), then captures the complete selection -- reverse CSR, masks,
+ * hub lists, initial gains and all k rounds -- into one HIP graph bound to a
+ * private workspace and to the given device pointers (graph arrays, seeds_out,
+ * gains_out). im_plan_launch enqueues one replay on `stream`: every replay
+ * recomputes everything from the graph arrays as they are at that time (they
+ * must keep their shape; their contents may change). Replays of one plan must
+ * not overlap. */
+typedef struct im_plan im_plan;
+int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                   uint32_t *seeds_out, uint64_t *gains_out, void *stream, im_plan **plan);
+int im_plan_launch(im_plan *plan, void *stream);
+int im_plan_stats(im_plan *plan, im_stats *out);   /* synchronous; last replay */
+int im_plan_destroy(im_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

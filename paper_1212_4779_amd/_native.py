@@ -15,7 +15,8 @@ IM_R_MAX = 4096
 
 EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_last_error",
            "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select",
-           "im_profile_enable", "im_profile_get", "im_workspace_set", "im_profile_launches")
+           "im_profile_enable", "im_profile_get", "im_workspace_set", "im_profile_launches",
+           "im_plan_create", "im_plan_launch", "im_plan_stats", "im_plan_destroy")
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
           "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs",
@@ -86,6 +87,10 @@ def lib():
         L.im_profile_enable.argtypes = [p, u32]
         L.im_workspace_set.argtypes = [p, ctypes.c_int, ctypes.c_int64]
         L.im_profile_launches.argtypes = [p, ctypes.c_int, p, u32, ctypes.POINTER(u32)]
+        L.im_plan_create.argtypes = [G, u32, u32, u64, p, p, p, ctypes.POINTER(p)]
+        L.im_plan_launch.argtypes = [p, p]
+        L.im_plan_stats.argtypes = [p, ctypes.POINTER(ImStats)]
+        L.im_plan_destroy.argtypes = [p]
         L.im_profile_get.argtypes = [p, ctypes.POINTER(ImProfile)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p

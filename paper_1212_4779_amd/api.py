@@ -185,3 +185,45 @@ def select(graph, R, k, seed, ws=None, trace=False):
                               _ptr(tr) if trace else ctypes.c_void_p(0), ws.handle,
                               _stream(dev)))
     return _u32(seeds), gains, (_u32(tr) if trace else None)
+
+
+class Plan:
+    """The whole selection captured into one HIP graph (device-resident loop).
+
+    Bound to `graph`'s device arrays and to its own output tensors; each
+    launch() recomputes the k seeds from the current contents of the arrays.
+    """
+
+    def __init__(self, graph, R, k, seed):
+        dev = graph.device
+        self.graph = graph
+        self.seeds_raw = torch.empty(k, dtype=torch.int32, device=dev)
+        self.gains = torch.empty(k, dtype=torch.int64, device=dev)
+        self._g = graph.c_struct()
+        h = ctypes.c_void_p()
+        N.check(N.lib().im_plan_create(ctypes.byref(self._g), R, k, seed, _ptr(self.seeds_raw),
+                                       _ptr(self.gains), _stream(dev), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        N.check(N.lib().im_plan_launch(self.handle, _stream(self.graph.device)))
+
+    @property
+    def seeds(self):
+        return _u32(self.seeds_raw)
+
+    def stats(self):
+        st = N.ImStats()
+        N.check(N.lib().im_plan_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            N.lib().im_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

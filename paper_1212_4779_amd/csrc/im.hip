@@ -1353,15 +1353,23 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     return IM_OK;
 }
 
-// everything up to (and including) the initial gains
-static int prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k, im_workspace *ws,
-                   hipStream_t s)
+// workspace growth and input validation (synchronous)
+static int check_and_reserve(const im_graph *g, uint32_t R, uint32_t k, im_workspace *ws,
+                             hipStream_t s)
 {
     int rc;
+    if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, k))) return rc;
+    return validate(g, ws, s, ws->row32);
+}
+
+// everything after validation up to (and including) the initial gains:
+// kernel launches only (no host synchronisation, no memset), so that the
+// sequence can be captured into a graph
+static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k,
+                           im_workspace *ws, hipStream_t s)
+{
     uint32_t n = g->n, W = (R + 63) / 64;
-    if ((rc = ws_reserve(ws, n, g->m, W, k))) return rc;
-    if ((rc = validate(g, ws, s, ws->row32))) return rc;
-    HIPCHK(hipMemsetAsync(ws->stats, 0, ST_COUNT * sizeof(unsigned long long), s));
+    fill<unsigned long long>(ws->stats, ST_COUNT, 0ull, s);
     fill<uint32_t>(ws->ctrs, (uint64_t)(k + 1) * PH_CTRS, 0u, s);
     fill<unsigned long long>(ws->keys, (uint64_t)k + 1, 0ull, s);
     fill<uint32_t>(ws->fctr, (uint64_t)(k ? k : 1) * FWD_CTRS, 0u, s);
@@ -1378,6 +1386,33 @@ static int prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k, im_
     initial_gains(g, R, ws, ws->ctrs, s);
     HIPCHK(hipGetLastError());
     ws->last_stream = s;
+    return IM_OK;
+}
+
+static int prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k, im_workspace *ws,
+                   hipStream_t s)
+{
+    int rc;
+    if ((rc = check_and_reserve(g, R, k, ws, s))) return rc;
+    return enqueue_prepare(g, R, seed, k, ws, s);
+}
+
+// the k greedy rounds (kernel launches only)
+static int enqueue_rounds(const im_graph *g, uint32_t R, uint32_t k, uint32_t *seeds_out,
+                          uint64_t *gains_out, uint32_t *trace_out, im_workspace *ws, hipStream_t s)
+{
+    int rc;
+    const uint32_t n = g->n;
+    for (uint32_t t = 0; t < k; t++) {
+        if (trace_out)
+            k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, trace_out + (uint64_t)t * n, n);
+        if ((rc = greedy_round(g, R, t, seeds_out, gains_out, ws,
+                               ws->ctrs + (uint64_t)(t + 1) * PH_CTRS, s)))
+            return rc;
+    }
+    if (trace_out && n)
+        k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, trace_out + (uint64_t)k * n, n);
+    HIPCHK(hipGetLastError());
     return IM_OK;
 }
 
@@ -1487,18 +1522,88 @@ extern "C" int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t see
     hipStream_t s = (hipStream_t)stream;
     PhaseTimer pt(ws, IM_PH_CALL, s);
     if ((rc = prepare(g, R, seed, k, ws, s))) return rc;
-    uint32_t n = g->n;
-    for (uint32_t t = 0; t < k; t++) {
-        if (trace_out)
-            k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, trace_out + (uint64_t)t * n, n);
-        if ((rc = greedy_round(g, R, t, seeds_out, gains_out, ws,
-                               ws->ctrs + (uint64_t)(t + 1) * PH_CTRS, s)))
-            return rc;
-    }
-    if (trace_out && n)
-        k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, trace_out + (uint64_t)k * n, n);
-    HIPCHK(hipGetLastError());
+    return enqueue_rounds(g, R, k, seeds_out, gains_out, trace_out, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// Plans: the whole selection captured once into a HIP graph on a private
+// workspace, replayed with one graph launch per selection
+// ---------------------------------------------------------------------------
+struct im_plan {
+    im_workspace *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int im_plan_destroy(im_plan *p)
+{
+    if (!p) return IM_OK;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ws) im_workspace_destroy(p->ws);
+    delete p;
     return IM_OK;
+}
+
+extern "C" int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                              uint32_t *seeds_out, uint64_t *gains_out, void *stream,
+                              im_plan **out)
+{
+    int rc;
+    if (!out) return fail(IM_EINVAL, "null plan output");
+    *out = nullptr;
+    if ((rc = check_args(g, R))) return rc;
+    if (k > g->n) return fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
+    if (k && (!seeds_out || !gains_out)) return fail(IM_EINVAL, "null seeds or gains output");
+    im_plan *p = new im_plan();
+    if ((rc = im_workspace_create(&p->ws))) { delete p; return rc; }
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        im_plan_destroy(p);
+        return fail(IM_EHIP, "hipStreamCreate failed");
+    }
+    rc = check_and_reserve(g, R, k, p->ws, s);
+    if (!rc) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            rc = fail(IM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        } else {
+            rc = enqueue_prepare(g, R, seed, k, p->ws, s);
+            if (!rc) rc = enqueue_rounds(g, R, k, seeds_out, gains_out, nullptr, p->ws, s);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(s, &graph);
+            if (!rc && e != hipSuccess) rc = fail(IM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            p->graph = graph;
+            if (!rc) {
+                e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) rc = fail(IM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (rc) {
+        (void)hipGetLastError();
+        im_plan_destroy(p);
+        return rc;
+    }
+    p->ws->last_stream = (hipStream_t)stream;
+    *out = p;
+    return IM_OK;
+}
+
+extern "C" int im_plan_launch(im_plan *p, void *stream)
+{
+    if (!p || !p->exec) return fail(IM_EINVAL, "null plan");
+    HIPCHK(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    p->ws->last_stream = (hipStream_t)stream;
+    return IM_OK;
+}
+
+extern "C" int im_plan_stats(im_plan *p, im_stats *out)
+{
+    if (!p) return fail(IM_EINVAL, "null plan");
+    return im_stats_get(p->ws, out);
 }
 
 extern "C" int im_profile_enable(im_workspace *ws, uint32_t mask)

@@ -286,3 +286,30 @@ def test_golden_workloads(im, name):
     assert gs["trav_rev"] == st["trav_rev"]
     assert gs["decrements"] == st["decrements"]
     assert gs["relax_init"] == st["word_reach_deg"]
+
+
+@pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
+def test_plan_graph_replays(im, name):
+    # the selection captured into one HIP graph: every replay, with eager work
+    # and synchronisations in between, equals the eager call and the oracle
+    import torch
+    w = gg.WORKLOADS[name]
+    g = gg.workload_graph(name)
+    d = _dev(im, g)
+    s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, w["R"], w["k"], w["seed"])
+    eager = im.select(d, w["R"], w["k"], w["seed"])
+    plan = im.Plan(d, w["R"], w["k"], w["seed"])
+    for rep in range(4):
+        plan.seeds_raw.fill_(-1)
+        plan.gains.fill_(-1)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert plan.seeds.cpu().tolist() == s_ref.tolist(), rep
+        assert plan.gains.cpu().tolist() == g_ref.tolist(), rep
+        # unrelated eager work between replays
+        other = im.select(_dev(im, gg.workload_graph("tiny_uic")), 64, 3, 7)
+        torch.cuda.synchronize()
+    assert eager[0].cpu().tolist() == s_ref.tolist()
+    st = plan.stats()
+    assert st["trav_init"] > 0
+    plan.close()
