@@ -164,6 +164,24 @@ int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
               uint32_t *seeds_out, uint64_t *gains_out, uint32_t *trace_out,
               im_workspace *ws, void *stream);
 
+/* One independent selection problem of a batch. */
+typedef struct im_instance {
+    im_graph g;       /* device CSR, as for im_select          */
+    uint32_t R;       /* snapshots, 1..IM_R_MAX; n*R < 2^32    */
+    uint32_t k;       /* seeds wanted, <= g.n                  */
+    uint64_t seed;    /* RNG seed of this instance's snapshots */
+} im_instance;
+
+/* Batched selection: `count` independent instances of uneven size (host
+ * array of descriptors; the graphs themselves are device-resident) are laid
+ * side by side as one block-diagonal graph and selected together, so every
+ * kernel runs once per phase for the whole batch. Each instance gets exactly
+ * the seeds and gains im_select would give it alone. seeds_out / gains_out
+ * (device) hold instance i's k_i results at offset k_0 + ... + k_{i-1}.
+ * Synchronous validation; limits: sum of n < 2^32 - 1, sum of m < 2^32. */
+int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
+                    uint64_t *gains_out, im_workspace *ws, void *stream);
+
 /* Plans (device-resident round loop). im_plan_create validates the graph
  * (synchronous), then captures the complete selection -- reverse CSR, masks,
  * hub lists, initial gains and all k rounds -- into one HIP graph bound to a

@@ -5,5 +5,6 @@ Influence Maximization", CIKM 2013 (arXiv 1212.4779). The selection runs in
 hand-written HIP kernels behind the C ABI of include/im.h; this package only
 passes torch tensors' device pointers and the current stream to it.
 """
-from .api import (Workspace, Graph, Plan, select, initial_gains, snapshot_masks,  # noqa: F401
+from .api import (Workspace, Graph, Plan, select, select_batch, initial_gains,  # noqa: F401
+                  snapshot_masks,
                   transpose, validate)

@@ -16,7 +16,8 @@ IM_R_MAX = 4096
 EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_last_error",
            "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select",
            "im_profile_enable", "im_profile_get", "im_workspace_set", "im_profile_launches",
-           "im_plan_create", "im_plan_launch", "im_plan_stats", "im_plan_destroy")
+           "im_plan_create", "im_plan_launch", "im_plan_stats", "im_plan_destroy",
+           "im_select_batch")
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
           "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs",
@@ -28,6 +29,11 @@ IM_OPT_COOP_GAIN = 2
 class ImGraph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("prob", ctypes.c_void_p)]
+
+
+class ImInstance(ctypes.Structure):
+    _fields_ = [("g", ImGraph), ("R", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
 
 
 STAT_FIELDS = ("trav_init", "trav_fwd", "trav_rev", "trav_eval", "relax_fwd", "tasks_rev",
@@ -91,6 +97,7 @@ def lib():
         L.im_plan_launch.argtypes = [p, p]
         L.im_plan_stats.argtypes = [p, ctypes.POINTER(ImStats)]
         L.im_plan_destroy.argtypes = [p]
+        L.im_select_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, p, p]
         L.im_profile_get.argtypes = [p, ctypes.POINTER(ImProfile)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p

@@ -187,6 +187,39 @@ def select(graph, R, k, seed, ws=None, trace=False):
     return _u32(seeds), gains, (_u32(tr) if trace else None)
 
 
+def select_batch(instances, ws=None):
+    """Select seeds for several independent instances in one batched pass.
+
+    instances: list of (Graph, R, k, seed), all graphs on one GPU.
+    Returns a list of (seeds int64 [k_i], gains int64 [k_i]), one per instance,
+    each identical to what select() gives that instance alone.
+    """
+    if not instances:
+        return []
+    dev = instances[0][0].device
+    arr = (N.ImInstance * len(instances))()
+    keep = []
+    for i, (g, R, k, seed) in enumerate(instances):
+        cg = g.c_struct()
+        keep.append(cg)
+        arr[i].g = cg
+        arr[i].R = R
+        arr[i].k = k
+        arr[i].seed = seed
+    K = sum(int(x[2]) for x in instances)
+    seeds = torch.empty(K, dtype=torch.int32, device=dev)
+    gains = torch.empty(K, dtype=torch.int64, device=dev)
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_select_batch(arr, len(instances), _ptr(seeds), _ptr(gains), ws.handle,
+                                    _stream(dev)))
+    s64 = _u32(seeds)
+    out, off = [], 0
+    for (_, _, k, _) in instances:
+        out.append((s64[off:off + k], gains[off:off + k]))
+        off += k
+    return out
+
+
 class Plan:
     """The whole selection captured into one HIP graph (device-resident loop).
 

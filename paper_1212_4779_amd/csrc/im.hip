@@ -175,6 +175,49 @@ __global__ __launch_bounds__(TR_NT) void k_transpose(const uint32_t *row32, cons
     }
 }
 
+// A batch's instances are copied side by side into one block-diagonal CSR
+// (node ids shifted by the instance's node offset, arc ids by its arc
+// offset) and validated on the way.
+struct InstDesc {
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+    const float *prob;
+    uint64_t m;
+    uint64_t arc_off;
+    uint32_t n;
+    uint32_t node_off;
+};
+
+__global__ void k_batch_merge(const InstDesc *desc, uint32_t *err, uint32_t *row32, uint32_t *mcol,
+                              float *mprob, uint32_t *node_inst)
+{
+    const uint32_t i = blockIdx.y;
+    const InstDesc d = desc[i];
+    const uint64_t lim = (uint64_t)d.n + 1 > d.m ? (uint64_t)d.n + 1 : d.m;
+    uint32_t e = 0;
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < lim;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        if (j <= d.n) {
+            const uint64_t r = d.row_ptr[j];
+            if (j == 0 && r != 0) e |= ERR_ROW0;
+            if (j == d.n && r != d.m) e |= ERR_ROWN;
+            if (j < d.n && d.row_ptr[j + 1] < r) e |= ERR_ROWDEC;
+            if (r > d.m) e |= ERR_ROWBIG;
+            row32[d.node_off + j] = (uint32_t)(d.arc_off + r);
+            if (j < d.n) node_inst[d.node_off + j] = i;
+        }
+        if (j < d.m) {
+            const uint32_t c = d.col[j];
+            if (c >= d.n) e |= ERR_COL;
+            mcol[d.arc_off + j] = d.node_off + c;
+            const float p = d.prob[j];
+            if (!(p >= 0.0f && p <= 1.0f)) e |= ERR_PROB;
+            mprob[d.arc_off + j] = p;
+        }
+    }
+    if (e) atomicOr(err, e);
+}
+
 constexpr int SCAN_NT = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_NT * SCAN_IPT;
 
 // exclusive scan, pass 1: per-tile scan and tile totals
@@ -237,25 +280,36 @@ __global__ void k_scan_add(uint32_t *out, uint64_t len, const uint32_t *sums)
 // Arc e is live in snapshot r iff the top 32 bits of output r+1 of a
 // SplitMix64 generator seeded with key_e (output e+1 of SplitMix64(seed))
 // are below floor(p_e * 2^32). One thread per (arc, word).
+// In a batch, arc e belongs to instance i and is arc e - arc_off[i] of it:
+// the instance's own seed and R apply (its words beyond R are all zero).
 __global__ __launch_bounds__(256) void k_mask_gen(const float *prob, uint64_t m, uint32_t R,
-                                                  uint64_t seed, uint64_t *mask)
+                                                  uint64_t seed, uint64_t *mask, Batch b)
 {
     uint64_t e = blockIdx.x * 256ull + threadIdx.x;
     uint32_t w = blockIdx.y;
     if (e >= m) return;
-    uint64_t thr = (uint64_t)((double)prob[e] * 4294967296.0);
-    uint32_t r0 = w * 64u;
-    uint32_t cnt = min(64u, R - r0);
+    uint64_t el = e;
+    if (b.arc_off) {
+        const uint32_t i = find_instance<uint64_t>(b.arc_off, b.count, e);
+        el = e - b.arc_off[i];
+        R = b.R[i];
+        seed = b.seed[i];
+    }
     uint64_t word = 0;
-    if (thr >= (1ull << 32)) {
-        word = im_valid_bits(R, w);
-    } else if (thr) {
-        uint64_t key = sm64_finalise(seed + (e + 1ull) * IM_GOLDEN);
-        uint64_t z = key + (uint64_t)(r0 + 1u) * IM_GOLDEN;
-        for (uint32_t b = 0; b < cnt; b++) {
-            uint64_t d = sm64_finalise(z) >> 32;
-            word |= (uint64_t)(d < thr) << b;
-            z += IM_GOLDEN;
+    const uint32_t r0 = w * 64u;
+    if (r0 < R) {
+        const uint32_t cnt = min(64u, R - r0);
+        const uint64_t thr = (uint64_t)((double)prob[e] * 4294967296.0);
+        if (thr >= (1ull << 32)) {
+            word = im_valid_bits(R, w);
+        } else if (thr) {
+            uint64_t key = sm64_finalise(seed + (el + 1ull) * IM_GOLDEN);
+            uint64_t z = key + (uint64_t)(r0 + 1u) * IM_GOLDEN;
+            for (uint32_t bt = 0; bt < cnt; bt++) {
+                uint64_t d = sm64_finalise(z) >> 32;
+                word |= (uint64_t)(d < thr) << bt;
+                z += IM_GOLDEN;
+            }
         }
     }
     mask[(uint64_t)w * m + e] = word;
@@ -388,13 +442,38 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
 // ---------------------------------------------------------------------------
 // A4: argmax of (gain, lowest id) over unselected nodes
 // ---------------------------------------------------------------------------
+// key = (gain << 32) | (0xFFFFFFFF - node): the larger gain wins, then the
+// lower id. In a batch every instance gets its own key (keys[i]); instances
+// that already have all their seeds (t >= k_i) take no part.
 __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint8_t *sel,
-                                                uint32_t n, unsigned long long *key,
-                                                uint32_t *zero, uint32_t nzero)
+                                                uint32_t n, unsigned long long *keys, Batch b,
+                                                uint32_t t, uint32_t *zero, uint32_t nzero)
 {
     __shared__ unsigned long long red[4];
     // also clear this round's reverse-task packing counters
     for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < nzero; i += gridDim.x * 256u) zero[i] = 0;
+    if (b.node_inst) {
+        for (uint32_t base = blockIdx.x * 256u; base < n; base += gridDim.x * 256u) {
+            const uint32_t u = base + threadIdx.x;
+            uint32_t inst = 0xFFFFFFFFu;
+            unsigned long long k = 0;
+            if (u < n) {
+                inst = b.node_inst[u];
+                if (t < b.k[inst] && !sel[u])
+                    k = ((unsigned long long)gain[u] << 32) | (0xFFFFFFFFu - u);
+            }
+            // one atomic per wavefront when all its lanes share an instance
+            const uint32_t i0 = __shfl(inst, 0, 64);
+            const bool same = __all(inst == i0);
+            if (same) {
+                k = wave_max_u64(k);
+                if ((threadIdx.x & 63) == 0 && k && i0 != 0xFFFFFFFFu) atomicMax(&keys[i0], k);
+            } else if (k) {
+                atomicMax(&keys[inst], k);
+            }
+        }
+        return;
+    }
     unsigned long long best = 0;
     for (uint32_t u = blockIdx.x * 256u + threadIdx.x; u < n; u += gridDim.x * 256u)
         if (!sel[u]) {
@@ -406,7 +485,7 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < 4; i++) best = red[i] > best ? red[i] : best;
-        if (best) atomicMax(key, best);
+        if (best) atomicMax(keys, best);
     }
 }
 
@@ -432,8 +511,9 @@ struct FwdArgs {
                                 // visit counts; zero on entry
     uint64_t *vis;              // visited (word << 32 | node), capacity W*n
     uint32_t *tnodes, *tcounts;
-    const unsigned long long *key;
+    const unsigned long long *key;   // keys of this round, one per instance
     uint32_t t;
+    Batch b;
     uint32_t *seeds_out;
     uint64_t *gains_out;
     uint8_t *sel;
@@ -508,35 +588,38 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     const int tid = threadIdx.x;
     const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
     const uint64_t gsize = (uint64_t)gridDim.x * FWD_NT;
-    const unsigned long long key = a.key[a.t];
-    if (key == 0) return;  // no unselected node (cannot happen for k <= n); uniform
-    if ((key >> 32) < a.coop_gain) return;  // a small round: k_forward_block runs it
-    const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
-    // a hub seed (W <= 4) is expanded by the whole grid at level 0
-    const uint32_t hs0 = a.hub.slot[v];
+    const bool single = a.b.count == 1;
+    const unsigned long long key0 = a.key[0];
+    if (single && key0 == 0) return;  // no unselected node (cannot happen for k <= n)
+    if (single && (key0 >> 32) < a.coop_gain) return;  // a small round: k_forward_block runs it
+    const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key0 & 0xFFFFFFFFull);
+    // a hub seed of a single graph (W <= 4) is expanded by the whole grid at level 0
+    const uint32_t hs0 = single ? a.hub.slot[v] : IM_EMPTY;
     const bool split0 = hs0 != IM_EMPTY && a.W <= 4;
     if (blockIdx.x == 0) {
-        if (tid == 0) {
-            a.seeds_out[a.t] = v;
-            a.gains_out[a.t] = key >> 32;
-            a.sel[v] = 1;
-            L.H.n = 0;
-            uint32_t nf = 0;
+        // commit every instance's argmax and enter its uncovered bits
+        for (uint32_t i = tid; i < a.b.count; i += FWD_NT) {
+            const unsigned long long key = a.key[i];
+            if (key == 0) continue;  // instance already has its k seeds
+            const uint32_t sv = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+            const uint32_t R = single ? a.R : a.b.R[i];
+            const uint32_t out = (single ? 0u : a.b.kpre[i]) + a.t;
+            a.seeds_out[out] = sv - (single ? 0u : a.b.node_off[i]);
+            a.gains_out[out] = key >> 32;
+            a.sel[sv] = 1;
             for (uint32_t w = 0; w < a.W; w++) {
                 const uint64_t off = (uint64_t)w * a.n;
-                uint64_t start = im_valid_bits(a.R, w) & ~a.covered[off + v];
+                uint64_t start = im_valid_bits(R, w) & ~a.covered[off + sv];
                 if (!start) continue;
-                a.newly[off + v] = start;
-                a.vis[nf] = ((uint64_t)w << 32) | v;
+                a.newly[off + sv] = start;
+                a.vis[atomicAdd(&a.cnt[3], 1u)] = ((uint64_t)w << 32) | sv;
                 if (!split0) {
-                    a.pend[off + v] = start;
-                    a.fq0[nf] = ((uint64_t)w << 32) | v;
+                    a.pend[off + sv] = start;
+                    a.fq0[atomicAdd(&a.cnt[0], 1u)] = ((uint64_t)w << 32) | sv;
                 }
-                nf++;
             }
-            a.cnt[0] = split0 ? 0u : nf;
-            a.cnt[3] = nf;
         }
+        if (tid == 0) L.H.n = 0;
     } else if (tid == 0) {
         L.H.n = 0;
     }
@@ -731,7 +814,7 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
 {
     __shared__ BlockLds<FWB_NT> L;
     const int tid = threadIdx.x;
-    const unsigned long long key = a.key[a.t];
+    const unsigned long long key = a.key[0];
     if (key == 0) return;
     if ((key >> 32) >= a.coop_gain) return;  // the cooperative kernel runs this round
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
@@ -917,6 +1000,17 @@ struct im_workspace {
     uint32_t *plist = nullptr, *mlist = nullptr;  // [W][n]
     unsigned fwd_grid = 0;
     unsigned long long *keys = nullptr;
+    uint64_t cap_keys = 0;
+    // batches
+    Batch batch = {1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    uint32_t cap_count = 0;
+    uint64_t cap_bn = 0, cap_bm = 0;
+    uint32_t *b_node_inst = nullptr, *b_mcol = nullptr;
+    float *b_mprob = nullptr;
+    uint32_t *b_u32 = nullptr;          // R, k, kpre, node_off per instance
+    uint64_t *b_u64 = nullptr;          // arc_off, seed per instance
+    InstDesc *b_desc = nullptr;
+    void *b_host = nullptr;             // pinned staging of the above
     uint32_t *ovf_q = nullptr, *ovf_q2 = nullptr;
     uint32_t *ctrs = nullptr;
     // hub lists per direction (0: forward arcs, 1: reverse arcs)
@@ -1036,6 +1130,9 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
         dfree(ws->hadj[d]); dfree(ws->hbase[d]);
     }
     dfree(ws->hnum); dfree(ws->halloc);
+    dfree(ws->b_node_inst); dfree(ws->b_mcol); dfree(ws->b_mprob); dfree(ws->b_u32);
+    dfree(ws->b_u64); dfree(ws->b_desc);
+    if (ws->b_host) (void)hipHostFree(ws->b_host);
     dfree(ws->stats); dfree(ws->err);
     if (ws->host_err) (void)hipHostFree(ws->host_err);
     if (ws->host_stats) (void)hipHostFree(ws->host_stats);
@@ -1115,9 +1212,14 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
                 return rc;
         ws->cap_hub = ch;
     }
+    const uint64_t nkeys = (uint64_t)(k + 1) * ws->batch.count;
+    if (nkeys > ws->cap_keys) {
+        if ((rc = dalloc(&ws->keys, nkeys))) return rc;
+        ws->cap_keys = nkeys;
+    }
     if (k + 1 > ws->cap_k) {
         uint32_t ck = k + 1;
-        if ((rc = dalloc(&ws->keys, ck)) || (rc = dalloc(&ws->ctrs, (uint64_t)(ck + 1) * PH_CTRS)) ||
+        if ((rc = dalloc(&ws->ctrs, (uint64_t)(ck + 1) * PH_CTRS)) ||
             (rc = dalloc(&ws->fctr, (uint64_t)ck * FWD_CTRS)))
             return rc;
         ws->cap_k = ck;
@@ -1196,7 +1298,7 @@ static void build_masks(const im_graph *g, uint32_t R, uint64_t seed, im_workspa
     dim3 grid((unsigned)((m + 255) / 256), W);
     {
         PhaseTimer pt(ws, IM_PH_MASK_GEN, s);
-        k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, mask_out);
+        k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, mask_out, ws->batch);
     }
     if (reverse) {
         PhaseTimer pt(ws, IM_PH_MASK_GATHER, s);
@@ -1238,6 +1340,7 @@ static BfsArgs bfs_args(im_workspace *ws, const uint32_t *row, const uint32_t *c
     BfsArgs a;
     memset(&a, 0, sizeof(a));
     a.row = row; a.col = col; a.mask = mask; a.m = m; a.n = n; a.R = R; a.W = W;
+    a.node_inst = ws->batch.node_inst; a.inst_R = ws->batch.R;
     a.gain = ws->gain;
     a.b_reach = ws->b_reach; a.b_pend = ws->b_pend; a.b_fdel = ws->b_fdel;
     a.b_qa = ws->b_qa; a.b_qb = ws->b_qb; a.b_vis = ws->b_vis;
@@ -1304,8 +1407,9 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     uint32_t n = g->n, W = (R + 63) / 64;
     {
         PhaseTimer pt(ws, IM_PH_ARGMAX, s);
-        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys + t, ws->pk,
-                                                         (uint32_t)PK_ZERO);
+        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n,
+                                                         ws->keys + (uint64_t)t * ws->batch.count,
+                                                         ws->batch, t, ws->pk, (uint32_t)PK_ZERO);
     }
 
     FwdArgs f;
@@ -1316,11 +1420,12 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
     f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
     f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
-    f.key = ws->keys; f.t = t; f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
+    f.key = ws->keys + (uint64_t)t * ws->batch.count; f.t = t; f.b = ws->batch;
+    f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
     f.stats = ws->stats;
     {
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
-        k_forward_block<<<W, FWB_NT, 0, s>>>(f);
+        if (ws->batch.count == 1) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
         void *args[] = {&f};
         const unsigned fg = std::min<unsigned>(ws->fwd_grid, 16u * W);
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
@@ -1371,7 +1476,7 @@ static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_
     uint32_t n = g->n, W = (R + 63) / 64;
     fill<unsigned long long>(ws->stats, ST_COUNT, 0ull, s);
     fill<uint32_t>(ws->ctrs, (uint64_t)(k + 1) * PH_CTRS, 0u, s);
-    fill<unsigned long long>(ws->keys, (uint64_t)k + 1, 0ull, s);
+    fill<unsigned long long>(ws->keys, (uint64_t)(k + 1) * ws->batch.count, 0ull, s);
     fill<uint32_t>(ws->fctr, (uint64_t)(k ? k : 1) * FWD_CTRS, 0u, s);
     fill<uint32_t>(ws->gain, n, 0u, s);
     fill<uint8_t>(ws->sel, n, (uint8_t)0, s);
@@ -1663,4 +1768,134 @@ extern "C" int im_profile_launches(im_workspace *ws, int phase, float *ms_out, u
     *count = (uint32_t)v.size();
     for (uint32_t i = 0; i < max && i < v.size(); i++) ms_out[i] = v[i];
     return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: many independent instances selected together
+// ---------------------------------------------------------------------------
+static int reserve_batch(im_workspace *ws, uint32_t count, uint64_t N, uint64_t M)
+{
+    int rc;
+    if (count > ws->cap_count) {
+        if ((rc = dalloc(&ws->b_u32, 4ull * (count + 1))) || (rc = dalloc(&ws->b_u64, 2ull * (count + 1))) ||
+            (rc = dalloc(&ws->b_desc, count)))
+            return rc;
+        if (ws->b_host) (void)hipHostFree(ws->b_host);
+        ws->b_host = nullptr;
+        size_t bytes = (4ull * (count + 1)) * 4 + (2ull * (count + 1)) * 8 + (uint64_t)count * sizeof(InstDesc);
+        HIPCHK(hipHostMalloc(&ws->b_host, bytes, hipHostMallocDefault));
+        ws->cap_count = count;
+    }
+    if (N > ws->cap_bn) {
+        if ((rc = dalloc(&ws->b_node_inst, N))) return rc;
+        ws->cap_bn = N;
+    }
+    if (M > ws->cap_bm || !ws->b_mcol) {
+        if ((rc = dalloc(&ws->b_mcol, M)) || (rc = dalloc(&ws->b_mprob, M))) return rc;
+        ws->cap_bm = M;
+    }
+    return IM_OK;
+}
+
+extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
+                               uint64_t *gains_out, im_workspace *ws, void *stream)
+{
+    int rc;
+    if (!inst || !ws) return fail(IM_EINVAL, "null instances or workspace");
+    if (count == 0) return IM_OK;
+    if (count == 1)
+        return im_select(&inst[0].g, inst[0].R, inst[0].k, inst[0].seed, seeds_out, gains_out,
+                         nullptr, ws, stream);
+    uint64_t N = 0, M = 0, K = 0;
+    uint32_t Rmax = 0, kmax = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        if ((rc = check_args(&inst[i].g, inst[i].R)))
+            return fail(rc, "instance %u: %s", i, g_err.c_str());
+        if (inst[i].k > inst[i].g.n) return fail(IM_EINVAL, "instance %u: k exceeds n", i);
+        N += inst[i].g.n;
+        M += inst[i].g.m;
+        K += inst[i].k;
+        Rmax = std::max(Rmax, inst[i].R);
+        kmax = std::max(kmax, inst[i].k);
+    }
+    if (N >= 0xFFFFFFFFull) return fail(IM_EINVAL, "batch has %llu nodes; must be < 2^32 - 1", (unsigned long long)N);
+    if (M >= (1ull << 32)) return fail(IM_EINVAL, "batch has %llu arcs; must be < 2^32", (unsigned long long)M);
+    if (K && (!seeds_out || !gains_out)) return fail(IM_EINVAL, "null seeds or gains output");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t W = (Rmax + 63) / 64;
+    ws->batch.count = count;  // sizes the per-round key arrays
+    rc = ws_reserve(ws, (uint32_t)N, M, W, kmax);
+    ws->batch.count = 1;
+    if (!rc) rc = reserve_batch(ws, count, N, M);
+    if (rc) return rc;
+    // per-instance tables, staged in pinned memory
+    uint32_t *hu = (uint32_t *)ws->b_host;              // R, k, kpre, node_off
+    uint64_t *h64 = (uint64_t *)(hu + 4ull * (count + 1));  // arc_off, seed
+    InstDesc *hd = (InstDesc *)(h64 + 2ull * (count + 1));
+    uint64_t no = 0, ao = 0, kp = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        hu[i] = inst[i].R;
+        hu[(count + 1) + i] = inst[i].k;
+        hu[2 * (count + 1) + i] = (uint32_t)kp;
+        hu[3 * (count + 1) + i] = (uint32_t)no;
+        h64[i] = ao;
+        h64[(count + 1) + i] = inst[i].seed;
+        hd[i].row_ptr = inst[i].g.row_ptr;
+        hd[i].col = inst[i].g.col;
+        hd[i].prob = inst[i].g.prob;
+        hd[i].m = inst[i].g.m;
+        hd[i].arc_off = ao;
+        hd[i].n = inst[i].g.n;
+        hd[i].node_off = (uint32_t)no;
+        if (inst[i].g.m && (!inst[i].g.col || !inst[i].g.prob))
+            return fail(IM_EINVAL, "instance %u: null col or prob", i);
+        if (!inst[i].g.row_ptr) return fail(IM_EINVAL, "instance %u: null row_ptr", i);
+        no += inst[i].g.n;
+        ao += inst[i].g.m;
+        kp += inst[i].k;
+    }
+    hu[3 * (count + 1) + count] = (uint32_t)no;
+    h64[count] = ao;
+    size_t bytes = (4ull * (count + 1)) * 4 + (2ull * (count + 1)) * 8;
+    HIPCHK(hipMemcpyAsync(ws->b_u32, hu, (4ull * (count + 1)) * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws->b_u64, h64, (2ull * (count + 1)) * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws->b_desc, hd, (uint64_t)count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    (void)bytes;
+    HIPCHK(hipMemsetAsync(ws->err, 0, sizeof(uint32_t), s));
+    {
+        uint64_t maxw = 0;
+        for (uint32_t i = 0; i < count; i++)
+            maxw = std::max<uint64_t>(maxw, std::max<uint64_t>((uint64_t)inst[i].g.n + 1, inst[i].g.m));
+        dim3 grid(grid_for(maxw, 256, 256), count);
+        k_batch_merge<<<grid, 256, 0, s>>>(ws->b_desc, ws->err, ws->row32, ws->b_mcol, ws->b_mprob,
+                                           ws->b_node_inst);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ws->host_err, ws->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*ws->host_err)
+        return fail(IM_EINVAL, "a batch instance failed validation (flags 0x%x)", *ws->host_err);
+    Batch b;
+    b.count = count;
+    b.node_inst = ws->b_node_inst;
+    b.R = ws->b_u32;
+    b.k = ws->b_u32 + (count + 1);
+    b.kpre = ws->b_u32 + 2 * (count + 1);
+    b.node_off = ws->b_u32 + 3 * (count + 1);
+    b.arc_off = ws->b_u64;
+    b.seed = ws->b_u64 + (count + 1);
+    ws->batch = b;
+    im_graph mg;
+    mg.n = (uint32_t)N;
+    mg.m = M;
+    mg.row_ptr = nullptr;
+    mg.col = ws->b_mcol;
+    mg.prob = ws->b_mprob;
+    {
+        PhaseTimer pt(ws, IM_PH_CALL, s);
+        rc = enqueue_prepare(&mg, Rmax, 0, kmax, ws, s);
+        if (!rc) rc = enqueue_rounds(&mg, Rmax, kmax, seeds_out, gains_out, nullptr, ws, s);
+    }
+    ws->batch = Batch{1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    return rc;
 }

@@ -59,6 +59,8 @@ struct BfsArgs {
     const uint64_t *mask;     // [W][m], word-major
     uint64_t m;
     uint32_t n, R, W;
+    const uint32_t *node_inst;  // batches: instance of each node (nullptr: one graph)
+    const uint32_t *inst_R;     // batches: snapshots per instance
     HubLists hub;
     const uint64_t *prune;    // [W][n] or nullptr
     uint32_t *gain;           // [n]
@@ -108,8 +110,9 @@ __device__ __forceinline__ void task_source(const BfsArgs &a, int mode, uint32_t
             src = t - w * a.n;
         }
         if (lane == 0) {
-            bits = im_valid_bits(a.R, w);
-            if (a.prune) bits &= ~a.prune[(uint64_t)w * a.n + src];
+            const uint32_t R = a.node_inst ? a.inst_R[a.node_inst[src]] : a.R;
+            bits = im_valid_bits(R, w);
+            if (bits && a.prune) bits &= ~a.prune[(uint64_t)w * a.n + src];
         }
         return;
     }
@@ -392,8 +395,11 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                 uint32_t w, src;
                 uint64_t bits;
                 task_source(a, MODE, t, L.wpre, (uint32_t)tid, w, src, bits);
+                // a task without start bits (e.g. a word beyond an instance's R)
+                // leaves the slot idle: an active slot must own frontier entries
+                const bool any = __ballot(bits != 0) != 0ull;
                 if (tid == 0) {
-                    L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w; L.s_act[s] = 1;
+                    L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w; L.s_act[s] = any ? 1u : 0u;
                 }
                 if (bits) lds_relax<NT, T, CS, LIM>(L, s, src, bits, cur, true);
             }

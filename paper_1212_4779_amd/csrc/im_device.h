@@ -28,8 +28,36 @@ __device__ __forceinline__ uint64_t sm64_finalise(uint64_t z)
 __device__ __forceinline__ uint64_t im_valid_bits(uint32_t R, uint32_t w)
 {
     uint32_t lo = w * 64u;
+    if (lo >= R) return 0ull;
     uint32_t cnt = R - lo;
     return cnt >= 64u ? ~0ull : ((1ull << cnt) - 1ull);
+}
+
+// Several independent instances laid side by side as one block-diagonal
+// graph: instance i owns nodes [node_off[i], node_off[i+1]) and arcs
+// [arc_off[i], arc_off[i+1]). count = 1 with null arrays is one graph whose
+// parameters are passed as scalars.
+struct Batch {
+    uint32_t count;
+    const uint32_t *node_inst;  // [N] instance of each node
+    const uint32_t *R;          // [count] snapshots
+    const uint32_t *k;          // [count] seeds wanted
+    const uint32_t *kpre;       // [count] offset of the instance's outputs
+    const uint32_t *node_off;   // [count+1]
+    const uint64_t *arc_off;    // [count+1]
+    const uint64_t *seed;       // [count]
+};
+
+// largest i with off[i] <= x (off[0] = 0 <= x < off[count])
+template <typename T>
+__device__ __forceinline__ uint32_t find_instance(const T *off, uint32_t count, T x)
+{
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (off[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------

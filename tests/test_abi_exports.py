@@ -32,3 +32,4 @@ def test_struct_layout_matches_header():
     from paper_1212_4779_amd import _native
     assert ctypes.sizeof(_native.ImGraph) == 40
     assert ctypes.sizeof(_native.ImStats) == 64 * 8
+    assert ctypes.sizeof(_native.ImInstance) == 56

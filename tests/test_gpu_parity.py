@@ -313,3 +313,42 @@ def test_plan_graph_replays(im, name):
     st = plan.stats()
     assert st["trav_init"] > 0
     plan.close()
+
+
+def _batch_instances():
+    out = []
+    recipes = gg.batch_instances(24, master_seed=11)
+    for i, w in enumerate(recipes):
+        # keep the CPU oracle fast: shrink the sampled sizes, keep the mix
+        n = max(200, w["n"] // 40)
+        w = dict(w, n=n, m=int(n * w["m"] / w["n"]), k=min(w["k"], 12))
+        out.append((gg.graph_from_recipe(w), w["R"], w["k"], 100 + i))
+    # degenerate members: no arcs, k = 0, k = n
+    out.append((_csr(30, [], 0.5), 64, 5, 3))
+    out.append((gg.chung_lu_graph(200, 900, 2.5, 4, True, 0.1), 128, 0, 4))
+    out.append((gg.chung_lu_graph(40, 150, 2.5, 5, True, 0.3), 100, 40, 5))
+    return out
+
+
+def test_batch_matches_oracle_and_single_runs(im):
+    insts = _batch_instances()
+    dev = [(_dev(im, g), R, k, seed) for (g, R, k, seed) in insts]
+    res = im.select_batch(dev)
+    for (g, R, k, seed), (d, _, _, _), (s_b, g_b) in zip(insts, dev, res):
+        s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
+        assert s_b.cpu().tolist() == s_ref.tolist()
+        assert g_b.cpu().tolist() == g_ref.tolist()
+        alone = im.select(d, R, k, seed)
+        assert alone[0].cpu().tolist() == s_b.cpu().tolist()
+
+
+def test_batch_rejects_bad_instance(im):
+    from paper_1212_4779_amd import _native as N
+    good = _dev(im, gg.workload_graph("tiny_uic"))
+    bad = _csr(3, [(0, 1), (1, 2)], 0.5)
+    bad.col[1] = 3
+    with pytest.raises(N.ImError) as e:
+        im.select_batch([(good, 64, 3, 1), (_dev(im, bad), 64, 1, 1)])
+    assert e.value.code == N.IM_EINVAL
+    with pytest.raises(N.ImError):
+        im.select_batch([(good, 64, 3, 1), (good, 0, 1, 1)])
