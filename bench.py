@@ -90,6 +90,95 @@ def cpu_baseline(g, w, log):
             "seconds": round(dt, 3)}, seeds, gains
 
 
+def run_batch(args, log):
+    """512 uneven instances selected together (one block-diagonal graph)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1212_4779_amd as im
+    from paper_1212_4779_amd import graphgen as gg
+
+    rec = gg.batch_instances(**gg.BATCH_WORKLOAD)
+    t0 = time.perf_counter()
+    graphs = gg.graphs_from_recipes(rec, workers=min(16, os.cpu_count() or 1))
+    log(f"batch: {len(graphs)} instances, n={sum(g.n for g in graphs)} "
+        f"m={sum(g.m for g in graphs)} ({time.perf_counter() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    insts = [(im.Graph.from_numpy(g.row_ptr, g.col, g.prob, device=dev), w["R"], w["k"], w["seed"])
+             for g, w in zip(graphs, rec)]
+    ws = im.Workspace()
+    for i in range(args.warmup):
+        t1 = time.perf_counter()
+        im.select_batch(insts, ws=ws)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t1:.2f}s")
+    ws.profile_enable()
+    res = im.select_batch(insts, ws=ws)
+    prof = ws.profile()
+    st = ws.stats()
+    W = 4
+    n_tot = sum(g.n for g in graphs)
+    kb = kernel_bytes(st, n_tot, W)
+    dom = max(PROPAGATION, key=lambda p: prof[p][0])
+    log("phases (ms, launches): " + ", ".join(f"{p}={prof[p][0]:.3f}/{prof[p][1]}" for p in prof))
+    ws.profile_enable([dom])
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        res = im.select_batch(insts, ws=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    dprof = ws.profile()[dom]
+    st = ws.stats()
+    trav = st["trav_init"] + st["trav_fwd"] + st["trav_rev"]
+    launches = max(1, dprof[1] // args.steps)
+    avg_ms = dprof[0] / max(1, dprof[1])
+    bpl = kb[dom] / launches
+    ach = bpl / (avg_ms / 1e3) / 1e9
+    gold_path = os.path.join(ROOT, "tests", "golden", "batch512.json")
+    parity = None
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)["instances"]
+        parity = all(res[gi["i"]][0].cpu().tolist() == gi["seeds"] and
+                     res[gi["i"]][1].cpu().tolist() == gi["gains"] for gi in gold)
+    cpu = None
+    if not args.no_cpu_baseline:
+        oracle._load()
+        t0 = time.perf_counter()
+        tr, used = 0, 0
+        for g, w in zip(graphs, rec):
+            _, _, _, ost = oracle.select_du(g.row_ptr, g.col, g.prob, w["R"], w["k"], w["seed"])
+            tr += ost["trav_init"] + ost["trav_fwd"] + ost["trav_rev"]
+            used += 1
+            if time.perf_counter() - t0 > 20:
+                break
+        dt = time.perf_counter() - t0
+        cpu = {"value": tr / dt, "unit": "snapshot-edge traversals/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {used} of {len(graphs)} instances, StaticGreedyDU oracle, one thread",
+               "seconds": round(dt, 3)}
+    return {
+        "metric": "k-seed selection wall time + snapshot-edge traversals/s (% HBM peak)",
+        "value": trav / (ms / 1e3), "unit": "snapshot-edge traversals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batch512", "instances": len(graphs), "n_total": n_tot,
+                   "m_total": sum(g.m for g in graphs), "R": "64/128/256", "k": 20,
+                   "path": "dynamic update, batched"},
+        "selection_ms": ms, "traversals_per_step": trav,
+        "phase_ms": {p: round(prof[p][0], 4) for p in prof},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": KERNEL_NAMES[dom], "phase": dom,
+                     "algorithmic_bytes_per_launch": int(bpl), "avg_launch_ms": round(avg_ms, 4)},
+        "cpu_baseline": cpu, "parity_vs_oracle_golden": parity,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +197,10 @@ def main():
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch512":
+        print(json.dumps(run_batch(args, log)), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -966,7 +966,7 @@ __global__ void k_copy_u32(const uint32_t *src, uint32_t *dst, uint64_t cnt)
 constexpr int T0_T = 8, T0_CS = 32, T0_LIM = 24, T0_U = 8;
 constexpr uint32_t T0_DMAX = 1024;
 // tier 1: 256 lanes, T1_T tasks of up to T1_LIM nodes, any degree
-constexpr int T1_NT = 256, T1_T = 1, T1_CS = 1024, T1_LIM = 768, T1_U = 8;
+constexpr int T1_NT = 256, T1_T = 1, T1_CS = 2048, T1_LIM = 1536, T1_U = 8;
 // tier 2: dense global arrays
 constexpr int T2_NT = 256, T2_U = 8;
 // per-phase device counters: grab0, n1, grab1, n2, grab2
@@ -1144,9 +1144,9 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
 
 static uint32_t slots_for(uint32_t n)
 {
-    // dense block-engine state: 36 bytes per node per slot, about 8 GB total
+    // dense global-engine state: 36 bytes per node per slot, at most 48 GB
     uint64_t per = 36ull * (n ? n : 1);
-    uint64_t s = (8ull << 30) / per;
+    uint64_t s = (48ull << 30) / per;
     if (s > 256) s = 256;
     if (s < 8) s = 8;
     return (uint32_t)s;

@@ -139,6 +139,9 @@ def workload_graph(name):
     return chung_lu_graph(w["n"], w["m"], w["gamma"], w["graph_seed"], w["directed"], w["p"])
 
 
+BATCH_WORKLOAD = dict(count=512, master_seed=4)
+
+
 def batch_instances(count=512, master_seed=4):
     """Recipe of the batched workload: `count` uneven instances.
 
@@ -164,6 +167,16 @@ def batch_instances(count=512, master_seed=4):
 
 def graph_from_recipe(w):
     return chung_lu_graph(w["n"], w["m"], w["gamma"], w["graph_seed"], w["directed"], w["p"])
+
+
+def graphs_from_recipes(recipes, workers=8):
+    """Generate many graphs in worker processes (same output as one by one)."""
+    if workers <= 1 or len(recipes) < 2:
+        return [graph_from_recipe(w) for w in recipes]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        return pool.map(graph_from_recipe, recipes, chunksize=1)
 
 
 def graph_digest(g):
