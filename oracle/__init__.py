@@ -3,8 +3,9 @@
 Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The GPU product path never imports it
 and shares no code with it. The arithmetic lives in ``oracle.c`` (plain C,
-single-threaded); this module only compiles it with gcc and marshals numpy
-arrays through ctypes.
+single-threaded) and ``mlp.c`` (FP64 reference of the candidate-scoring
+network); this module only compiles them with gcc and marshals numpy arrays
+through ctypes.
 
 Paper: Cheng et al., "StaticGreedy: Solving the Scalability-Accuracy Dilemma
 in Influence Maximization", CIKM 2013 (arXiv 1212.4779): Sec. 3.1 (IC model,
@@ -18,7 +19,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "mlp.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 NSTATS = 8
@@ -31,10 +32,10 @@ class OracleError(RuntimeError):
 
 
 def build():
-    """Compile oracle.c with gcc into liboracle.so (always recompiles)."""
+    """Compile oracle.c and mlp.c with gcc into liboracle.so (always recompiles)."""
     tmp = _LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
-                           "-Wextra", "-o", tmp, _SRC, "-lm"])
+                           "-Wextra", "-o", tmp, *_SRC, "-lm"])
     os.replace(tmp, _LIB)
 
 
@@ -57,6 +58,14 @@ def _load():
         lib.oracle_select_alg1.argtypes = graph + [u32, u64, p, p]
         lib.oracle_select_celf.argtypes = graph + [u32, u64, p, p, p]
         lib.oracle_spread.argtypes = graph + [u64, p, u32, p]
+        lib.oracle_mlp_nparams.restype = ctypes.c_int
+        lib.oracle_bf16_round.argtypes = [u64, p, p]
+        lib.oracle_node_features.argtypes = [u32, u64, p, p, p, p]
+        lib.oracle_mlp_forward.argtypes = [p, u64, p, p]
+        lib.oracle_mlp_loss_grad.argtypes = [p, u64, p, p, p]
+        lib.oracle_mlp_loss_grad.restype = ctypes.c_double
+        d = ctypes.c_double
+        lib.oracle_adam_step.argtypes = [u64, p, p, p, p, d, d, d, d, u32]
         _lib = lib
     return _lib
 
@@ -144,3 +153,57 @@ def spread(row_ptr, col, prob, R, seed, S):
     _check(_load().oracle_spread(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, seed,
                                  _ptr(S), len(S), ctypes.byref(out)), "spread")
     return int(out.value)
+
+
+# ---------------------------------------------------------------------------
+# candidate-scoring network (mlp.c)
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_H = 5, 64
+
+
+def mlp_nparams():
+    return int(_load().oracle_mlp_nparams())
+
+
+def bf16_round(a):
+    """Round float32 values to bfloat16 precision (nearest, ties to even)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    out = np.empty_like(a)
+    _load().oracle_bf16_round(a.size, _ptr(a), _ptr(out))
+    return out
+
+
+def node_features(row_ptr, col, prob):
+    """Static node features float64 [n, 4] (ln(1+x) of in/out degree, out-probability
+    sum, two-hop out-degree sum)."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    out = np.zeros((n, 4), dtype=np.float64)
+    _check(_load().oracle_node_features(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(out)),
+           "node_features")
+    return out
+
+
+def mlp_forward(params, x):
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    y = np.zeros(len(x), dtype=np.float64)
+    _load().oracle_mlp_forward(_ptr(params), len(x), _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    """(L, dL/dparams) for L = sum (y - t)^2 / (2N), in float64."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    g = np.zeros(mlp_nparams(), dtype=np.float64)
+    loss = _load().oracle_mlp_loss_grad(_ptr(params), len(x), _ptr(x), _ptr(t), _ptr(g))
+    return float(loss), g
+
+
+def adam_step(theta, m, v, g, lr, b1, b2, eps, t):
+    """One Adam step in place on float64 arrays theta, m, v."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    _load().oracle_adam_step(len(theta), _ptr(theta), _ptr(m), _ptr(v), _ptr(g), lr, b1, b2, eps, t)
