@@ -101,7 +101,9 @@ typedef struct im_stats {
     uint64_t handed_over[3][3];/* tasks passed on to the next tier                */
     uint64_t fwd_levels;       /* levels of the forward searches (sum over words) */
     uint64_t fwd_entries;      /* frontier entries expanded by them               */
-    uint64_t reserved[18];
+    uint64_t celf_batches;     /* evaluation batches of the lazy path             */
+    uint64_t celf_fallbacks;   /* learned picks that fell back to bound order     */
+    uint64_t reserved[16];
 } im_stats;
 
 int im_stats_get(im_workspace *ws, im_stats *out);
@@ -115,11 +117,13 @@ enum {
     IM_PH_VALIDATE = 0, IM_PH_TRANSPOSE, IM_PH_MASK_GEN, IM_PH_MASK_GATHER,
     IM_PH_INIT_T0, IM_PH_INIT_T1, IM_PH_INIT_T2, IM_PH_ARGMAX, IM_PH_FORWARD,
     IM_PH_REV_T0, IM_PH_REV_T1, IM_PH_REV_T2, IM_PH_CLEAR, IM_PH_CALL, IM_PH_HUBS,
-    IM_PH_PACK, IM_PH_COUNT
+    IM_PH_PACK, IM_PH_ORDER, IM_PH_SCORE, IM_PH_PICK, IM_PH_EVAL_T0, IM_PH_EVAL_T1,
+    IM_PH_EVAL_T2, IM_PH_UPDATE, IM_PH_COUNT
 };
+#define IM_PH_MAX 24
 typedef struct im_profile {
-    double   ms[16];
-    uint64_t launches[16];
+    double   ms[IM_PH_MAX];
+    uint64_t launches[IM_PH_MAX];
 } im_profile;
 
 int im_profile_enable(im_workspace *ws, uint32_t mask);
@@ -196,6 +200,70 @@ int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
 int im_plan_launch(im_plan *plan, void *stream);
 int im_plan_stats(im_plan *plan, im_stats *out);   /* synchronous; last replay */
 int im_plan_destroy(im_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Lazy evaluation with an optional learned candidate order.
+ *
+ * Candidate-scoring network (a small MLP, 5 -> 64 -> 64 -> 1, ReLU after both
+ * hidden layers, bfloat16 weights with FP32 master copies, FP32 accumulate).
+ * Parameter vector of IM_MLP_NPARAM floats, in this order: W1[64][5], b1[64],
+ * W2[64][64], b2[64], w3[64], b3. Input x of node u (each ln(1 + .)):
+ * in-degree, out-degree, sum of out-arc probabilities, sum over out-arcs
+ * (u,v) of out-degree(v), last exact gain / R. Output: a score; the lazy
+ * path uses it only to order candidates, never to decide a pick.
+ * ------------------------------------------------------------------------ */
+#define IM_MLP_IN 5
+#define IM_MLP_HIDDEN 64
+#define IM_MLP_NPARAM 4609
+typedef struct im_mlp im_mlp;
+/* Device-resident network, all parameters zero. */
+int im_mlp_create(im_mlp **model);
+int im_mlp_destroy(im_mlp *model);
+/* Host array of IM_MLP_NPARAM finite floats -> master weights; the bfloat16
+ * copies are their nearest-even roundings; Adam state reset (synchronous). */
+int im_mlp_set_params(im_mlp *model, const float *host_params);
+/* Host outputs (either may be NULL): master weights, bfloat16 bit patterns
+ * of the copies used by every forward pass (synchronous). */
+int im_mlp_get_params(const im_mlp *model, float *host_master, uint16_t *host_bf16);
+/* y[i] = network(x[i]) for x [N][5] float, y [N] float (device). */
+int im_mlp_forward(const im_mlp *model, const float *x, uint32_t N, float *y, void *stream);
+/* Loss L = sum_i (y_i - t_i)^2 / (2N) of the bfloat16 network on x [N][5],
+ * t [N] and its gradient with respect to the parameters (grad [IM_MLP_NPARAM],
+ * loss [1], device; either may be NULL). Deterministic. N >= 1. */
+int im_mlp_loss_grad(im_mlp *model, const float *x, const float *t, uint32_t N, float *grad,
+                     float *loss, void *stream);
+/* One Adam step (Kingma & Ba 2015) on the master weights with gradient grad
+ * (device), then refresh of the bfloat16 copies. */
+int im_mlp_adam(im_mlp *model, const float *grad, float lr, float beta1, float beta2, float eps,
+                void *stream);
+/* Minibatch step: loss and gradient over the samples idx[0..nbatch) of
+ * (x, t) (idx device uint32, each < nsamples), written to grad_scratch
+ * [IM_MLP_NPARAM] and loss_out [1] (device), then one Adam step. */
+int im_mlp_train_step(im_mlp *model, const float *x, const float *t, uint32_t nsamples,
+                      const uint32_t *idx, uint32_t nbatch, float *grad_scratch, float *loss_out,
+                      float lr, float beta1, float beta2, float eps, void *stream);
+/* Static node features feat_out [n][4] float (device): the first four
+ * inputs of the network, for the graph g. */
+int im_node_features(const im_graph *g, float *feat_out, im_workspace *ws, void *stream);
+/* Training samples from a gain trace (im_select's trace_out, [T][n] uint32):
+ * sample s takes node[s] and rounds tprev[s] < tcur[s] < T:
+ * x_out[s] = (feat[node][0..3], ln(1 + trace[tprev][node] / R)),
+ * t_out[s] = ln(1 + trace[tcur][node] / R). Out-of-range entries give NaN. */
+int im_mlp_samples(const float *feat, const uint32_t *trace, uint32_t n, uint32_t T, uint32_t R,
+                   const uint32_t *node, const uint32_t *tprev, const uint32_t *tcur, uint32_t N,
+                   float *x_out, float *t_out, void *stream);
+/* k-seed selection by lazy exact evaluation (the paper's StaticGreedyCELF,
+ * Sec. 5, on the snapshots of Sec. 3.3): stale gains are upper bounds; each
+ * round evaluates candidates exactly, `batch` at a time (1..1024), until the
+ * best exact (gain, lowest id) beats the bound of every candidate not yet
+ * evaluated in the round. model = NULL: candidates in bound order; otherwise
+ * in the network's score order among those whose bound can still win (bound
+ * order when more than 2048 can). Seeds and gains are those of im_select
+ * for any model and batch. Synchronous (one host wait per batch); the
+ * number of exact evaluations is reported in im_stats.celf_evals. */
+int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uint32_t batch,
+                   const im_mlp *model, uint32_t *seeds_out, uint64_t *gains_out,
+                   im_workspace *ws, void *stream);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,7 @@ Influence Maximization", CIKM 2013 (arXiv 1212.4779). The selection runs in
 hand-written HIP kernels behind the C ABI of include/im.h; this package only
 passes torch tensors' device pointers and the current stream to it.
 """
-from .api import (Workspace, Graph, Plan, select, select_batch, initial_gains,  # noqa: F401
-                  snapshot_masks,
-                  transpose, validate)
+from ._native import ImError  # noqa: F401
+from .api import (Workspace, Graph, Plan, Mlp, select, select_batch, select_lazy,  # noqa: F401
+                  initial_gains, snapshot_masks, transpose, validate, node_features,
+                  mlp_samples)

@@ -17,11 +17,15 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_validate", "im_snapshot_masks", "im_transpose", "im_initial_gains", "im_select",
            "im_profile_enable", "im_profile_get", "im_workspace_set", "im_profile_launches",
            "im_plan_create", "im_plan_launch", "im_plan_stats", "im_plan_destroy",
-           "im_select_batch")
+           "im_select_batch", "im_mlp_create", "im_mlp_destroy", "im_mlp_set_params",
+           "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
+           "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy")
+IM_MLP_NPARAM = 4609
+IM_PH_MAX = 24
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
           "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs",
-          "pack")
+          "pack", "order", "score", "pick", "eval_t0", "eval_t1", "eval_t2", "update")
 IM_OPT_HUB_DEGREE = 1
 IM_OPT_COOP_GAIN = 2
 
@@ -46,10 +50,12 @@ class ImStats(ctypes.Structure):
     _fields_ = ([(f, ctypes.c_uint64) for f in STAT_FIELDS] +
                 [(f, (ctypes.c_uint64 * 3) * 3) for f in TIER_FIELDS] +
                 [("fwd_levels", ctypes.c_uint64), ("fwd_entries", ctypes.c_uint64),
-                 ("reserved", ctypes.c_uint64 * 18)])
+                 ("celf_batches", ctypes.c_uint64), ("celf_fallbacks", ctypes.c_uint64),
+                 ("reserved", ctypes.c_uint64 * 16)])
 
     def as_dict(self):
-        d = {f: int(getattr(self, f)) for f in STAT_FIELDS + ("fwd_levels", "fwd_entries")}
+        d = {f: int(getattr(self, f)) for f in STAT_FIELDS + ("fwd_levels", "fwd_entries",
+                                                               "celf_batches", "celf_fallbacks")}
         for f in TIER_FIELDS:
             arr = getattr(self, f)
             for p, pn in enumerate(PASSES):
@@ -61,7 +67,7 @@ class ImStats(ctypes.Structure):
 
 
 class ImProfile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_uint64 * 16)]
+    _fields_ = [("ms", ctypes.c_double * IM_PH_MAX), ("launches", ctypes.c_uint64 * IM_PH_MAX)]
 
 
 class ImError(RuntimeError):
@@ -99,6 +105,18 @@ def lib():
         L.im_plan_destroy.argtypes = [p]
         L.im_select_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, p, p]
         L.im_profile_get.argtypes = [p, ctypes.POINTER(ImProfile)]
+        f32 = ctypes.c_float
+        L.im_mlp_create.argtypes = [ctypes.POINTER(p)]
+        L.im_mlp_destroy.argtypes = [p]
+        L.im_mlp_set_params.argtypes = [p, p]
+        L.im_mlp_get_params.argtypes = [p, p, p]
+        L.im_mlp_forward.argtypes = [p, p, u32, p, p]
+        L.im_mlp_loss_grad.argtypes = [p, p, p, u32, p, p, p]
+        L.im_mlp_adam.argtypes = [p, p, f32, f32, f32, f32, p]
+        L.im_mlp_train_step.argtypes = [p, p, p, u32, p, u32, p, p, f32, f32, f32, f32, p]
+        L.im_node_features.argtypes = [G, p, p, p]
+        L.im_mlp_samples.argtypes = [p, p, u32, u32, u32, p, p, p, u32, p, p, p]
+        L.im_select_lazy.argtypes = [G, u32, u32, u64, u32, p, p, p, p, p]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

@@ -260,3 +260,111 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# lazy evaluation and the candidate-scoring network
+# ---------------------------------------------------------------------------
+MLP_NPARAM = N.IM_MLP_NPARAM
+MLP_IN = 5
+
+
+class Mlp:
+    """Device-resident candidate-scoring network (bfloat16 weights, FP32 masters)."""
+
+    def __init__(self, params=None):
+        h = ctypes.c_void_p()
+        N.check(N.lib().im_mlp_create(ctypes.byref(h)))
+        self.handle = h
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAM,):
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
+        N.check(N.lib().im_mlp_set_params(self.handle, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def params(self):
+        """(master float32 [P], bfloat16 copies as uint16 bit patterns [P])."""
+        m = np.zeros(MLP_NPARAM, np.float32)
+        b = np.zeros(MLP_NPARAM, np.uint16)
+        N.check(N.lib().im_mlp_get_params(self.handle, m.ctypes.data_as(ctypes.c_void_p),
+                                          b.ctypes.data_as(ctypes.c_void_p)))
+        return m, b
+
+    def forward(self, x):
+        """x: float32 [N, 5] on the GPU -> float32 [N]."""
+        x = x.contiguous()
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        N.check(N.lib().im_mlp_forward(self.handle, _ptr(x), x.shape[0], _ptr(y), _stream(x.device)))
+        return y
+
+    def loss_grad(self, x, t):
+        """(loss float32 [1], grad float32 [P]) of sum (y - t)^2 / (2N)."""
+        x, t = x.contiguous(), t.contiguous()
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        N.check(N.lib().im_mlp_loss_grad(self.handle, _ptr(x), _ptr(t), x.shape[0], _ptr(g),
+                                         _ptr(loss), _stream(x.device)))
+        return loss, g
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        N.check(N.lib().im_mlp_adam(self.handle, _ptr(grad.contiguous()), lr, beta1, beta2, eps,
+                                    _stream(grad.device)))
+
+    def train_step(self, x, t, idx, grad_scratch, loss_out, lr=1e-3, beta1=0.9, beta2=0.999,
+                   eps=1e-8):
+        """One minibatch (rows idx of x, t) gradient + Adam step, all on the GPU."""
+        N.check(N.lib().im_mlp_train_step(self.handle, _ptr(x), _ptr(t), x.shape[0], _ptr(idx),
+                                          idx.shape[0], _ptr(grad_scratch), _ptr(loss_out), lr,
+                                          beta1, beta2, eps, _stream(x.device)))
+
+    def close(self):
+        if self.handle:
+            N.lib().im_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def node_features(graph, ws=None):
+    """Static network inputs float32 [n, 4]."""
+    out = torch.empty((graph.n, 4), dtype=torch.float32, device=graph.device)
+    g = graph.c_struct()
+    ws = _ws(ws, graph.device)
+    N.check(N.lib().im_node_features(ctypes.byref(g), _ptr(out), ws.handle, _stream(graph.device)))
+    return out
+
+
+def mlp_samples(feat, trace, R, node, tprev, tcur):
+    """Training inputs/targets gathered from a gain trace (int32 tensors on the GPU)."""
+    T, n = trace.shape
+    Ns = node.shape[0]
+    x = torch.empty((Ns, MLP_IN), dtype=torch.float32, device=feat.device)
+    t = torch.empty(Ns, dtype=torch.float32, device=feat.device)
+    N.check(N.lib().im_mlp_samples(_ptr(feat.contiguous()), _ptr(trace.contiguous()), n, T, R,
+                                   _ptr(node.contiguous()), _ptr(tprev.contiguous()),
+                                   _ptr(tcur.contiguous()), Ns, _ptr(x), _ptr(t),
+                                   _stream(feat.device)))
+    return x, t
+
+
+def select_lazy(graph, R, k, seed, batch=64, model=None, ws=None):
+    """Lazy exact evaluation (bound order, or `model`'s score order).
+
+    Returns (seeds int64 [k], gains int64 [k]) -- always those of select().
+    """
+    dev = graph.device
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    gains = torch.empty(k, dtype=torch.int64, device=dev)
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_select_lazy(ctypes.byref(g), R, k, seed, batch,
+                                   model.handle if model is not None else ctypes.c_void_p(0),
+                                   _ptr(seeds), _ptr(gains), ws.handle, _stream(dev)))
+    return _u32(seeds), gains

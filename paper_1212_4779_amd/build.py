@@ -5,7 +5,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libim.so")
-SOURCES = [os.path.join(PKG, "csrc", "im.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "im.hip"), os.path.join(PKG, "csrc", "mlp.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

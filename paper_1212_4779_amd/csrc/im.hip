@@ -30,13 +30,17 @@
 
 #include "im.h"
 #include "im_bfs.h"
+#include "im_host.h"
+#include "im_mlp.h"
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
+static_assert(IM_PH_COUNT <= IM_PH_MAX, "phase table too small");
+
 static thread_local std::string g_err;
 
-static int fail(int code, const char *fmt, ...)
+int im_fail(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -46,13 +50,6 @@ static int fail(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
-
-#define HIPCHK(call)                                                               \
-    do {                                                                           \
-        hipError_t e_ = (call);                                                    \
-        if (e_ != hipSuccess)                                                      \
-            return fail(IM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
-    } while (0)
 
 extern "C" const char *im_last_error(void) { return g_err.c_str(); }
 
@@ -1023,6 +1020,14 @@ struct im_workspace {
     // block engine slots
     uint64_t *b_reach = nullptr, *b_pend = nullptr, *b_fdel = nullptr;
     uint32_t *b_qa = nullptr, *b_qb = nullptr, *b_vis = nullptr;
+    // lazy evaluation (A9)
+    uint32_t cap_celf = 0;
+    uint64_t cap_sort = 0;
+    uint32_t *c_bound = nullptr, *c_fresh = nullptr, *c_ev = nullptr, *c_ordB = nullptr,
+             *c_ordS = nullptr, *c_E = nullptr, *c_cand = nullptr, *c_ctl = nullptr;
+    uint8_t *c_moved = nullptr;
+    float *c_score = nullptr, *c_feat = nullptr;
+    unsigned long long *c_sort = nullptr;
     // misc
     unsigned long long *stats = nullptr;
     uint32_t *err = nullptr;
@@ -1074,7 +1079,7 @@ static int dalloc(Tv **p, uint64_t cnt)
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
-        return fail(IM_ENOMEM, "hipMalloc of %llu bytes failed: %s",
+        return im_fail(IM_ENOMEM, "hipMalloc of %llu bytes failed: %s",
                     (unsigned long long)(cnt * sizeof(Tv)), hipGetErrorString(e));
     }
     return IM_OK;
@@ -1089,7 +1094,7 @@ static void dfree(Tv *&p)
 
 extern "C" int im_workspace_create(im_workspace **out)
 {
-    if (!out) return fail(IM_EINVAL, "im_workspace_create: null output pointer");
+    if (!out) return im_fail(IM_EINVAL, "im_workspace_create: null output pointer");
     im_workspace *ws = new im_workspace();
     HIPCHK(hipGetDevice(&ws->device));
     hipDeviceProp_t prop;
@@ -1133,6 +1138,9 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->b_node_inst); dfree(ws->b_mcol); dfree(ws->b_mprob); dfree(ws->b_u32);
     dfree(ws->b_u64); dfree(ws->b_desc);
     if (ws->b_host) (void)hipHostFree(ws->b_host);
+    dfree(ws->c_bound); dfree(ws->c_fresh); dfree(ws->c_ev); dfree(ws->c_ordB); dfree(ws->c_ordS);
+    dfree(ws->c_E); dfree(ws->c_cand); dfree(ws->c_ctl); dfree(ws->c_moved); dfree(ws->c_score);
+    dfree(ws->c_feat); dfree(ws->c_sort);
     dfree(ws->stats); dfree(ws->err);
     if (ws->host_err) (void)hipHostFree(ws->host_err);
     if (ws->host_stats) (void)hipHostFree(ws->host_stats);
@@ -1232,13 +1240,13 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
 // ---------------------------------------------------------------------------
 static int check_args(const im_graph *g, uint32_t R)
 {
-    if (!g) return fail(IM_EINVAL, "null graph");
-    if (g->m >= (1ull << 32)) return fail(IM_EINVAL, "m = %llu must be < 2^32", (unsigned long long)g->m);
-    if (!g->row_ptr) return fail(IM_EINVAL, "null row_ptr");
-    if (g->m && (!g->col || !g->prob)) return fail(IM_EINVAL, "null col or prob");
-    if (R == 0 || R > IM_R_MAX) return fail(IM_EINVAL, "R = %u must be in [1, %u]", R, IM_R_MAX);
+    if (!g) return im_fail(IM_EINVAL, "null graph");
+    if (g->m >= (1ull << 32)) return im_fail(IM_EINVAL, "m = %llu must be < 2^32", (unsigned long long)g->m);
+    if (!g->row_ptr) return im_fail(IM_EINVAL, "null row_ptr");
+    if (g->m && (!g->col || !g->prob)) return im_fail(IM_EINVAL, "null col or prob");
+    if (R == 0 || R > IM_R_MAX) return im_fail(IM_EINVAL, "R = %u must be in [1, %u]", R, IM_R_MAX);
     if ((uint64_t)g->n * R >= (1ull << 32))
-        return fail(IM_EOVERFLOW, "n * R = %llu must be < 2^32", (unsigned long long)g->n * R);
+        return im_fail(IM_EOVERFLOW, "n * R = %llu must be < 2^32", (unsigned long long)g->n * R);
     return IM_OK;
 }
 
@@ -1253,11 +1261,11 @@ static int validate(const im_graph *g, im_workspace *ws, hipStream_t s, uint32_t
     HIPCHK(hipMemcpyAsync(ws->host_err, ws->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     uint32_t e = *ws->host_err;
-    if (e & ERR_ROW0) return fail(IM_EINVAL, "row_ptr[0] != 0");
-    if (e & ERR_ROWN) return fail(IM_EINVAL, "row_ptr[n] != m");
-    if (e & (ERR_ROWDEC | ERR_ROWBIG)) return fail(IM_EINVAL, "row_ptr is not non-decreasing within [0, m]");
-    if (e & ERR_COL) return fail(IM_EINVAL, "col entry >= n");
-    if (e & ERR_PROB) return fail(IM_EINVAL, "prob outside [0, 1] or NaN");
+    if (e & ERR_ROW0) return im_fail(IM_EINVAL, "row_ptr[0] != 0");
+    if (e & ERR_ROWN) return im_fail(IM_EINVAL, "row_ptr[n] != m");
+    if (e & (ERR_ROWDEC | ERR_ROWBIG)) return im_fail(IM_EINVAL, "row_ptr is not non-decreasing within [0, m]");
+    if (e & ERR_COL) return im_fail(IM_EINVAL, "col entry >= n");
+    if (e & ERR_PROB) return im_fail(IM_EINVAL, "prob outside [0, 1] or NaN");
     return IM_OK;
 }
 
@@ -1431,7 +1439,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
                                                   dim3(FWD_NT), args, 0, s);
         if (e != hipSuccess)
-            return fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
+            return im_fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
     }
 
     uint32_t *bcnt = ws->pk, *bcur = ws->pk + 64 * 64, *gcnt = ws->pk + 2 * 64 * 64,
@@ -1522,12 +1530,542 @@ static int enqueue_rounds(const im_graph *g, uint32_t R, uint32_t k, uint32_t *s
 }
 
 // ---------------------------------------------------------------------------
+// A9: lazy evaluation (the StaticGreedyCELF variant of Sec. 5) with an
+// optional learned candidate order
+// ---------------------------------------------------------------------------
+// Every unselected node u keeps a bound b_u: its exact gain when it was last
+// evaluated (at first its initial count). Gains only shrink as seeds are
+// added (the spread is submodular, Sec. 3.2), so b_u bounds u's current gain.
+// A round evaluates candidates exactly, a batch at a time, with the covered
+// snapshots pruned (the count engine with prune = covered), until the best
+// exact key (gain, lowest id) of the round beats the bound key of every
+// unselected node not evaluated in the round. That best is the argmax of
+// the exact gains, so the seed and its gain equal the dynamic update's.
+//
+// Candidate order: bound order (plain), or the network's score among the
+// nodes whose bound can still win (learned). An order is kept as the node
+// list sorted by the keys the nodes had at the last rebuild (ordB, ordS);
+// nodes evaluated since ("moved") sit in a short list E, which every pick
+// filters, sorts in LDS and merges with a walk down the sorted list.
+constexpr int CP_NT = 1024;
+constexpr uint32_t CELF_BMAX = 1024;   // largest batch
+constexpr uint32_t CELF_CAPE = 2048;   // moved nodes held before the orders are rebuilt
+constexpr uint32_t CELF_CAPW = 2048;   // can-win nodes gathered for a learned pick
+constexpr int SORT_TILE = 4096;        // keys sorted per workgroup in LDS
+// control words: candidate count, |E|, walk heads of ordB / ordS, then the
+// evaluation's tier counters
+enum { CC_NCAND = 0, CC_NE = 1, CC_HEADB = 2, CC_HEADS = 3, CC_EVCTR = 8, CC_COUNT = 8 + PH_CTRS };
+
+__device__ __forceinline__ unsigned long long node_key(uint32_t primary, uint32_t u)
+{
+    return ((unsigned long long)primary << 32) | (0xFFFFFFFFu - u);
+}
+
+__device__ __forceinline__ uint32_t key_node(unsigned long long key)
+{
+    return 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+}
+
+// order-preserving map of a float score to uint32
+__device__ __forceinline__ uint32_t score_bits(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// static inputs of the network (see im_mlp.h), from the out-CSR and the
+// reverse CSR's row offsets
+__global__ void k_features(const uint32_t *row, const uint32_t *col, const float *prob,
+                           const uint32_t *in_row, uint32_t n, float *feat)
+{
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const uint32_t rs = row[u], re = row[u + 1];
+        float ps = 0.0f;
+        uint64_t two = 0;
+        for (uint32_t e = rs; e < re; e++) {
+            ps += prob[e];
+            const uint32_t v = col[e];
+            two += row[v + 1] - row[v];
+        }
+        feat[(uint64_t)u * 4 + 0] = log1pf((float)(in_row[u + 1] - in_row[u]));
+        feat[(uint64_t)u * 4 + 1] = log1pf((float)(re - rs));
+        feat[(uint64_t)u * 4 + 2] = log1pf(ps);
+        feat[(uint64_t)u * 4 + 3] = log1pf((float)two);
+    }
+}
+
+// score[u] = network(feat[u], ln(1 + bound[u] / R)) for u in list[0..cnt)
+// (list = nullptr: u = 0..cnt-1; cnt_dev != nullptr: count read on the device)
+__global__ __launch_bounds__(256) void k_celf_score(const uint16_t *wb, const float *feat,
+                                                    const uint32_t *bound, float invR,
+                                                    const uint32_t *list, uint32_t cnt,
+                                                    const uint32_t *cnt_dev, float *score)
+{
+    __shared__ float sw[MLP_NP];
+    mlp_stage(wb, sw);
+    const uint32_t c = cnt_dev ? *cnt_dev : cnt;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < c; i += gridDim.x * 256u) {
+        const uint32_t u = list ? list[i] : i;
+        float x[MLP_IN];
+#pragma unroll
+        for (int q = 0; q < 4; q++) x[q] = feat[(uint64_t)u * 4 + q];
+        x[4] = log1pf((float)bound[u] * invR);
+        score[u] = mlp_eval(sw, x);
+    }
+}
+
+// sort keys: node_key(primary(u), u) for u < n, 0 for the padding up to len
+__global__ void k_order_keys(const uint32_t *bound, const float *score, uint32_t n, uint64_t len,
+                             unsigned long long *keys)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < len;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        unsigned long long k = 0;
+        if (i < n) {
+            const uint32_t u = (uint32_t)i;
+            k = node_key(score ? score_bits(score[u]) : bound[u], u);
+        }
+        keys[i] = k;
+    }
+}
+
+// Bitonic sorting network, descending. Step (kk, j) compares i with i ^ j;
+// blocks with (i & kk) == 0 go descending, the others ascending.
+__device__ __forceinline__ void bitonic_cx(unsigned long long *a, uint64_t i, uint64_t l,
+                                           uint64_t gi, uint64_t kk)
+{
+    const unsigned long long x = a[i], y = a[l];
+    const bool desc = (gi & kk) == 0;
+    if (desc ? x < y : x > y) { a[i] = y; a[l] = x; }
+}
+
+// all steps with j < SORT_TILE of stages kk in [kk_lo, kk_hi] on one tile
+// held in LDS (kk_lo = 2: a full local sort)
+__global__ __launch_bounds__(1024) void k_bitonic_tile(unsigned long long *keys, uint64_t kk_lo,
+                                                       uint64_t kk_hi)
+{
+    __shared__ unsigned long long t[SORT_TILE];
+    const uint64_t base = (uint64_t)blockIdx.x * SORT_TILE;
+    for (int i = threadIdx.x; i < SORT_TILE; i += 1024) t[i] = keys[base + i];
+    __syncthreads();
+    for (uint64_t kk = kk_lo; kk <= kk_hi; kk <<= 1) {
+        for (uint64_t j = std::min<uint64_t>(kk >> 1, SORT_TILE / 2); j >= 1; j >>= 1) {
+            for (int p = threadIdx.x; p < SORT_TILE / 2; p += 1024) {
+                const uint64_t i = 2 * j * (p / j) + (p % j);
+                bitonic_cx(t, i, i + j, base + i, kk);
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < SORT_TILE; i += 1024) keys[base + i] = t[i];
+}
+
+__global__ void k_bitonic_step(unsigned long long *keys, uint64_t len, uint64_t kk, uint64_t j)
+{
+    const uint64_t half = len / 2;
+    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < half;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = 2 * j * (p / j) + (p % j);
+        bitonic_cx(keys, i, i + j, i, kk);
+    }
+}
+
+__global__ void k_order_extract(const unsigned long long *keys, uint32_t n, uint32_t *ord)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        ord[i] = key_node(keys[i]);
+}
+
+__global__ void k_celf_reset(uint32_t *ctl)
+{
+    if (threadIdx.x == 0) { ctl[CC_NE] = 0; ctl[CC_HEADB] = 0; ctl[CC_HEADS] = 0; }
+}
+
+struct PickArgs {
+    uint32_t n, t, B;
+    int learned;
+    const uint32_t *ordB, *ordS;
+    const uint32_t *bound;
+    const float *score;
+    const uint32_t *fresh;
+    const uint8_t *sel, *moved;
+    const uint32_t *E;
+    uint32_t *ctl;
+    const unsigned long long *best;
+    uint32_t *cand;
+    uint32_t *ev;
+    unsigned long long *stats;
+};
+
+struct PickLds {
+    unsigned long long a[CELF_CAPW];                 // walk result, descending
+    unsigned long long e[CELF_CAPW + CELF_CAPE];     // moved nodes (and the learned union)
+    uint32_t wsum[CP_NT / 64 + 1];
+    uint32_t na, ne, done, full, lead, first;
+};
+
+// Walk ord from ctl[head] and collect, in list order, the keys of nodes that
+// are neither selected, moved nor evaluated this round and whose key exceeds
+// stop, up to cap. Advances ctl[head] past leading entries that can never be
+// taken again (selected or moved). Sets L.na; L.full when more may follow.
+template <typename KeyOf>
+__device__ void pick_walk(const PickArgs &a, const uint32_t *ord, int head, KeyOf key_of,
+                          unsigned long long stop, uint32_t cap, PickLds &L)
+{
+    const int tid = threadIdx.x;
+    const uint32_t h0 = a.ctl[head];
+    if (tid == 0) { L.na = 0; L.done = 0; L.full = 0; L.lead = 1; }
+    __syncthreads();
+    for (uint64_t p = h0; p < a.n; p += CP_NT) {
+        if (tid == 0) L.first = CP_NT;
+        __syncthreads();
+        const uint64_t i = p + tid;
+        bool take = false, stopped = false;
+        unsigned long long key = 0;
+        if (i < a.n) {
+            const uint32_t u = ord[i];
+            const bool gone = a.sel[u] || a.moved[u];
+            if (!gone) atomicMin(&L.first, (uint32_t)tid);
+            if (!gone && a.fresh[u] != a.t + 1) {
+                key = key_of(u);
+                take = key > stop;
+                stopped = !take;   // keys descend along the list: nothing later passes
+            }
+        }
+        if (__syncthreads_or(stopped) && tid == 0) L.done = 1;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<CP_NT>(take ? 1u : 0u, L.wsum, &tot);
+        const uint32_t na = L.na;
+        if (take && na + ex < cap) L.a[na + ex] = key;
+        __syncthreads();
+        if (tid == 0) {
+            if (L.lead) {
+                if (L.first < CP_NT) { a.ctl[head] = (uint32_t)(p + L.first); L.lead = 0; }
+                else a.ctl[head] = (uint32_t)std::min<uint64_t>(p + CP_NT, a.n);
+            }
+            if (na + tot >= cap) {
+                L.full = (na + tot > cap) || (!L.done && p + CP_NT < a.n);
+                L.na = cap;
+                L.done = 1;
+            } else {
+                L.na = na + tot;
+            }
+        }
+        __syncthreads();
+        if (L.done) break;
+    }
+    __syncthreads();
+}
+
+// sort L.e[0..cnt) descending in LDS (cnt <= CELF_CAPW + CELF_CAPE)
+__device__ void lds_sort_desc(unsigned long long *e, uint32_t cnt)
+{
+    uint32_t len = 1;
+    while (len < cnt) len <<= 1;
+    for (uint32_t i = cnt + threadIdx.x; i < len; i += CP_NT) e[i] = 0;
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= len; kk <<= 1)
+        for (uint32_t j = kk >> 1; j >= 1; j >>= 1) {
+            for (uint32_t p = threadIdx.x; p < len / 2; p += CP_NT) {
+                const uint32_t i = 2 * j * (p / j) + (p % j);
+                bitonic_cx(e, i, i + j, i, kk);
+            }
+            __syncthreads();
+        }
+}
+
+// number of entries of the descending list s[0..cnt) greater than x
+__device__ __forceinline__ uint32_t count_greater(const unsigned long long *s, uint32_t cnt,
+                                                  unsigned long long x)
+{
+    uint32_t lo = 0, hi = cnt;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (s[mid] > x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// moved nodes passing the pick's filter, keyed by key_of, into L.e (unsorted)
+template <typename KeyOf>
+__device__ void pick_moved(const PickArgs &a, KeyOf key_of, unsigned long long stop_bound, PickLds &L)
+{
+    if (threadIdx.x == 0) L.ne = 0;
+    __syncthreads();
+    const uint32_t ne = min(a.ctl[CC_NE], CELF_CAPE);
+    for (uint32_t i = threadIdx.x; i < ne; i += CP_NT) {
+        const uint32_t u = a.E[i];
+        if (a.sel[u] || a.fresh[u] == a.t + 1) continue;
+        if (node_key(a.bound[u], u) <= stop_bound) continue;
+        L.e[atomicAdd(&L.ne, 1u)] = key_of(u);
+    }
+    __syncthreads();
+}
+
+// top B of the descending lists L.a[0..na) and L.e[0..ne) -> cand (node ids)
+__device__ uint32_t pick_merge(const PickArgs &a, PickLds &L, uint32_t na, uint32_t ne)
+{
+    for (uint32_t i = threadIdx.x; i < na; i += CP_NT) {
+        const uint32_t r = i + count_greater(L.e, ne, L.a[i]);
+        if (r < a.B) a.cand[r] = key_node(L.a[i]);
+    }
+    for (uint32_t j = threadIdx.x; j < ne; j += CP_NT) {
+        const uint32_t r = j + count_greater(L.a, na, L.e[j]);
+        if (r < a.B) a.cand[r] = key_node(L.e[j]);
+    }
+    return min(a.B, na + ne);
+}
+
+__global__ __launch_bounds__(CP_NT) void k_celf_pick(PickArgs a)
+{
+    __shared__ PickLds L;
+    const unsigned long long best = *a.best;
+    auto bkey = [&](uint32_t u) { return node_key(a.bound[u], u); };
+    auto skey = [&](uint32_t u) { return node_key(score_bits(a.score[u]), u); };
+    uint32_t ncand = 0;
+    bool fallback = false;
+    if (!a.learned) {
+        pick_walk(a, a.ordB, CC_HEADB, bkey, best, a.B, L);
+        pick_moved(a, bkey, best, L);
+        const uint32_t na = L.na, ne = L.ne;
+        lds_sort_desc(L.e, ne);
+        ncand = pick_merge(a, L, na, ne);
+    } else if (best == 0) {
+        // first batch of the round: every unselected node can still win
+        pick_walk(a, a.ordS, CC_HEADS, skey, 0ull, a.B, L);
+        pick_moved(a, skey, 0ull, L);
+        const uint32_t na = L.na, ne = L.ne;
+        lds_sort_desc(L.e, ne);
+        ncand = pick_merge(a, L, na, ne);
+    } else {
+        // gather every node whose bound can still win, then order by score
+        pick_walk(a, a.ordB, CC_HEADB, bkey, best, CELF_CAPW, L);
+        pick_moved(a, bkey, best, L);
+        const uint32_t na = L.na, ne = L.ne;
+        if (L.full) {
+            fallback = true;
+            lds_sort_desc(L.e, ne);
+            ncand = pick_merge(a, L, na, ne);
+        } else {
+            // re-key the union by score
+            for (uint32_t j = threadIdx.x; j < ne; j += CP_NT) L.e[j] = skey(key_node(L.e[j]));
+            for (uint32_t i = threadIdx.x; i < na; i += CP_NT) L.e[ne + i] = skey(key_node(L.a[i]));
+            __syncthreads();
+            lds_sort_desc(L.e, na + ne);
+            ncand = min(a.B, na + ne);
+            for (uint32_t i = threadIdx.x; i < ncand; i += CP_NT) a.cand[i] = key_node(L.e[i]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ncand; i += CP_NT) a.ev[a.cand[i]] = 0;
+    if (threadIdx.x < PH_CTRS) a.ctl[CC_EVCTR + threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        a.ctl[CC_NCAND] = ncand;
+        a.stats[ST_CELF_EVALS] += ncand;
+        if (ncand) a.stats[ST_CELF_BATCHES] += 1;
+        if (fallback) a.stats[ST_CELF_FALLBACKS] += 1;
+    }
+}
+
+// record the batch's exact gains: new bounds, fresh marks, the round's best
+// key, moved list and (learned) new scores
+__global__ __launch_bounds__(256) void k_celf_update(const uint32_t *cand, uint32_t *ctl,
+                                                     const uint32_t *ev, uint32_t *bound,
+                                                     uint32_t *fresh, uint8_t *moved, uint32_t *E,
+                                                     unsigned long long *best, uint32_t t,
+                                                     const uint16_t *wb, const float *feat,
+                                                     float invR, float *score)
+{
+    __shared__ float sw[MLP_NP];
+    if (wb) mlp_stage(wb, sw);
+    const uint32_t ncand = ctl[CC_NCAND];
+    for (uint32_t i = threadIdx.x; i < ncand; i += 256) {
+        const uint32_t c = cand[i];
+        const uint32_t g = ev[c];
+        bound[c] = g;
+        fresh[c] = t + 1;
+        atomicMax(best, node_key(g, c));
+        if (!moved[c]) {
+            moved[c] = 1;
+            const uint32_t q = atomicAdd(&ctl[CC_NE], 1u);
+            if (q < CELF_CAPE) E[q] = c;
+        }
+        if (wb) {
+            float x[MLP_IN];
+#pragma unroll
+            for (int q = 0; q < 4; q++) x[q] = feat[(uint64_t)c * 4 + q];
+            x[4] = log1pf((float)g * invR);
+            score[c] = mlp_eval(sw, x);
+        }
+    }
+}
+
+static int reserve_celf(im_workspace *ws, uint32_t n)
+{
+    int rc;
+    uint64_t len = SORT_TILE;
+    while (len < n) len <<= 1;
+    if (n > ws->cap_celf || !ws->c_bound) {
+        const uint32_t cn = std::max(n, ws->cap_celf);
+        if ((rc = dalloc(&ws->c_bound, cn)) || (rc = dalloc(&ws->c_fresh, cn)) ||
+            (rc = dalloc(&ws->c_moved, cn)) || (rc = dalloc(&ws->c_ev, cn)) ||
+            (rc = dalloc(&ws->c_ordB, cn)) || (rc = dalloc(&ws->c_ordS, cn)) ||
+            (rc = dalloc(&ws->c_score, cn)) || (rc = dalloc(&ws->c_feat, 4ull * cn)) ||
+            (rc = dalloc(&ws->c_E, CELF_CAPE)) || (rc = dalloc(&ws->c_cand, CELF_BMAX)) ||
+            (rc = dalloc(&ws->c_ctl, CC_COUNT)))
+            return rc;
+        ws->cap_celf = cn;
+    }
+    if (len > ws->cap_sort) {
+        if ((rc = dalloc(&ws->c_sort, len))) return rc;
+        ws->cap_sort = len;
+    }
+    return IM_OK;
+}
+
+// sort all nodes by (primary desc, id asc): primary = score when given, else bound
+static void build_order(im_workspace *ws, uint32_t n, const float *score, uint32_t *ord,
+                        hipStream_t s)
+{
+    uint64_t len = SORT_TILE;
+    while (len < n) len <<= 1;
+    k_order_keys<<<grid_for(len, 256), 256, 0, s>>>(ws->c_bound, score, n, len, ws->c_sort);
+    const unsigned tiles = (unsigned)(len / SORT_TILE);
+    k_bitonic_tile<<<tiles, 1024, 0, s>>>(ws->c_sort, 2, SORT_TILE);
+    for (uint64_t kk = 2 * SORT_TILE; kk <= len; kk <<= 1) {
+        for (uint64_t j = kk >> 1; j >= SORT_TILE; j >>= 1)
+            k_bitonic_step<<<grid_for(len / 2, 256), 256, 0, s>>>(ws->c_sort, len, kk, j);
+        k_bitonic_tile<<<tiles, 1024, 0, s>>>(ws->c_sort, kk, kk);
+    }
+    k_order_extract<<<grid_for(n, 256), 256, 0, s>>>(ws->c_sort, n, ord);
+}
+
+static void rebuild_orders(im_workspace *ws, uint32_t n, bool learned, hipStream_t s)
+{
+    PhaseTimer pt(ws, IM_PH_ORDER, s);
+    build_order(ws, n, nullptr, ws->c_ordB, s);
+    if (learned) build_order(ws, n, ws->c_score, ws->c_ordS, s);
+    fill<uint8_t>(ws->c_moved, n, (uint8_t)0, s);
+    k_celf_reset<<<1, 64, 0, s>>>(ws->c_ctl);
+}
+
+// A5 without A6: commit the round's argmax key keys[t] (forward search,
+// covered |= newly covered) and clear the newly-covered words
+static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seeds_out,
+                       uint64_t *gains_out, im_workspace *ws, hipStream_t s)
+{
+    const uint32_t n = g->n, W = (R + 63) / 64;
+    FwdArgs f;
+    f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
+    f.hub = hub_lists(ws, 0);
+    f.n = n; f.R = R; f.W = W;
+    f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend; f.fdel = ws->ffdel;
+    f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
+    f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
+    f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
+    f.key = ws->keys + t; f.t = t; f.b = ws->batch;
+    f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
+    f.stats = ws->stats;
+    {
+        PhaseTimer pt(ws, IM_PH_FORWARD, s);
+        k_forward_block<<<W, FWB_NT, 0, s>>>(f);
+        void *args[] = {&f};
+        const unsigned fg = std::min<unsigned>(ws->fwd_grid, 16u * W);
+        hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
+                                                  dim3(FWD_NT), args, 0, s);
+        if (e != hipSuccess)
+            return im_fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
+    }
+    {
+        PhaseTimer pt(ws, IM_PH_CLEAR, s);
+        k_clear_newly<<<grid_for(n, 256, 1024), 256, 0, s>>>(ws->newly, ws->tnodes, ws->tcounts, n, W);
+    }
+    return IM_OK;
+}
+
+static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, const im_mlp *model,
+                       uint32_t *seeds_out, uint64_t *gains_out, im_workspace *ws, hipStream_t s)
+{
+    int rc;
+    const uint32_t n = g->n, W = (R + 63) / 64;
+    const bool learned = model != nullptr;
+    const float invR = 1.0f / (float)R;
+    if ((rc = reserve_celf(ws, n))) return rc;
+    k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, ws->c_bound, n);
+    fill<uint32_t>(ws->c_fresh, n, 0u, s);
+    fill<uint32_t>(ws->c_ctl, CC_COUNT, 0u, s);
+    if (learned) {
+        PhaseTimer pt(ws, IM_PH_SCORE, s);
+        k_features<<<grid_for(n, 256), 256, 0, s>>>(ws->row32, g->col, g->prob, ws->in_row, n,
+                                                    ws->c_feat);
+        k_celf_score<<<grid_for(n, 256, 4096), 256, 0, s>>>(model->wb, ws->c_feat, ws->c_bound, invR,
+                                                            nullptr, n, nullptr, ws->c_score);
+    }
+    rebuild_orders(ws, n, learned, s);
+    HIPCHK(hipGetLastError());
+    uint64_t moved_bound = 0;  // upper bound of |E| since the last rebuild
+    PickArgs pa;
+    pa.n = n; pa.B = B; pa.learned = learned ? 1 : 0;
+    pa.ordB = ws->c_ordB; pa.ordS = ws->c_ordS; pa.bound = ws->c_bound; pa.score = ws->c_score;
+    pa.fresh = ws->c_fresh; pa.sel = ws->sel; pa.moved = ws->c_moved; pa.E = ws->c_E;
+    pa.ctl = ws->c_ctl; pa.cand = ws->c_cand; pa.ev = ws->c_ev; pa.stats = ws->stats;
+    // round 0: every bound is exact (the initial counts), so the round's
+    // argmax needs no evaluation
+    {
+        PhaseTimer pt(ws, IM_PH_ARGMAX, s);
+        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys, ws->batch, 0,
+                                                         ws->pk, (uint32_t)PK_ZERO);
+    }
+    if ((rc = commit_seed(g, R, 0, seeds_out, gains_out, ws, s))) return rc;
+    for (uint32_t t = 1; t < k; t++) {
+        pa.t = t;
+        pa.best = ws->keys + t;
+        for (;;) {
+            if (moved_bound + B > CELF_CAPE) {
+                rebuild_orders(ws, n, learned, s);
+                moved_bound = 0;
+            }
+            {
+                PhaseTimer pt(ws, IM_PH_PICK, s);
+                k_celf_pick<<<1, CP_NT, 0, s>>>(pa);
+            }
+            HIPCHK(hipMemcpyAsync(ws->host_err, ws->c_ctl + CC_NCAND, sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const uint32_t ncand = *ws->host_err;
+            if (ncand == 0) break;
+            BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W);
+            a.cand = ws->c_cand;
+            a.ncand = ncand;
+            a.ntasks = ncand * W;
+            a.gain = ws->c_ev;
+            a.prune = ws->covered;
+            a.hub = hub_lists(ws, 0);
+            a.pass = PASS_EVAL;
+            a.st_trav = ST_TRAV_EVAL;
+            run_tiers<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T0, s);
+            {
+                PhaseTimer pt(ws, IM_PH_UPDATE, s);
+                k_celf_update<<<1, 256, 0, s>>>(ws->c_cand, ws->c_ctl, ws->c_ev, ws->c_bound,
+                                                ws->c_fresh, ws->c_moved, ws->c_E, ws->keys + t, t,
+                                                learned ? model->wb : nullptr, ws->c_feat, invR,
+                                                ws->c_score);
+            }
+            moved_bound += ncand;
+        }
+        if ((rc = commit_seed(g, R, t, seeds_out, gains_out, ws, s))) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" int im_validate(const im_graph *g, uint32_t R, void *stream)
 {
-    if (!g) return fail(IM_EINVAL, "null graph");
-    int rc = R ? check_args(g, R) : (g->m >= (1ull << 32) ? fail(IM_EINVAL, "m >= 2^32") : IM_OK);
+    if (!g) return im_fail(IM_EINVAL, "null graph");
+    int rc = R ? check_args(g, R) : (g->m >= (1ull << 32) ? im_fail(IM_EINVAL, "m >= 2^32") : IM_OK);
     if (rc) return rc;
     im_workspace *ws;
     if ((rc = im_workspace_create(&ws))) return rc;
@@ -1538,7 +2076,7 @@ extern "C" int im_validate(const im_graph *g, uint32_t R, void *stream)
 
 extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
 {
-    if (!ws || !out) return fail(IM_EINVAL, "null argument");
+    if (!ws || !out) return im_fail(IM_EINVAL, "null argument");
     HIPCHK(hipStreamSynchronize(ws->last_stream));
     HIPCHK(hipMemcpy(ws->host_stats, ws->stats, ST_COUNT * sizeof(unsigned long long),
                      hipMemcpyDeviceToHost));
@@ -1554,6 +2092,8 @@ extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
     out->celf_evals = h[ST_CELF_EVALS];
     out->fwd_levels = h[ST_FWD_LEVELS];
     out->fwd_entries = h[ST_FWD_ENTRIES];
+    out->celf_batches = h[ST_CELF_BATCHES];
+    out->celf_fallbacks = h[ST_CELF_FALLBACKS];
     for (int p = 0; p < 3; p++)
         for (int t = 0; t < 3; t++) {
             out->relax[p][t] = h[st_tier(p, t, F_RELAX)];
@@ -1569,7 +2109,7 @@ extern "C" int im_snapshot_masks(const im_graph *g, uint32_t R, uint64_t seed, u
 {
     int rc;
     if ((rc = check_args(g, R))) return rc;
-    if (!ws || (g->m && !mask_out)) return fail(IM_EINVAL, "null workspace or output");
+    if (!ws || (g->m && !mask_out)) return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
     if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, 0))) return rc;
     if ((rc = validate(g, ws, s, nullptr))) return rc;
@@ -1585,7 +2125,7 @@ extern "C" int im_transpose(const im_graph *g, uint32_t *in_row_ptr, uint32_t *i
     int rc;
     if ((rc = check_args(g, 1))) return rc;
     if (!ws || !in_row_ptr || (g->m && (!in_col || !in2out)))
-        return fail(IM_EINVAL, "null workspace or output");
+        return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
     if ((rc = ws_reserve(ws, g->n, g->m, 1, 0))) return rc;
     if ((rc = validate(g, ws, s, ws->row32))) return rc;
@@ -1606,7 +2146,7 @@ extern "C" int im_initial_gains(const im_graph *g, uint32_t R, uint64_t seed, ui
 {
     int rc;
     if ((rc = check_args(g, R))) return rc;
-    if (!ws || (g->n && !gain_out)) return fail(IM_EINVAL, "null workspace or output");
+    if (!ws || (g->n && !gain_out)) return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
     if ((rc = prepare(g, R, seed, 0, ws, s))) return rc;
     if (g->n)
@@ -1621,9 +2161,9 @@ extern "C" int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t see
 {
     int rc;
     if ((rc = check_args(g, R))) return rc;
-    if (!ws) return fail(IM_EINVAL, "null workspace");
-    if (k > g->n) return fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
-    if (k && (!seeds_out || !gains_out)) return fail(IM_EINVAL, "null seeds or gains output");
+    if (!ws) return im_fail(IM_EINVAL, "null workspace");
+    if (k > g->n) return im_fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
+    if (k && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
     hipStream_t s = (hipStream_t)stream;
     PhaseTimer pt(ws, IM_PH_CALL, s);
     if ((rc = prepare(g, R, seed, k, ws, s))) return rc;
@@ -1655,33 +2195,33 @@ extern "C" int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_
                               im_plan **out)
 {
     int rc;
-    if (!out) return fail(IM_EINVAL, "null plan output");
+    if (!out) return im_fail(IM_EINVAL, "null plan output");
     *out = nullptr;
     if ((rc = check_args(g, R))) return rc;
-    if (k > g->n) return fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
-    if (k && (!seeds_out || !gains_out)) return fail(IM_EINVAL, "null seeds or gains output");
+    if (k > g->n) return im_fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
+    if (k && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
     im_plan *p = new im_plan();
     if ((rc = im_workspace_create(&p->ws))) { delete p; return rc; }
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
         im_plan_destroy(p);
-        return fail(IM_EHIP, "hipStreamCreate failed");
+        return im_fail(IM_EHIP, "hipStreamCreate failed");
     }
     rc = check_and_reserve(g, R, k, p->ws, s);
     if (!rc) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
-            rc = fail(IM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+            rc = im_fail(IM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
         } else {
             rc = enqueue_prepare(g, R, seed, k, p->ws, s);
             if (!rc) rc = enqueue_rounds(g, R, k, seeds_out, gains_out, nullptr, p->ws, s);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(s, &graph);
-            if (!rc && e != hipSuccess) rc = fail(IM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            if (!rc && e != hipSuccess) rc = im_fail(IM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
             p->graph = graph;
             if (!rc) {
                 e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-                if (e != hipSuccess) rc = fail(IM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+                if (e != hipSuccess) rc = im_fail(IM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
             }
         }
     }
@@ -1699,7 +2239,7 @@ extern "C" int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_
 
 extern "C" int im_plan_launch(im_plan *p, void *stream)
 {
-    if (!p || !p->exec) return fail(IM_EINVAL, "null plan");
+    if (!p || !p->exec) return im_fail(IM_EINVAL, "null plan");
     HIPCHK(hipGraphLaunch(p->exec, (hipStream_t)stream));
     p->ws->last_stream = (hipStream_t)stream;
     return IM_OK;
@@ -1707,13 +2247,13 @@ extern "C" int im_plan_launch(im_plan *p, void *stream)
 
 extern "C" int im_plan_stats(im_plan *p, im_stats *out)
 {
-    if (!p) return fail(IM_EINVAL, "null plan");
+    if (!p) return im_fail(IM_EINVAL, "null plan");
     return im_stats_get(p->ws, out);
 }
 
 extern "C" int im_profile_enable(im_workspace *ws, uint32_t mask)
 {
-    if (!ws) return fail(IM_EINVAL, "null workspace");
+    if (!ws) return im_fail(IM_EINVAL, "null workspace");
     ws->prof_mask = mask;
     for (int p = 0; p < IM_PH_COUNT; p++) ws->ev_used[p] = 0;
     return IM_OK;
@@ -1721,7 +2261,7 @@ extern "C" int im_profile_enable(im_workspace *ws, uint32_t mask)
 
 extern "C" int im_profile_get(im_workspace *ws, im_profile *out)
 {
-    if (!ws || !out) return fail(IM_EINVAL, "null argument");
+    if (!ws || !out) return im_fail(IM_EINVAL, "null argument");
     memset(out, 0, sizeof(*out));
     HIPCHK(hipStreamSynchronize(ws->last_stream));
     HIPCHK(hipDeviceSynchronize());
@@ -1744,26 +2284,26 @@ extern "C" int im_profile_get(im_workspace *ws, im_profile *out)
 
 extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
 {
-    if (!ws) return fail(IM_EINVAL, "null workspace");
+    if (!ws) return im_fail(IM_EINVAL, "null workspace");
     switch (option) {
     case IM_OPT_HUB_DEGREE:
         if (value != 0 && (value < 16 || value > 0x7FFFFFFF))
-            return fail(IM_EINVAL, "hub degree must be 0 (off) or in [16, 2^31)");
+            return im_fail(IM_EINVAL, "hub degree must be 0 (off) or in [16, 2^31)");
         ws->hub_deg = (uint32_t)value;
         return IM_OK;
     case IM_OPT_COOP_GAIN:
-        if (value < 0) return fail(IM_EINVAL, "cooperative gain threshold must be >= 0");
+        if (value < 0) return im_fail(IM_EINVAL, "cooperative gain threshold must be >= 0");
         ws->coop_gain = (uint64_t)value;
         return IM_OK;
     default:
-        return fail(IM_EINVAL, "unknown option %d", option);
+        return im_fail(IM_EINVAL, "unknown option %d", option);
     }
 }
 
 extern "C" int im_profile_launches(im_workspace *ws, int phase, float *ms_out, uint32_t max,
                                    uint32_t *count)
 {
-    if (!ws || !count || phase < 0 || phase >= IM_PH_COUNT) return fail(IM_EINVAL, "bad argument");
+    if (!ws || !count || phase < 0 || phase >= IM_PH_COUNT) return im_fail(IM_EINVAL, "bad argument");
     const std::vector<float> &v = ws->last_ms[phase];
     *count = (uint32_t)v.size();
     for (uint32_t i = 0; i < max && i < v.size(); i++) ms_out[i] = v[i];
@@ -1801,7 +2341,7 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
                                uint64_t *gains_out, im_workspace *ws, void *stream)
 {
     int rc;
-    if (!inst || !ws) return fail(IM_EINVAL, "null instances or workspace");
+    if (!inst || !ws) return im_fail(IM_EINVAL, "null instances or workspace");
     if (count == 0) return IM_OK;
     if (count == 1)
         return im_select(&inst[0].g, inst[0].R, inst[0].k, inst[0].seed, seeds_out, gains_out,
@@ -1810,17 +2350,17 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     uint32_t Rmax = 0, kmax = 0;
     for (uint32_t i = 0; i < count; i++) {
         if ((rc = check_args(&inst[i].g, inst[i].R)))
-            return fail(rc, "instance %u: %s", i, g_err.c_str());
-        if (inst[i].k > inst[i].g.n) return fail(IM_EINVAL, "instance %u: k exceeds n", i);
+            return im_fail(rc, "instance %u: %s", i, g_err.c_str());
+        if (inst[i].k > inst[i].g.n) return im_fail(IM_EINVAL, "instance %u: k exceeds n", i);
         N += inst[i].g.n;
         M += inst[i].g.m;
         K += inst[i].k;
         Rmax = std::max(Rmax, inst[i].R);
         kmax = std::max(kmax, inst[i].k);
     }
-    if (N >= 0xFFFFFFFFull) return fail(IM_EINVAL, "batch has %llu nodes; must be < 2^32 - 1", (unsigned long long)N);
-    if (M >= (1ull << 32)) return fail(IM_EINVAL, "batch has %llu arcs; must be < 2^32", (unsigned long long)M);
-    if (K && (!seeds_out || !gains_out)) return fail(IM_EINVAL, "null seeds or gains output");
+    if (N >= 0xFFFFFFFFull) return im_fail(IM_EINVAL, "batch has %llu nodes; must be < 2^32 - 1", (unsigned long long)N);
+    if (M >= (1ull << 32)) return im_fail(IM_EINVAL, "batch has %llu arcs; must be < 2^32", (unsigned long long)M);
+    if (K && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
     hipStream_t s = (hipStream_t)stream;
     const uint32_t W = (Rmax + 63) / 64;
     ws->batch.count = count;  // sizes the per-round key arrays
@@ -1848,8 +2388,8 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
         hd[i].n = inst[i].g.n;
         hd[i].node_off = (uint32_t)no;
         if (inst[i].g.m && (!inst[i].g.col || !inst[i].g.prob))
-            return fail(IM_EINVAL, "instance %u: null col or prob", i);
-        if (!inst[i].g.row_ptr) return fail(IM_EINVAL, "instance %u: null row_ptr", i);
+            return im_fail(IM_EINVAL, "instance %u: null col or prob", i);
+        if (!inst[i].g.row_ptr) return im_fail(IM_EINVAL, "instance %u: null row_ptr", i);
         no += inst[i].g.n;
         ao += inst[i].g.m;
         kp += inst[i].k;
@@ -1874,7 +2414,7 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     HIPCHK(hipMemcpyAsync(ws->host_err, ws->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (*ws->host_err)
-        return fail(IM_EINVAL, "a batch instance failed validation (flags 0x%x)", *ws->host_err);
+        return im_fail(IM_EINVAL, "a batch instance failed validation (flags 0x%x)", *ws->host_err);
     Batch b;
     b.count = count;
     b.node_inst = ws->b_node_inst;
@@ -1898,4 +2438,39 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     }
     ws->batch = Batch{1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     return rc;
+}
+
+extern "C" int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                              uint32_t batch, const im_mlp *model, uint32_t *seeds_out,
+                              uint64_t *gains_out, im_workspace *ws, void *stream)
+{
+    int rc;
+    if ((rc = check_args(g, R))) return rc;
+    if (!ws) return im_fail(IM_EINVAL, "null workspace");
+    if (k > g->n) return im_fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
+    if (k && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
+    if (batch == 0 || batch > CELF_BMAX)
+        return im_fail(IM_EINVAL, "batch = %u must be in [1, %u]", batch, CELF_BMAX);
+    if ((uint64_t)batch * ((R + 63) / 64) >= (1ull << 32)) return im_fail(IM_EINVAL, "batch too large");
+    hipStream_t s = (hipStream_t)stream;
+    PhaseTimer pt(ws, IM_PH_CALL, s);
+    if ((rc = prepare(g, R, seed, k, ws, s))) return rc;
+    if (g->n == 0 || k == 0) return IM_OK;
+    return select_lazy(g, R, k, batch, model, seeds_out, gains_out, ws, s);
+}
+
+extern "C" int im_node_features(const im_graph *g, float *feat_out, im_workspace *ws, void *stream)
+{
+    int rc;
+    if (!g || !ws || (g->n && !feat_out)) return im_fail(IM_EINVAL, "null argument");
+    if ((rc = check_args(g, 1))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = check_and_reserve(g, 1, 0, ws, s))) return rc;
+    if (g->n == 0) return IM_OK;
+    build_reverse(g, ws, s);
+    k_features<<<grid_for(g->n, 256), 256, 0, s>>>(ws->row32, g->col, g->prob, ws->in_row, g->n,
+                                                   feat_out);
+    HIPCHK(hipGetLastError());
+    ws->last_stream = s;
+    return IM_OK;
 }

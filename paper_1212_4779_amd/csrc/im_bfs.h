@@ -31,7 +31,7 @@ enum {
     ST_TRAV_INIT = 0, ST_TRAV_FWD, ST_TRAV_REV, ST_TRAV_EVAL,
     ST_RELAX_FWD, ST_TASKS_REV, ST_DECREMENTS, ST_CELF_EVALS,
     ST_TIER_BASE = 8,   // + pass*12 + tier*4 + field
-    ST_FWD_LEVELS = 44, ST_FWD_ENTRIES = 45, ST_REV_TASKS_RUN = 46,
+    ST_FWD_LEVELS = 44, ST_FWD_ENTRIES = 45, ST_CELF_BATCHES = 46, ST_CELF_FALLBACKS = 47,
     ST_COUNT = 64
 };
 enum { PASS_INIT = 0, PASS_REV = 1, PASS_EVAL = 2 };
