@@ -165,6 +165,33 @@ def batch_instances(count=512, master_seed=4):
     return out
 
 
+TRAINING_WORKLOAD = dict(count=200, master_seed=5, first_graph_seed=5000)
+
+
+def training_recipes(count=200, master_seed=5, first_graph_seed=5000):
+    """Graphs whose selection traces train the candidate-scoring network.
+
+    Per graph i: n log-uniform in [1e5, 1e6], exponent uniform in [2.1, 2.5],
+    mean degree uniform in [4, 16], directed Chung-Lu (graph seed 5000+i);
+    even i uniform IC with p alternating 0.01 / 0.05, odd i weighted cascade;
+    R = 256, k = 50, selection seed 1. The last tenth is held out for
+    validation.
+    """
+    rng = np.random.default_rng(master_seed)
+    out = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(1e5), np.log(1e6)))))
+        gamma = float(rng.uniform(2.1, 2.5))
+        deg = float(rng.uniform(4.0, 16.0))
+        if i % 2 == 0:
+            p = 0.01 if (i // 2) % 2 == 0 else 0.05
+        else:
+            p = None
+        out.append(dict(n=n, m=int(round(n * deg)), gamma=gamma, graph_seed=first_graph_seed + i,
+                        directed=True, p=p, R=256, k=50, seed=1, validation=i >= count * 9 // 10))
+    return out
+
+
 def graph_from_recipe(w):
     return chung_lu_graph(w["n"], w["m"], w["gamma"], w["graph_seed"], w["directed"], w["p"])
 
