@@ -75,7 +75,7 @@ int im_workspace_destroy(im_workspace *ws);
  *     least this value run the forward search on a cooperative grid (about
  *     16 workgroups per snapshot word); smaller rounds use one workgroup per
  *     word. Default 0 (always the cooperative grid). */
-enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2 };
+enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the

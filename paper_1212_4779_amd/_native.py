@@ -28,6 +28,7 @@ PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t
           "pack", "order", "score", "pick", "eval_t0", "eval_t1", "eval_t2", "update")
 IM_OPT_HUB_DEGREE = 1
 IM_OPT_COOP_GAIN = 2
+IM_OPT_LAZY_ENGINE = 3
 
 
 class ImGraph(ctypes.Structure):

@@ -88,6 +88,11 @@ class Workspace:
         """Rounds with seed gain >= gain use the grid-wide forward search. No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_COOP_GAIN, int(gain)))
 
+    def set_lazy_engine(self, engine):
+        """Exact evaluations of the lazy path: 1 one cooperative grid per batch
+        (default), 0 the three per-task engine tiers. No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LAZY_ENGINE, int(engine)))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases

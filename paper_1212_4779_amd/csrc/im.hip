@@ -584,7 +584,6 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     __shared__ FwdLds L;
     const int tid = threadIdx.x;
     const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
-    const uint64_t gsize = (uint64_t)gridDim.x * FWD_NT;
     const bool single = a.b.count == 1;
     const unsigned long long key0 = a.key[0];
     if (single && key0 == 0) return;  // no unselected node (cannot happen for k <= n)
@@ -1028,6 +1027,12 @@ struct im_workspace {
     uint8_t *c_moved = nullptr;
     float *c_score = nullptr, *c_feat = nullptr;
     unsigned long long *c_sort = nullptr;
+    int lazy_engine = 1;     // 1: cooperative batched evaluation, 0: the three tiers
+    unsigned eval_grid = 0;
+    uint64_t cap_eval = 0;
+    uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
+             *e_vis = nullptr;
+    uint32_t *e_cnt = nullptr;
     // misc
     unsigned long long *stats = nullptr;
     uint32_t *err = nullptr;
@@ -1092,6 +1097,9 @@ static void dfree(Tv *&p)
     p = nullptr;
 }
 
+struct EvalArgs;
+__global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a);
+
 extern "C" int im_workspace_create(im_workspace **out)
 {
     if (!out) return im_fail(IM_EINVAL, "im_workspace_create: null output pointer");
@@ -1106,6 +1114,10 @@ extern "C" int im_workspace_create(im_workspace **out)
         if (b < 1) b = 1;
         // 16 workgroups per snapshot word at most: grid barriers stay cheap
         ws->fwd_grid = std::min<unsigned>((unsigned)b * (unsigned)ws->num_cu, 16u * 64u);
+        int be = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_eval_coop, FWD_NT, 0));
+        if (be < 1) be = 1;
+        ws->eval_grid = (unsigned)be * (unsigned)ws->num_cu;
     }
     int rc;
     if ((rc = dalloc(&ws->stats, ST_COUNT))) { delete ws; return rc; }
@@ -1141,6 +1153,8 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->c_bound); dfree(ws->c_fresh); dfree(ws->c_ev); dfree(ws->c_ordB); dfree(ws->c_ordS);
     dfree(ws->c_E); dfree(ws->c_cand); dfree(ws->c_ctl); dfree(ws->c_moved); dfree(ws->c_score);
     dfree(ws->c_feat); dfree(ws->c_sort);
+    dfree(ws->e_reach); dfree(ws->e_pend); dfree(ws->e_fq0); dfree(ws->e_fq1); dfree(ws->e_vis);
+    dfree(ws->e_cnt);
     dfree(ws->stats); dfree(ws->err);
     if (ws->host_err) (void)hipHostFree(ws->host_err);
     if (ws->host_stats) (void)hipHostFree(ws->host_stats);
@@ -1900,6 +1914,189 @@ __global__ __launch_bounds__(256) void k_celf_update(const uint32_t *cand, uint3
     }
 }
 
+// Exact evaluation of a batch of candidates on one cooperative grid. Each
+// (candidate slot s, word w) pair is a virtual word vw = s * W + w with its
+// own reach map R[vw][x] (dense, [V][n]); the search from candidate s in
+// word w starts with the valid bits not covered at s and never enters
+// covered bits (Sec. 4: the newly reachable part of the snapshot). All
+// V searches advance level by level together; small levels are spread one
+// frontier entry per workgroup so that huge nodes do not serialise on one
+// workgroup. Afterwards ev[cand[s]] += sum over w, x of popcount(R[vw][x])
+// and R is returned to zero.
+struct EvalArgs {
+    const uint32_t *row, *col;
+    const uint64_t *mask;
+    HubLists hub;
+    uint64_t m;
+    uint32_t n, R, W, V;
+    const uint64_t *covered;
+    uint64_t *reach, *pend;      // [Vmax][n], zero on entry and on exit
+    uint64_t *fq0, *fq1, *vis;   // (vw << 32 | node), capacity V * n each
+    uint32_t *cnt;               // [4]: frontier ring [3], visit count; zero on entry
+    const uint32_t *cand;        // V / W candidates
+    uint32_t *ev;
+    unsigned long long *stats;
+};
+
+__device__ __forceinline__ void eval_relax(const EvalArgs &a, uint32_t vw, uint32_t v, uint64_t bits,
+                                           bool &first, bool &push)
+{
+    first = false;
+    push = false;
+    if (bits) bits &= ~a.covered[(uint64_t)(vw % a.W) * a.n + v];
+    if (!bits) return;
+    const uint64_t off = (uint64_t)vw * a.n + v;
+    const uint64_t old = atomicOr((unsigned long long *)&a.reach[off], (unsigned long long)bits);
+    const uint64_t nb = bits & ~old;
+    if (!nb) return;
+    first = old == 0;
+    const uint64_t op = atomicOr((unsigned long long *)&a.pend[off], (unsigned long long)nb);
+    push = op == 0;
+}
+
+__global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
+{
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    __shared__ FwdLds L;
+    __shared__ uint32_t slot_sum[256];
+    const int tid = threadIdx.x;
+    const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
+    if (tid == 0) L.H.n = 0;
+    // seeds: one virtual word per thread
+    if (gtid < a.V) {
+        const uint32_t vw = (uint32_t)gtid, s = vw / a.W, w = vw % a.W, c = a.cand[s];
+        const uint64_t start = im_valid_bits(a.R, w) & ~a.covered[(uint64_t)w * a.n + c];
+        if (start) {
+            a.reach[(uint64_t)vw * a.n + c] = start;
+            a.pend[(uint64_t)vw * a.n + c] = start;
+            a.vis[atomicAdd(&a.cnt[3], 1u)] = ((uint64_t)vw << 32) | c;
+            a.fq0[atomicAdd(&a.cnt[0], 1u)] = ((uint64_t)vw << 32) | c;
+        }
+    }
+    grid.sync();
+    uint64_t arcs = 0;
+    for (uint32_t lev = 0;; lev++) {
+        const uint32_t nf = group_load(&a.cnt[lev % 3], &L.bcast);
+        if (nf == 0) break;
+        const uint64_t *cur = (lev & 1) ? a.fq1 : a.fq0;
+        uint64_t *nxt = (lev & 1) ? a.fq0 : a.fq1;
+        uint32_t *ncnt = &a.cnt[(lev + 1) % 3];
+        if (gtid == 0) a.cnt[(lev + 2) % 3] = 0;
+        // entries per workgroup: a full tile when there is enough work for
+        // every workgroup, fewer (down to one) otherwise
+        const uint32_t per = std::max<uint32_t>(1u, std::min<uint32_t>(FWD_NT, (nf + gridDim.x - 1) / gridDim.x));
+        for (uint64_t tile = (uint64_t)blockIdx.x * per; tile < nf; tile += (uint64_t)gridDim.x * per) {
+            const uint64_t i = tile + tid;
+            uint32_t deg = 0, rs = 0, vw = 0;
+            uint64_t d = 0;
+            if ((uint32_t)tid < per && i < nf) {
+                const uint64_t e = cur[i];
+                vw = (uint32_t)(e >> 32);
+                const uint32_t x = (uint32_t)e;
+                const uint32_t hs = a.hub.slot[x];
+                rs = a.row[x];
+                deg = a.row[x + 1] - rs;
+                d = atomicExch((unsigned long long *)&a.pend[(uint64_t)vw * a.n + x], 0ull);
+                if (hs != IM_EMPTY) {
+                    hub_push(L.H, hs, vw, d);
+                    deg = 0; d = 0;
+                }
+            }
+            uint32_t total;
+            const uint32_t ex = block_excl_scan<FWD_NT>(deg, L.wsum, &total);
+            L.scan[tid] = ex; L.rs[tid] = rs; L.del[tid] = d; L.wd[tid] = vw;
+            __syncthreads();
+            const uint32_t nhub = L.H.n;
+            arcs += total;
+            for (uint32_t j0 = 0; j0 < total; j0 += FWD_NT * FWD_U) {
+                uint32_t kk[FWD_U], ee[FWD_U], vv[FWD_U];
+                uint64_t bb[FWD_U];
+#pragma unroll
+                for (int u = 0; u < FWD_U; u++) {
+                    const uint32_t j = j0 + (uint32_t)tid + (uint32_t)u * FWD_NT;
+                    kk[u] = 0xFFFFFFFFu; ee[u] = 0; bb[u] = 0; vv[u] = 0;
+                    if (j < total) {
+                        const int k = upper_index<FWD_NT>(L.scan, j);
+                        kk[u] = (uint32_t)k;
+                        ee[u] = L.rs[k] + (j - L.scan[k]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < FWD_U; u++)
+                    if (kk[u] != 0xFFFFFFFFu) {
+                        bb[u] = a.mask[(uint64_t)(L.wd[kk[u]] % a.W) * a.m + ee[u]];
+                        vv[u] = a.col[ee[u]];
+                    }
+                uint64_t vis_e[FWD_U], nxt_e[FWD_U];
+                uint32_t nvis = 0, nnxt = 0;
+#pragma unroll
+                for (int u = 0; u < FWD_U; u++) {
+                    const uint32_t ww = kk[u] != 0xFFFFFFFFu ? L.wd[kk[u]] : 0u;
+                    const uint64_t bits = kk[u] != 0xFFFFFFFFu ? (bb[u] & L.del[kk[u]]) : 0ull;
+                    bool first, push;
+                    eval_relax(a, ww, vv[u], bits, first, push);
+                    const uint64_t ent = ((uint64_t)ww << 32) | vv[u];
+                    if (first) vis_e[nvis++] = ent;
+                    if (push) nxt_e[nnxt++] = ent;
+                }
+                wave_append_n<FWD_U>(nvis, vis_e, a.cnt + 3, a.vis);
+                wave_append_n<FWD_U>(nnxt, nxt_e, ncnt, nxt);
+            }
+            __syncthreads();
+            if (nhub) {
+                const uint32_t W = a.W;
+                auto word_of = [W](uint32_t own) { return own % W; };
+                uint64_t vis_e[FWD_U], nxt_e[FWD_U];
+                uint32_t nvis = 0, nnxt = 0;
+                auto relax = [&](uint32_t own, uint32_t hv, uint64_t bits) {
+                    bool first, push;
+                    eval_relax(a, own, hv, bits, first, push);
+                    const uint64_t ent = ((uint64_t)own << 32) | hv;
+                    if (first) vis_e[nvis++] = ent;
+                    if (push) nxt_e[nnxt++] = ent;
+                };
+                auto flush = [&]() {
+                    wave_append_n<FWD_U>(nvis, vis_e, a.cnt + 3, a.vis);
+                    wave_append_n<FWD_U>(nnxt, nxt_e, ncnt, nxt);
+                    nvis = 0;
+                    nnxt = 0;
+                };
+                expand_hubs<FWD_NT, 16, FWD_U>(L.H, nhub, a.hub, a.W, word_of, relax, flush, arcs);
+            }
+        }
+        grid.sync();
+    }
+    // per-candidate sums of the reached bits; reach returns to zero
+    const uint32_t nslot = a.V / a.W;
+    for (uint32_t s = tid; s < nslot; s += FWD_NT) slot_sum[s] = 0;
+    __syncthreads();
+    uint64_t relax = 0, trav = 0;
+    const uint32_t nv = group_load(&a.cnt[3], &L.bcast);
+    for (uint64_t i = gtid; i < nv; i += (uint64_t)gridDim.x * FWD_NT) {
+        const uint64_t e = a.vis[i];
+        const uint32_t vw = (uint32_t)(e >> 32), x = (uint32_t)e;
+        const uint64_t off = (uint64_t)vw * a.n + x;
+        const uint32_t pc = (uint32_t)__popcll(a.reach[off]);
+        a.reach[off] = 0;
+        const uint32_t dg = a.row[x + 1] - a.row[x];
+        relax += dg;
+        trav += (uint64_t)pc * dg;
+        atomicAdd(&slot_sum[vw / a.W], pc);
+    }
+    __syncthreads();
+    for (uint32_t s = tid; s < nslot; s += FWD_NT)
+        if (slot_sum[s]) atomicAdd(&a.ev[a.cand[s]], slot_sum[s]);
+    relax = group_sum<FWD_NT>(relax, L.red);
+    trav = group_sum<FWD_NT>(trav, L.red);
+    if (tid == 0) {
+        atomicAdd(&a.stats[st_tier(PASS_EVAL, 2, F_RELAX)], (unsigned long long)relax);
+        if (blockIdx.x == 0) atomicAdd(&a.stats[st_tier(PASS_EVAL, 2, F_REACHED)], (unsigned long long)nv);
+        atomicAdd(&a.stats[st_tier(PASS_EVAL, 2, F_ARCS)], (unsigned long long)arcs);
+        atomicAdd(&a.stats[ST_TRAV_EVAL], (unsigned long long)trav);
+    }
+}
+
 static int reserve_celf(im_workspace *ws, uint32_t n)
 {
     int rc;
@@ -1919,6 +2116,60 @@ static int reserve_celf(im_workspace *ws, uint32_t n)
     if (len > ws->cap_sort) {
         if ((rc = dalloc(&ws->c_sort, len))) return rc;
         ws->cap_sort = len;
+    }
+    return IM_OK;
+}
+
+// virtual words of one cooperative evaluation launch: at most 256 and at
+// most EVAL_BUDGET bytes of search state (40 bytes per node and virtual
+// word); 0 when not even one candidate fits (the tier engines run then)
+constexpr uint64_t EVAL_BUDGET = 8ull << 30;
+
+static uint32_t eval_vmax(uint32_t n, uint32_t W)
+{
+    uint64_t v = EVAL_BUDGET / (40ull * std::max<uint32_t>(n, 1));
+    v = std::min<uint64_t>(v, 256);
+    v -= v % W;
+    return (uint32_t)v;
+}
+
+static int reserve_eval(im_workspace *ws, uint32_t n, uint32_t V)
+{
+    int rc;
+    const uint64_t need = (uint64_t)V * std::max<uint32_t>(n, 1);
+    if (need > ws->cap_eval) {
+        if ((rc = dalloc(&ws->e_reach, need)) || (rc = dalloc(&ws->e_pend, need)) ||
+            (rc = dalloc(&ws->e_fq0, need)) || (rc = dalloc(&ws->e_fq1, need)) ||
+            (rc = dalloc(&ws->e_vis, need)) || (rc = dalloc(&ws->e_cnt, 4)))
+            return rc;
+        HIPCHK(hipMemset(ws->e_reach, 0, need * sizeof(uint64_t)));
+        HIPCHK(hipMemset(ws->e_pend, 0, need * sizeof(uint64_t)));
+        ws->cap_eval = need;
+    }
+    return IM_OK;
+}
+
+// exact gains of cand[0..ncand) into ev (zeroed by the pick) on cooperative grids
+static int eval_coop(const im_graph *g, uint32_t R, uint32_t ncand, uint32_t vmax, im_workspace *ws,
+                     hipStream_t s)
+{
+    const uint32_t n = g->n, W = (R + 63) / 64, per = vmax / W;
+    EvalArgs e;
+    e.row = ws->row32; e.col = g->col; e.mask = ws->mask_out; e.hub = hub_lists(ws, 0);
+    e.m = g->m; e.n = n; e.R = R; e.W = W;
+    e.covered = ws->covered; e.reach = ws->e_reach; e.pend = ws->e_pend;
+    e.fq0 = ws->e_fq0; e.fq1 = ws->e_fq1; e.vis = ws->e_vis; e.cnt = ws->e_cnt;
+    e.ev = ws->c_ev; e.stats = ws->stats;
+    for (uint32_t c0 = 0; c0 < ncand; c0 += per) {
+        const uint32_t nc = std::min(per, ncand - c0);
+        e.cand = ws->c_cand + c0;
+        e.V = nc * W;
+        fill<uint32_t>(ws->e_cnt, 4, 0u, s);
+        void *args[] = {&e};
+        hipError_t err = hipLaunchCooperativeKernel((const void *)k_eval_coop, dim3(ws->eval_grid),
+                                                    dim3(FWD_NT), args, 0, s);
+        if (err != hipSuccess)
+            return im_fail(IM_EHIP, "cooperative launch of k_eval_coop: %s", hipGetErrorString(err));
     }
     return IM_OK;
 }
@@ -1991,6 +2242,8 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
     const bool learned = model != nullptr;
     const float invR = 1.0f / (float)R;
     if ((rc = reserve_celf(ws, n))) return rc;
+    const uint32_t vmax = ws->lazy_engine ? eval_vmax(n, W) : 0u;
+    if (vmax && (rc = reserve_eval(ws, n, vmax))) return rc;
     k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, ws->c_bound, n);
     fill<uint32_t>(ws->c_fresh, n, 0u, s);
     fill<uint32_t>(ws->c_ctl, CC_COUNT, 0u, s);
@@ -2034,16 +2287,21 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
             HIPCHK(hipStreamSynchronize(s));
             const uint32_t ncand = *ws->host_err;
             if (ncand == 0) break;
-            BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W);
-            a.cand = ws->c_cand;
-            a.ncand = ncand;
-            a.ntasks = ncand * W;
-            a.gain = ws->c_ev;
-            a.prune = ws->covered;
-            a.hub = hub_lists(ws, 0);
-            a.pass = PASS_EVAL;
-            a.st_trav = ST_TRAV_EVAL;
-            run_tiers<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T0, s);
+            if (vmax) {
+                PhaseTimer pt(ws, IM_PH_EVAL_T2, s);
+                if ((rc = eval_coop(g, R, ncand, vmax, ws, s))) return rc;
+            } else {
+                BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W);
+                a.cand = ws->c_cand;
+                a.ncand = ncand;
+                a.ntasks = ncand * W;
+                a.gain = ws->c_ev;
+                a.prune = ws->covered;
+                a.hub = hub_lists(ws, 0);
+                a.pass = PASS_EVAL;
+                a.st_trav = ST_TRAV_EVAL;
+                run_tiers<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T0, s);
+            }
             {
                 PhaseTimer pt(ws, IM_PH_UPDATE, s);
                 k_celf_update<<<1, 256, 0, s>>>(ws->c_cand, ws->c_ctl, ws->c_ev, ws->c_bound,
@@ -2294,6 +2552,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
     case IM_OPT_COOP_GAIN:
         if (value < 0) return im_fail(IM_EINVAL, "cooperative gain threshold must be >= 0");
         ws->coop_gain = (uint64_t)value;
+        return IM_OK;
+    case IM_OPT_LAZY_ENGINE:
+        if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");
+        ws->lazy_engine = (int)value;
         return IM_OK;
     default:
         return im_fail(IM_EINVAL, "unknown option %d", option);

@@ -47,14 +47,16 @@ def _random_params(seed, scale=0.2):
 # ------------------------------------------------------------------- lazy path
 
 
+@pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
 @pytest.mark.parametrize("batch", [1, 7, 64, 1024])
-def test_lazy_bound_order_matches_golden(im, name, batch):
+def test_lazy_bound_order_matches_golden(im, name, batch, engine):
     gold = _gold(name)
     w = gg.WORKLOADS[name]
     g = gg.workload_graph(name)
     d = _dev(im, g)
     ws = im.Workspace()
+    ws.set_lazy_engine(engine)
     seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=batch, ws=ws)
     assert seeds.cpu().tolist() == gold["seeds"]
     assert gains.cpu().tolist() == gold["gains"]
@@ -63,13 +65,15 @@ def test_lazy_bound_order_matches_golden(im, name, batch):
     assert st["celf_evals"] >= w["k"] - 1
 
 
+@pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
-def test_lazy_batch1_evaluations_equal_oracle_celf(im, name):
+def test_lazy_batch1_evaluations_equal_oracle_celf(im, name, engine):
     w = gg.WORKLOADS[name]
     g = gg.workload_graph(name)
     s_ref, g_ref, st_ref = oracle.select_celf(g.row_ptr, g.col, g.prob, w["R"], w["k"], w["seed"])
     d = _dev(im, g)
     ws = im.Workspace()
+    ws.set_lazy_engine(engine)
     seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=1, ws=ws)
     assert seeds.cpu().tolist() == s_ref.tolist()
     assert gains.cpu().tolist() == g_ref.tolist()
@@ -118,9 +122,11 @@ def test_lazy_million_golden(im):
     w = gg.WORKLOADS["million_uic"]
     g = gg.workload_graph("million_uic")
     d = _dev(im, g)
-    for model in (None, im.Mlp(_random_params(12))):
+    for engine, model, batch in ((1, None, 64), (1, im.Mlp(_random_params(12)), 16), (0, None, 64),
+                                 (1, None, 1)):
         ws = im.Workspace()
-        seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=64, model=model, ws=ws)
+        ws.set_lazy_engine(engine)
+        seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=batch, model=model, ws=ws)
         assert seeds.cpu().tolist() == gold["seeds"]
         assert gains.cpu().tolist() == gold["gains"]
 
@@ -141,10 +147,13 @@ def test_lazy_small_cases_match_oracle(im, case, learned):
     s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
     d = _dev(im, g)
     model = im.Mlp(_random_params(13)) if learned else None
-    for batch in (1, 5, 1024):
-        seeds, gains = im.select_lazy(d, R, k, seed, batch=batch, model=model)
-        assert seeds.cpu().tolist() == s_ref.tolist()
-        assert gains.cpu().tolist() == g_ref.tolist()
+    for engine in (0, 1):
+        ws = im.Workspace()
+        ws.set_lazy_engine(engine)
+        for batch in (1, 5, 1024):
+            seeds, gains = im.select_lazy(d, R, k, seed, batch=batch, model=model, ws=ws)
+            assert seeds.cpu().tolist() == s_ref.tolist()
+            assert gains.cpu().tolist() == g_ref.tolist()
 
 
 def test_lazy_edge_cases_and_errors(im):
