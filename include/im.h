@@ -70,12 +70,13 @@ int im_workspace_destroy(im_workspace *ws);
  * only choose how the work is scheduled.
  *   IM_OPT_HUB_DEGREE: nodes with at least this many arcs (in the direction
  *     of a pass) are expanded through per-snapshot live lists instead of the
- *     snapshot masks; 0 disables the lists; otherwise >= 16. Default 1024.
+ *     snapshot masks; 0 disables the lists; otherwise >= 16. Default 256.
  *   IM_OPT_COOP_GAIN: rounds whose seed gain (summed over snapshots) is at
  *     least this value run the forward search on a cooperative grid (about
  *     16 workgroups per snapshot word); smaller rounds use one workgroup per
  *     word. Default 0 (always the cooperative grid). */
-enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3 };
+enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
+       IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -186,6 +187,28 @@ typedef struct im_instance {
 int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
                     uint64_t *gains_out, im_workspace *ws, void *stream);
 
+/* Schedule autotuning (synchronous). A schedule -- hub threshold, tier-1
+ * table, tier-2 lanes and slots (the IM_OPT_* options above) -- decides only
+ * where each reachability task runs, never a result. Each candidate schedule
+ * is timed on the initial reach counts of the given graph (Algorithm 2's
+ * initial loop, run by the same engines as every later pass) and the
+ * fastest is set on the workspace and returned in *out (host, may be NULL).
+ * im_autotune caches its choice per graph signature (n, m, R and a checksum
+ * of col and prob) for the life of the process; a cached choice is applied
+ * without timing (out->tried = 0). im_autotune_batch tunes on the instances
+ * it is given (a caller may pass a representative subset of a batch). */
+typedef struct im_tuning {
+    int32_t  hub_degree;
+    int32_t  tier1_table;
+    int32_t  tier2_lanes;
+    int32_t  max_slots;
+    float    ms;       /* initial-count time of the chosen schedule */
+    uint32_t tried;    /* schedules timed (0: taken from the cache)  */
+} im_tuning;
+int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,
+                im_tuning *out);
+int im_autotune_batch(const im_instance *inst, uint32_t count, im_workspace *ws, void *stream,
+                      im_tuning *out);
 /* Plans (device-resident round loop). im_plan_create validates the graph
  * (synchronous), then captures the complete selection -- reverse CSR, masks,
  * hub lists, initial gains and all k rounds -- into one HIP graph bound to a

@@ -19,7 +19,8 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_plan_create", "im_plan_launch", "im_plan_stats", "im_plan_destroy",
            "im_select_batch", "im_mlp_create", "im_mlp_destroy", "im_mlp_set_params",
            "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
-           "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy")
+           "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy",
+           "im_autotune", "im_autotune_batch")
 IM_MLP_NPARAM = 4609
 IM_PH_MAX = 24
 
@@ -29,6 +30,9 @@ PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t
 IM_OPT_HUB_DEGREE = 1
 IM_OPT_COOP_GAIN = 2
 IM_OPT_LAZY_ENGINE = 3
+IM_OPT_MAX_SLOTS = 4
+IM_OPT_TIER1_TABLE = 5
+IM_OPT_TIER2_LANES = 6
 
 
 class ImGraph(ctypes.Structure):
@@ -65,6 +69,15 @@ class ImStats(ctypes.Structure):
                 for t in range(3):
                     d[f"{f}_{pn}_t{t}"] = per[t]
         return d
+
+
+class ImTuning(ctypes.Structure):
+    _fields_ = [("hub_degree", ctypes.c_int32), ("tier1_table", ctypes.c_int32),
+                ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("tried", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class ImProfile(ctypes.Structure):
@@ -118,6 +131,8 @@ def lib():
         L.im_node_features.argtypes = [G, p, p, p]
         L.im_mlp_samples.argtypes = [p, p, u32, u32, u32, p, p, p, u32, p, p, p]
         L.im_select_lazy.argtypes = [G, u32, u32, u64, u32, p, p, p, p, p]
+        L.im_autotune.argtypes = [G, u32, u64, p, p, ctypes.POINTER(ImTuning)]
+        L.im_autotune_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, ctypes.POINTER(ImTuning)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

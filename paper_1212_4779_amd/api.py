@@ -93,6 +93,18 @@ class Workspace:
         (default), 0 the three per-task engine tiers. No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LAZY_ENGINE, int(engine)))
 
+    def set_max_slots(self, slots):
+        """Workgroups of the last engine tier (8..65536). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_MAX_SLOTS, int(slots)))
+
+    def set_tier1_table(self, entries):
+        """LDS table entries of the middle engine tier (1024 or 2048). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER1_TABLE, int(entries)))
+
+    def set_tier2_lanes(self, lanes):
+        """Lanes per task of the last engine tier (256 or 1024). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER2_LANES, int(lanes)))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases
@@ -192,6 +204,39 @@ def select(graph, R, k, seed, ws=None, trace=False):
     return _u32(seeds), gains, (_u32(tr) if trace else None)
 
 
+def autotune(graph, R, seed, ws=None):
+    """Pick the fastest engine schedule for this graph (set on `ws`); returns it as a dict."""
+    g = graph.c_struct()
+    ws = _ws(ws, graph.device)
+    t = N.ImTuning()
+    N.check(N.lib().im_autotune(ctypes.byref(g), R, seed, ws.handle, _stream(graph.device),
+                                ctypes.byref(t)))
+    return t.as_dict()
+
+
+def _instances(instances):
+    arr = (N.ImInstance * len(instances))()
+    keep = []
+    for i, (g, R, k, seed) in enumerate(instances):
+        cg = g.c_struct()
+        keep.append(cg)
+        arr[i].g = cg
+        arr[i].R = R
+        arr[i].k = k
+        arr[i].seed = seed
+    return arr, keep
+
+
+def autotune_batch(instances, ws=None):
+    """Pick the fastest engine schedule for a batch (or a sample of it); set on `ws`."""
+    dev = instances[0][0].device
+    arr, _keep = _instances(instances)
+    ws = _ws(ws, dev)
+    t = N.ImTuning()
+    N.check(N.lib().im_autotune_batch(arr, len(instances), ws.handle, _stream(dev), ctypes.byref(t)))
+    return t.as_dict()
+
+
 def select_batch(instances, ws=None):
     """Select seeds for several independent instances in one batched pass.
 
@@ -202,15 +247,7 @@ def select_batch(instances, ws=None):
     if not instances:
         return []
     dev = instances[0][0].device
-    arr = (N.ImInstance * len(instances))()
-    keep = []
-    for i, (g, R, k, seed) in enumerate(instances):
-        cg = g.c_struct()
-        keep.append(cg)
-        arr[i].g = cg
-        arr[i].R = R
-        arr[i].k = k
-        arr[i].seed = seed
+    arr, _keep = _instances(instances)
     K = sum(int(x[2]) for x in instances)
     seeds = torch.empty(K, dtype=torch.int32, device=dev)
     gains = torch.empty(K, dtype=torch.int64, device=dev)

@@ -963,8 +963,11 @@ constexpr int T0_T = 8, T0_CS = 32, T0_LIM = 24, T0_U = 8;
 constexpr uint32_t T0_DMAX = 1024;
 // tier 1: 256 lanes, T1_T tasks of up to T1_LIM nodes, any degree
 constexpr int T1_NT = 256, T1_T = 1, T1_CS = 2048, T1_LIM = 1536, T1_U = 8;
+// the smaller tier-1 table (more workgroups per CU, earlier hand-over)
+constexpr int T1S_CS = 1024, T1S_LIM = 768;
 // tier 2: dense global arrays
 constexpr int T2_NT = 256, T2_U = 8;
+constexpr int T2W_NT = 1024;   // the wide variant: more lanes per task
 // per-phase device counters: grab0, n1, grab1, n2, grab2
 constexpr int PH_CTRS = 8;
 // per-round forward counters: 3 frontier counts + one visit count per word
@@ -977,6 +980,9 @@ struct im_workspace {
     int device = -1;
     int num_cu = 256;
     uint32_t cap_n = 0, cap_W = 0, cap_k = 0, slots = 0;
+    uint32_t max_slots = 256, slots_cap = 0, slots_n = 0;  // tier-2 slots in use / allocated
+    int tier1_small = 1;     // tier-1 table of 1024 entries instead of 2048
+    int tier2_wide = 0;      // 1024 lanes per tier-2 task instead of 256
     uint64_t cap_m = 0;
     // graph-derived
     uint32_t *row32 = nullptr, *in_row = nullptr, *in_col = nullptr, *in2out = nullptr;
@@ -1010,7 +1016,7 @@ struct im_workspace {
     uint32_t *ovf_q = nullptr, *ovf_q2 = nullptr;
     uint32_t *ctrs = nullptr;
     // hub lists per direction (0: forward arcs, 1: reverse arcs)
-    uint32_t hub_deg = 1024;
+    uint32_t hub_deg = 256;
     uint64_t cap_hub = 0, cap_hadj = 0;
     uint32_t *hslot[2] = {}, *hlist[2] = {}, *hcnt[2] = {}, *hoff[2] = {}, *hadj[2] = {};
     unsigned long long *hbase[2] = {};
@@ -1164,14 +1170,34 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     return IM_OK;
 }
 
-static uint32_t slots_for(uint32_t n)
+static uint32_t slots_for(uint32_t n, uint32_t max_slots)
 {
     // dense global-engine state: 36 bytes per node per slot, at most 48 GB
     uint64_t per = 36ull * (n ? n : 1);
     uint64_t s = (48ull << 30) / per;
-    if (s > 256) s = 256;
+    if (s > max_slots) s = max_slots;
     if (s < 8) s = 8;
     return (uint32_t)s;
+}
+
+// tier-2 slot arrays for graphs of up to cap_n nodes
+static int reserve_slots(im_workspace *ws)
+{
+    int rc;
+    const uint32_t slots = slots_for(ws->cap_n, ws->max_slots);
+    if (slots > ws->slots_cap || ws->cap_n > ws->slots_n) {
+        uint64_t sn = (uint64_t)slots * ws->cap_n;
+        if ((rc = dalloc(&ws->b_reach, sn)) || (rc = dalloc(&ws->b_pend, sn)) ||
+            (rc = dalloc(&ws->b_fdel, sn)) || (rc = dalloc(&ws->b_qa, sn)) ||
+            (rc = dalloc(&ws->b_qb, sn)) || (rc = dalloc(&ws->b_vis, sn)))
+            return rc;
+        HIPCHK(hipMemset(ws->b_reach, 0, sn * sizeof(uint64_t)));
+        HIPCHK(hipMemset(ws->b_pend, 0, sn * sizeof(uint64_t)));
+        ws->slots_cap = slots;
+        ws->slots_n = ws->cap_n;
+    }
+    ws->slots = slots;
+    return IM_OK;
 }
 
 // grow the workspace to hold a graph with n nodes, m arcs, W words, k rounds
@@ -1200,17 +1226,9 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
             if ((rc = dalloc(&ws->hslot[d], cn))) return rc;
         HIPCHK(hipMemset(ws->newly, 0, nW * sizeof(uint64_t)));
         HIPCHK(hipMemset(ws->fpend, 0, nW * sizeof(uint64_t)));
-        uint32_t slots = slots_for(cn);
-        uint64_t sn = (uint64_t)slots * cn;
-        if ((rc = dalloc(&ws->b_reach, sn)) || (rc = dalloc(&ws->b_pend, sn)) ||
-            (rc = dalloc(&ws->b_fdel, sn)) || (rc = dalloc(&ws->b_qa, sn)) ||
-            (rc = dalloc(&ws->b_qb, sn)) || (rc = dalloc(&ws->b_vis, sn)))
-            return rc;
-        HIPCHK(hipMemset(ws->b_reach, 0, sn * sizeof(uint64_t)));
-        HIPCHK(hipMemset(ws->b_pend, 0, sn * sizeof(uint64_t)));
-        ws->slots = slots;
         ws->cap_n = cn;
     }
+    if ((rc = reserve_slots(ws))) return rc;
     if (grow_m) {
         if ((rc = dalloc(&ws->in_col, cm)) || (rc = dalloc(&ws->in2out, cm)) ||
             (rc = dalloc(&ws->mask_out, cm * cW)) || (rc = dalloc(&ws->mask_in, cm * cW)))
@@ -1396,15 +1414,24 @@ static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipSt
     a.out_q = ws->ovf_q2; a.out_n = ctr + 3; a.grab = ctr + 2; a.tier = 1;
     {
         PhaseTimer pt(ws, ph0 + 1, s);
-        auto k1 = k_lds_bfs<MODE, T1_NT, T1_T, T1_CS, T1_LIM, 0xFFFFFFFFu, T1_U, PRUNE>;
-        static const unsigned g1 = per_cu(k1, T1_NT);
-        k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
+        if (ws->tier1_small) {
+            auto k1 = k_lds_bfs<MODE, T1_NT, T1_T, T1S_CS, T1S_LIM, 0xFFFFFFFFu, T1_U, PRUNE>;
+            static const unsigned g1 = per_cu(k1, T1_NT);
+            k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
+        } else {
+            auto k1 = k_lds_bfs<MODE, T1_NT, T1_T, T1_CS, T1_LIM, 0xFFFFFFFFu, T1_U, PRUNE>;
+            static const unsigned g1 = per_cu(k1, T1_NT);
+            k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
+        }
     }
     a.in_q = ws->ovf_q2; a.in_n = ctr + 3;
     a.out_q = nullptr; a.out_n = nullptr; a.grab = ctr + 4; a.tier = 2;
     {
         PhaseTimer pt(ws, ph0 + 2, s);
-        k_block_bfs<MODE, T2_NT, T2_U, PRUNE><<<ws->slots, T2_NT, 0, s>>>(a);
+        if (ws->tier2_wide)
+            k_block_bfs<MODE, T2W_NT, T2_U, PRUNE><<<ws->slots, T2W_NT, 0, s>>>(a);
+        else
+            k_block_bfs<MODE, T2_NT, T2_U, PRUNE><<<ws->slots, T2_NT, 0, s>>>(a);
     }
 }
 
@@ -2553,6 +2580,18 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         if (value < 0) return im_fail(IM_EINVAL, "cooperative gain threshold must be >= 0");
         ws->coop_gain = (uint64_t)value;
         return IM_OK;
+    case IM_OPT_MAX_SLOTS:
+        if (value < 8 || value > 65536) return im_fail(IM_EINVAL, "slots must be in [8, 65536]");
+        ws->max_slots = (uint32_t)value;
+        return IM_OK;
+    case IM_OPT_TIER1_TABLE:
+        if (value != 1024 && value != 2048) return im_fail(IM_EINVAL, "tier-1 table must be 1024 or 2048");
+        ws->tier1_small = value == 1024;
+        return IM_OK;
+    case IM_OPT_TIER2_LANES:
+        if (value != 256 && value != 1024) return im_fail(IM_EINVAL, "tier-2 lanes must be 256 or 1024");
+        ws->tier2_wide = value == 1024;
+        return IM_OK;
     case IM_OPT_LAZY_ENGINE:
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");
         ws->lazy_engine = (int)value;
@@ -2599,15 +2638,14 @@ static int reserve_batch(im_workspace *ws, uint32_t count, uint64_t N, uint64_t 
     return IM_OK;
 }
 
-extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
-                               uint64_t *gains_out, im_workspace *ws, void *stream)
+// Lay `count` instances out as one block-diagonal graph in the workspace:
+// validate them, stage the instance tables, merge the CSRs. On success
+// ws->batch describes the batch and *mg the merged graph (the caller resets
+// ws->batch afterwards). Synchronous.
+static int batch_setup(const im_instance *inst, uint32_t count, bool need_out, im_workspace *ws,
+                       hipStream_t s, im_graph *mg, uint32_t *Rmax_out, uint32_t *kmax_out)
 {
     int rc;
-    if (!inst || !ws) return im_fail(IM_EINVAL, "null instances or workspace");
-    if (count == 0) return IM_OK;
-    if (count == 1)
-        return im_select(&inst[0].g, inst[0].R, inst[0].k, inst[0].seed, seeds_out, gains_out,
-                         nullptr, ws, stream);
     uint64_t N = 0, M = 0, K = 0;
     uint32_t Rmax = 0, kmax = 0;
     for (uint32_t i = 0; i < count; i++) {
@@ -2622,8 +2660,7 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     }
     if (N >= 0xFFFFFFFFull) return im_fail(IM_EINVAL, "batch has %llu nodes; must be < 2^32 - 1", (unsigned long long)N);
     if (M >= (1ull << 32)) return im_fail(IM_EINVAL, "batch has %llu arcs; must be < 2^32", (unsigned long long)M);
-    if (K && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
-    hipStream_t s = (hipStream_t)stream;
+    if (K && !need_out) return im_fail(IM_EINVAL, "null seeds or gains output");
     const uint32_t W = (Rmax + 63) / 64;
     ws->batch.count = count;  // sizes the per-round key arrays
     rc = ws_reserve(ws, (uint32_t)N, M, W, kmax);
@@ -2636,6 +2673,9 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     InstDesc *hd = (InstDesc *)(h64 + 2ull * (count + 1));
     uint64_t no = 0, ao = 0, kp = 0;
     for (uint32_t i = 0; i < count; i++) {
+        if (inst[i].g.m && (!inst[i].g.col || !inst[i].g.prob))
+            return im_fail(IM_EINVAL, "instance %u: null col or prob", i);
+        if (!inst[i].g.row_ptr) return im_fail(IM_EINVAL, "instance %u: null row_ptr", i);
         hu[i] = inst[i].R;
         hu[(count + 1) + i] = inst[i].k;
         hu[2 * (count + 1) + i] = (uint32_t)kp;
@@ -2649,20 +2689,15 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
         hd[i].arc_off = ao;
         hd[i].n = inst[i].g.n;
         hd[i].node_off = (uint32_t)no;
-        if (inst[i].g.m && (!inst[i].g.col || !inst[i].g.prob))
-            return im_fail(IM_EINVAL, "instance %u: null col or prob", i);
-        if (!inst[i].g.row_ptr) return im_fail(IM_EINVAL, "instance %u: null row_ptr", i);
         no += inst[i].g.n;
         ao += inst[i].g.m;
         kp += inst[i].k;
     }
     hu[3 * (count + 1) + count] = (uint32_t)no;
     h64[count] = ao;
-    size_t bytes = (4ull * (count + 1)) * 4 + (2ull * (count + 1)) * 8;
     HIPCHK(hipMemcpyAsync(ws->b_u32, hu, (4ull * (count + 1)) * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ws->b_u64, h64, (2ull * (count + 1)) * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ws->b_desc, hd, (uint64_t)count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
-    (void)bytes;
     HIPCHK(hipMemsetAsync(ws->err, 0, sizeof(uint32_t), s));
     {
         uint64_t maxw = 0;
@@ -2687,19 +2722,200 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     b.arc_off = ws->b_u64;
     b.seed = ws->b_u64 + (count + 1);
     ws->batch = b;
+    mg->n = (uint32_t)N;
+    mg->m = M;
+    mg->row_ptr = nullptr;
+    mg->col = ws->b_mcol;
+    mg->prob = ws->b_mprob;
+    *Rmax_out = Rmax;
+    *kmax_out = kmax;
+    return IM_OK;
+}
+
+static const Batch kSingle = {1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+
+extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
+                               uint64_t *gains_out, im_workspace *ws, void *stream)
+{
+    int rc;
+    if (!inst || !ws) return im_fail(IM_EINVAL, "null instances or workspace");
+    if (count == 0) return IM_OK;
+    if (count == 1)
+        return im_select(&inst[0].g, inst[0].R, inst[0].k, inst[0].seed, seeds_out, gains_out,
+                         nullptr, ws, stream);
+    hipStream_t s = (hipStream_t)stream;
     im_graph mg;
-    mg.n = (uint32_t)N;
-    mg.m = M;
-    mg.row_ptr = nullptr;
-    mg.col = ws->b_mcol;
-    mg.prob = ws->b_mprob;
-    {
+    uint32_t Rmax = 0, kmax = 0;
+    rc = batch_setup(inst, count, seeds_out && gains_out, ws, s, &mg, &Rmax, &kmax);
+    if (!rc) {
         PhaseTimer pt(ws, IM_PH_CALL, s);
         rc = enqueue_prepare(&mg, Rmax, 0, kmax, ws, s);
         if (!rc) rc = enqueue_rounds(&mg, Rmax, kmax, seeds_out, gains_out, nullptr, ws, s);
     }
-    ws->batch = Batch{1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    ws->batch = kSingle;
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// A8: schedule autotuning. A schedule (hub threshold, tier-1 table, tier-2
+// lanes and slots) never changes a result, only where each reachability
+// task runs; the best one depends on the reach-size profile of the graph.
+// Candidates are timed on the initial reach counts (the same engines every
+// later pass uses) and the fastest is kept, cached per graph signature.
+// ---------------------------------------------------------------------------
+struct Schedule {
+    int32_t hub_degree, tier1_table, tier2_lanes, max_slots;
+};
+static const Schedule kSchedules[] = {
+    {256, 1024, 256, 256},  {256, 1024, 1024, 256}, {256, 1024, 256, 2048},
+    {256, 1024, 256, 1024}, {1024, 1024, 1024, 256}, {256, 2048, 256, 2048},
+};
+constexpr int N_SCHEDULES = sizeof(kSchedules) / sizeof(kSchedules[0]);
+
+static void apply_schedule(im_workspace *ws, const Schedule &c)
+{
+    ws->hub_deg = (uint32_t)c.hub_degree;
+    ws->tier1_small = c.tier1_table == 1024;
+    ws->tier2_wide = c.tier2_lanes == 1024;
+    ws->max_slots = (uint32_t)c.max_slots;
+}
+
+// signature of a graph: sizes plus a checksum of its arcs (heads and probabilities)
+__global__ void k_signature(const uint32_t *col, const float *prob, uint64_t m,
+                            unsigned long long *out)
+{
+    unsigned long long h = 0;
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = ((uint64_t)col[e] << 32) ^ __float_as_uint(prob[e]) ^ (e * IM_GOLDEN);
+        h += sm64_finalise(x);
+    }
+    h = wave_sum_u64(h);
+    if ((threadIdx.x & 63) == 0 && h) atomicAdd(out, h);
+}
+
+struct TuneKey {
+    uint64_t n, m, R, sum;
+    bool operator==(const TuneKey &o) const { return n == o.n && m == o.m && R == o.R && sum == o.sum; }
+};
+static std::vector<std::pair<TuneKey, im_tuning>> g_tune_cache;
+
+static int graph_signature(const im_graph *g, uint32_t R, im_workspace *ws, hipStream_t s, TuneKey *key)
+{
+    fill<unsigned long long>(ws->stats, 1, 0ull, s);
+    if (g->m)
+        k_signature<<<grid_for(g->m, 256, 4096), 256, 0, s>>>(g->col, g->prob, g->m, ws->stats);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ws->host_stats, ws->stats, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *key = TuneKey{g->n, g->m, R, ws->host_stats[0]};
+    return IM_OK;
+}
+
+// time `prepare` (everything up to and including the initial counts) under
+// each candidate schedule; keep the fastest on the workspace
+template <typename Prep>
+static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
+{
+    int rc;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const uint32_t saved_mask = ws->prof_mask;
+    ws->prof_mask = 0;
+    float best_ms = -1.0f;
+    int best_i = 0;
+    for (int i = 0; i < N_SCHEDULES; i++) {
+        apply_schedule(ws, kSchedules[i]);
+        float ms_min = -1.0f;
+        for (int rep = 0; rep < 2; rep++) {
+            if ((rc = prep(true))) break;  // reservation and validation (synchronous)
+            HIPCHK(hipEventRecord(e0, s));
+            rc = prep(false);
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            if (rc) break;
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms_min < 0 || ms < ms_min) ms_min = ms;
+        }
+        if (rc) break;
+        if (best_ms < 0 || ms_min < best_ms) { best_ms = ms_min; best_i = i; }
+    }
+    ws->prof_mask = saved_mask;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    apply_schedule(ws, kSchedules[best_i]);
+    best->hub_degree = kSchedules[best_i].hub_degree;
+    best->tier1_table = kSchedules[best_i].tier1_table;
+    best->tier2_lanes = kSchedules[best_i].tier2_lanes;
+    best->max_slots = kSchedules[best_i].max_slots;
+    best->ms = best_ms;
+    best->tried = N_SCHEDULES;
+    return IM_OK;
+}
+
+static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, bool *hit)
+{
+    for (auto &kv : g_tune_cache)
+        if (kv.first == key) {
+            const im_tuning &t = kv.second;
+            apply_schedule(ws, Schedule{t.hub_degree, t.tier1_table, t.tier2_lanes, t.max_slots});
+            if (out) { *out = t; out->tried = 0; }
+            *hit = true;
+            return IM_OK;
+        }
+    *hit = false;
+    return IM_OK;
+}
+
+extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws,
+                           void *stream, im_tuning *out)
+{
+    int rc;
+    if ((rc = check_args(g, R))) return rc;
+    if (!ws) return im_fail(IM_EINVAL, "null workspace");
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = check_and_reserve(g, R, 0, ws, s))) return rc;
+    TuneKey key;
+    if ((rc = graph_signature(g, R, ws, s, &key))) return rc;
+    bool hit;
+    tune_cached(key, ws, out, &hit);
+    if (hit) return IM_OK;
+    im_tuning best;
+    auto prep = [&](bool reserve) -> int {
+        return reserve ? check_and_reserve(g, R, 0, ws, s) : enqueue_prepare(g, R, seed, 0, ws, s);
+    };
+    if ((rc = tune(ws, s, prep, &best))) return rc;
+    g_tune_cache.push_back({key, best});
+    if (out) *out = best;
+    return IM_OK;
+}
+
+extern "C" int im_autotune_batch(const im_instance *inst, uint32_t count, im_workspace *ws,
+                                 void *stream, im_tuning *out)
+{
+    int rc;
+    if (!inst || !ws || count == 0) return im_fail(IM_EINVAL, "null or empty instances");
+    if (count == 1) return im_autotune(&inst[0].g, inst[0].R, inst[0].seed, ws, stream, out);
+    hipStream_t s = (hipStream_t)stream;
+    im_graph mg;
+    uint32_t Rmax = 0, kmax = 0;
+    im_tuning best;
+    auto prep = [&](bool reserve) -> int {
+        if (reserve) {
+            ws->batch = kSingle;
+            return batch_setup(inst, count, true, ws, s, &mg, &Rmax, &kmax);
+        }
+        return enqueue_prepare(&mg, Rmax, 0, 0, ws, s);
+    };
+    rc = tune(ws, s, prep, &best);
+    ws->batch = kSingle;
+    if (rc) return rc;
+    if (out) *out = best;
+    return IM_OK;
 }
 
 extern "C" int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,

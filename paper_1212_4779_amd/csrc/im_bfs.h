@@ -574,7 +574,8 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
     st_trav = group_sum<NT>(st_trav, L.red);
     st_dec = group_sum<NT>(st_dec, L.red);
     st_ovf = group_sum<NT>(st_ovf, L.red);
-    if (tid == 0) {
+    // workgroups that found no task add nothing (no contended atomics)
+    if (tid == 0 && st_reached + st_ovf) {
         if (MODE == MODE_DEC) atomicAdd(&a.stats[ST_DECREMENTS], (unsigned long long)st_dec);
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_RELAX)], (unsigned long long)st_relax);
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)st_reached);
@@ -768,7 +769,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     reached = group_sum<NT>(reached, L.red);
     trav = group_sum<NT>(trav, L.red);
     dec = group_sum<NT>(dec, L.red);
-    if (tid == 0) {
+    if (tid == 0 && reached) {
         if (MODE == MODE_DEC) atomicAdd(&a.stats[ST_DECREMENTS], (unsigned long long)dec);
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_RELAX)], (unsigned long long)relax);
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)reached);

@@ -1,0 +1,96 @@
+"""Schedules never change results: every engine option combination and the
+autotuner's choice give the oracle's full per-round gain trace."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1212_4779_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+SCHEDULES = [  # (hub degree, tier-1 table, tier-2 lanes, tier-2 slots)
+    (256, 1024, 256, 256), (256, 1024, 1024, 256), (256, 1024, 256, 2048),
+    (1024, 2048, 256, 8), (0, 2048, 1024, 8), (16, 1024, 1024, 64),
+]
+
+
+@pytest.fixture(scope="module")
+def im():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1212_4779_amd as im
+    return im
+
+
+def _dev(im, g):
+    return im.Graph.from_numpy(g.row_ptr, g.col, g.prob, device="cuda:0")
+
+
+def _cases():
+    return [
+        ("nethept_wc", gg.workload_graph("nethept_wc"), 100, 50, 1),
+        ("dense_p30", gg.chung_lu_graph(3000, 24000, 2.3, 7, True, 0.3), 130, 12, 5),
+        ("wc_directed", gg.chung_lu_graph(20000, 160000, 2.3, 11, True, None), 256, 10, 2),
+    ]
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
+def test_every_schedule_gives_the_oracle_trace(im, case):
+    _, g, R, k, seed = case
+    s_ref, g_ref, tr_ref, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    d = _dev(im, g)
+    for hub, t1, lanes, slots in SCHEDULES:
+        ws = im.Workspace()
+        ws.set_hub_degree(hub)
+        ws.set_tier1_table(t1)
+        ws.set_tier2_lanes(lanes)
+        ws.set_max_slots(slots)
+        seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
+        assert seeds.cpu().tolist() == s_ref.tolist(), (hub, t1, lanes, slots)
+        assert gains.cpu().tolist() == g_ref.tolist()
+        assert np.array_equal(tr.cpu().numpy().astype(np.uint32), tr_ref)
+
+
+def test_autotune_choice_and_cache(im):
+    with open(os.path.join(GOLDEN, "nethept_wc.json")) as f:
+        gold = json.load(f)
+    w = gg.WORKLOADS["nethept_wc"]
+    g = gg.workload_graph("nethept_wc")
+    d = _dev(im, g)
+    ws = im.Workspace()
+    t = im.autotune(d, w["R"], w["seed"], ws=ws)
+    assert t["tried"] >= 2 and t["ms"] > 0
+    assert t["tier1_table"] in (1024, 2048) and t["tier2_lanes"] in (256, 1024)
+    seeds, gains, _ = im.select(d, w["R"], w["k"], w["seed"], ws=ws)
+    assert seeds.cpu().tolist() == gold["seeds"]
+    assert gains.cpu().tolist() == gold["gains"]
+    ws2 = im.Workspace()
+    t2 = im.autotune(d, w["R"], w["seed"], ws=ws2)
+    assert t2["tried"] == 0
+    assert {k: t2[k] for k in ("hub_degree", "tier1_table", "tier2_lanes", "max_slots")} == \
+           {k: t[k] for k in ("hub_degree", "tier1_table", "tier2_lanes", "max_slots")}
+
+
+def test_autotune_batch_then_select_batch(im):
+    rng = np.random.default_rng(3)
+    graphs, insts, refs = [], [], []
+    for i in range(6):
+        n = int(rng.integers(300, 3000))
+        g = gg.chung_lu_graph(n, n * 6, 2.5, 100 + i, True, None if i % 2 else 0.05)
+        R, k = int(rng.choice([64, 100, 256])), 5
+        graphs.append(g)
+        insts.append((_dev(im, g), R, k, 1 + i))
+        s, gn, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, 1 + i)
+        refs.append((s.tolist(), gn.tolist()))
+    ws = im.Workspace()
+    t = im.autotune_batch(insts, ws=ws)
+    assert t["tried"] >= 2
+    out = im.select_batch(insts, ws=ws)
+    for (s, gn), (rs, rg) in zip(out, refs):
+        assert s.cpu().tolist() == rs and gn.cpu().tolist() == rg
