@@ -500,7 +500,7 @@ struct FwdArgs {
     HubLists hub;
     uint64_t m;
     uint32_t n, R, W;
-    uint64_t *covered, *newly, *pend, *fdel;
+    uint64_t *covered, *newly, *pend;
     uint64_t *fq0, *fq1;        // frontier entries (word << 32 | node), capacity W*n
     uint32_t *bq0, *bq1;        // per-word frontier queues of the one-workgroup kernel [W][n]
     uint64_t coop_gain;         // rounds whose seed gain reaches this use the cooperative kernel
@@ -828,7 +828,7 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
     }
     uint64_t arcs = 0;
     block_bfs_run<FWB_NT, 8, true>(L, v, tid == 0 ? start : 0ull, a.row, a.col, a.mask + (uint64_t)w * a.m, a.hub,
-                                   a.W, w, a.covered + off, a.newly + off, a.pend + off, nullptr,
+                                   a.W, w, a.covered + off, a.newly + off, a.pend + off, 0u,
                                    a.bq0 + off, a.bq1 + off, a.tnodes + off, arcs);
     const uint32_t nvis = L.nvis;
     uint64_t relax = 0, trav = 0;
@@ -863,9 +863,12 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
 constexpr int PK_NT = 256;
 constexpr int PK_ZERO = 64 * 64 * 2 + 128;  // bcnt, bcur [W][64]; gcnt, mcnt [64]
 
+// pack = false (batches: a reverse task must stay inside one instance):
+// every source is its own task
 __global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, const uint32_t *tcounts,
                                                       const uint64_t *newly, uint32_t n,
-                                                      uint32_t *bcnt, uint32_t *mcnt, uint32_t *mlist)
+                                                      uint32_t *bcnt, uint32_t *mcnt, uint32_t *mlist,
+                                                      bool pack)
 {
     __shared__ uint32_t cnt[64];
     const uint32_t w = blockIdx.y;
@@ -880,7 +883,7 @@ __global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, co
         if (i < c) {
             x = tnodes[off + i];
             const uint64_t b = newly[off + x];
-            if (__popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
+            if (pack && __popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
             else multi = true;
         }
         const uint32_t p = wave_append(multi, &mcnt[w]);
@@ -905,8 +908,9 @@ __global__ __launch_bounds__(64) void k_pack_scan(const uint32_t *bcnt, uint32_t
 __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, const uint32_t *tcounts,
                                                      const uint64_t *newly, uint32_t n,
                                                      const uint32_t *boff, uint32_t *bcur,
-                                                     uint32_t *plist)
+                                                     uint32_t *plist, bool pack)
 {
+    if (!pack) return;
     __shared__ uint32_t cnt[64], base0[64];
     const uint32_t w = blockIdx.y;
     const uint64_t off = (uint64_t)w * n;
@@ -980,7 +984,8 @@ struct im_workspace {
     int device = -1;
     int num_cu = 256;
     uint32_t cap_n = 0, cap_W = 0, cap_k = 0, slots = 0;
-    uint32_t max_slots = 256, slots_cap = 0, slots_n = 0;  // tier-2 slots in use / allocated
+    uint32_t max_slots = 256, slots_n = 0;  // tier-2: slot limit, length of each slot in use
+    uint64_t slots_entries = 0;             // allocated slot entries
     int tier1_small = 1;     // tier-1 table of 1024 entries instead of 2048
     int tier2_wide = 0;      // 1024 lanes per tier-2 task instead of 256
     uint64_t cap_m = 0;
@@ -991,7 +996,7 @@ struct im_workspace {
     // selection state
     uint32_t *gain = nullptr;
     uint8_t *sel = nullptr;
-    uint64_t *covered = nullptr, *newly = nullptr, *fpend = nullptr, *ffdel = nullptr;
+    uint64_t *covered = nullptr, *newly = nullptr, *fpend = nullptr;
     uint64_t *fqa = nullptr, *fqb = nullptr, *fvis = nullptr;
     uint32_t *bqa = nullptr, *bqb = nullptr;
     uint64_t coop_gain = 0;  // every round uses the cooperative forward search
@@ -1023,7 +1028,7 @@ struct im_workspace {
     uint32_t *hnum = nullptr;            // [2] hub counts
     unsigned long long *halloc = nullptr;  // [2] allocation counters
     // block engine slots
-    uint64_t *b_reach = nullptr, *b_pend = nullptr, *b_fdel = nullptr;
+    uint64_t *b_reach = nullptr, *b_pend = nullptr;
     uint32_t *b_qa = nullptr, *b_qb = nullptr, *b_vis = nullptr;
     // lazy evaluation (A9)
     uint32_t cap_celf = 0;
@@ -1143,10 +1148,10 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->row32); dfree(ws->in_row); dfree(ws->in_col); dfree(ws->in2out);
     dfree(ws->cnt); dfree(ws->scan_sums); dfree(ws->mask_out); dfree(ws->mask_in);
     dfree(ws->gain); dfree(ws->sel); dfree(ws->covered); dfree(ws->newly);
-    dfree(ws->fpend); dfree(ws->ffdel); dfree(ws->fqa); dfree(ws->fqb); dfree(ws->fvis); dfree(ws->bqa); dfree(ws->bqb); dfree(ws->fctr);
+    dfree(ws->fpend); dfree(ws->fqa); dfree(ws->fqb); dfree(ws->fvis); dfree(ws->bqa); dfree(ws->bqb); dfree(ws->fctr);
     dfree(ws->pk); dfree(ws->boff); dfree(ws->plist); dfree(ws->mlist);
     dfree(ws->tnodes); dfree(ws->tcounts); dfree(ws->keys); dfree(ws->ovf_q); dfree(ws->ovf_q2); dfree(ws->ctrs);
-    dfree(ws->b_reach); dfree(ws->b_pend); dfree(ws->b_fdel);
+    dfree(ws->b_reach); dfree(ws->b_pend);
     dfree(ws->b_qa); dfree(ws->b_qb); dfree(ws->b_vis);
     for (int d = 0; d < 2; d++) {
         dfree(ws->hslot[d]); dfree(ws->hlist[d]); dfree(ws->hcnt[d]); dfree(ws->hoff[d]);
@@ -1180,28 +1185,32 @@ static uint32_t slots_for(uint32_t n, uint32_t max_slots)
     return (uint32_t)s;
 }
 
-// tier-2 slot arrays for graphs of up to cap_n nodes
-static int reserve_slots(im_workspace *ws)
+// tier-2 slot arrays of slot_len nodes each (the largest instance of a
+// batch, else the graph); every entry of reach and pend is zero at rest,
+// so the arrays may be re-sliced between calls
+static int reserve_slots(im_workspace *ws, uint32_t slot_len)
 {
     int rc;
-    const uint32_t slots = slots_for(ws->cap_n, ws->max_slots);
-    if (slots > ws->slots_cap || ws->cap_n > ws->slots_n) {
-        uint64_t sn = (uint64_t)slots * ws->cap_n;
+    slot_len = std::max<uint32_t>(slot_len, 1);
+    const uint32_t slots = slots_for(slot_len, ws->max_slots);
+    const uint64_t sn = (uint64_t)slots * slot_len;
+    if (sn > ws->slots_entries) {
         if ((rc = dalloc(&ws->b_reach, sn)) || (rc = dalloc(&ws->b_pend, sn)) ||
-            (rc = dalloc(&ws->b_fdel, sn)) || (rc = dalloc(&ws->b_qa, sn)) ||
-            (rc = dalloc(&ws->b_qb, sn)) || (rc = dalloc(&ws->b_vis, sn)))
+            (rc = dalloc(&ws->b_qa, sn)) || (rc = dalloc(&ws->b_qb, sn)) ||
+            (rc = dalloc(&ws->b_vis, sn)))
             return rc;
         HIPCHK(hipMemset(ws->b_reach, 0, sn * sizeof(uint64_t)));
         HIPCHK(hipMemset(ws->b_pend, 0, sn * sizeof(uint64_t)));
-        ws->slots_cap = slots;
-        ws->slots_n = ws->cap_n;
+        ws->slots_entries = sn;
     }
     ws->slots = slots;
+    ws->slots_n = slot_len;
     return IM_OK;
 }
 
 // grow the workspace to hold a graph with n nodes, m arcs, W words, k rounds
-static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint32_t k)
+static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint32_t k,
+                      uint32_t slot_len)
 {
     int rc;
     const bool grow_n = n > ws->cap_n || W > ws->cap_W || ws->gain == nullptr;
@@ -1214,7 +1223,7 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
             (rc = dalloc(&ws->cnt, nn)) || (rc = dalloc(&ws->scan_sums, nn / SCAN_TILE + 2)) ||
             (rc = dalloc(&ws->gain, cn)) || (rc = dalloc(&ws->sel, cn)) ||
             (rc = dalloc(&ws->covered, nW)) || (rc = dalloc(&ws->newly, nW)) ||
-            (rc = dalloc(&ws->fpend, nW)) || (rc = dalloc(&ws->ffdel, nW)) ||
+            (rc = dalloc(&ws->fpend, nW)) ||
             (rc = dalloc(&ws->fqa, nW)) || (rc = dalloc(&ws->fqb, nW)) || (rc = dalloc(&ws->fvis, nW)) ||
             (rc = dalloc(&ws->bqa, nW)) || (rc = dalloc(&ws->bqb, nW)) ||
             (rc = dalloc(&ws->plist, nW)) || (rc = dalloc(&ws->mlist, nW)) ||
@@ -1228,7 +1237,7 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
         HIPCHK(hipMemset(ws->fpend, 0, nW * sizeof(uint64_t)));
         ws->cap_n = cn;
     }
-    if ((rc = reserve_slots(ws))) return rc;
+    if ((rc = reserve_slots(ws, slot_len))) return rc;
     if (grow_m) {
         if ((rc = dalloc(&ws->in_col, cm)) || (rc = dalloc(&ws->in2out, cm)) ||
             (rc = dalloc(&ws->mask_out, cm * cW)) || (rc = dalloc(&ws->mask_in, cm * cW)))
@@ -1380,9 +1389,10 @@ static BfsArgs bfs_args(im_workspace *ws, const uint32_t *row, const uint32_t *c
     BfsArgs a;
     memset(&a, 0, sizeof(a));
     a.row = row; a.col = col; a.mask = mask; a.m = m; a.n = n; a.R = R; a.W = W;
-    a.node_inst = ws->batch.node_inst; a.inst_R = ws->batch.R;
+    a.node_inst = ws->batch.node_inst; a.inst_R = ws->batch.R; a.inst_off = ws->batch.node_off;
+    a.slot_n = ws->slots_n;
     a.gain = ws->gain;
-    a.b_reach = ws->b_reach; a.b_pend = ws->b_pend; a.b_fdel = ws->b_fdel;
+    a.b_reach = ws->b_reach; a.b_pend = ws->b_pend;
     a.b_qa = ws->b_qa; a.b_qb = ws->b_qb; a.b_vis = ws->b_vis;
     a.stats = ws->stats;
     return a;
@@ -1465,7 +1475,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
     f.hub = hub_lists(ws, 0);
     f.n = n; f.R = R; f.W = W;
-    f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend; f.fdel = ws->ffdel;
+    f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend;
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
     f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
     f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
@@ -1488,10 +1498,12 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     {
         PhaseTimer pt(ws, IM_PH_PACK, s);
         dim3 pg(grid_for(n, PK_NT, 64), W);
-        k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist);
+        const bool pack = ws->batch.count == 1;
+        k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist,
+                                          pack);
         k_pack_scan<<<W, 64, 0, s>>>(bcnt, ws->boff, gcnt);
         k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, ws->boff, bcur,
-                                         ws->plist);
+                                         ws->plist, pack);
     }
     BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W);
     a.gcnt = gcnt; a.mcnt = mcnt; a.bcnt = bcnt; a.boff = ws->boff;
@@ -1512,7 +1524,7 @@ static int check_and_reserve(const im_graph *g, uint32_t R, uint32_t k, im_works
                              hipStream_t s)
 {
     int rc;
-    if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, k))) return rc;
+    if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, k, g->n))) return rc;
     return validate(g, ws, s, ws->row32);
 }
 
@@ -2237,7 +2249,7 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
     f.hub = hub_lists(ws, 0);
     f.n = n; f.R = R; f.W = W;
-    f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend; f.fdel = ws->ffdel;
+    f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend;
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
     f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
     f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
@@ -2396,7 +2408,7 @@ extern "C" int im_snapshot_masks(const im_graph *g, uint32_t R, uint64_t seed, u
     if ((rc = check_args(g, R))) return rc;
     if (!ws || (g->m && !mask_out)) return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, 0))) return rc;
+    if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, 0, g->n))) return rc;
     if ((rc = validate(g, ws, s, nullptr))) return rc;
     build_masks(g, R, seed, ws, mask_out, false, s);
     HIPCHK(hipGetLastError());
@@ -2412,7 +2424,7 @@ extern "C" int im_transpose(const im_graph *g, uint32_t *in_row_ptr, uint32_t *i
     if (!ws || !in_row_ptr || (g->m && (!in_col || !in2out)))
         return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = ws_reserve(ws, g->n, g->m, 1, 0))) return rc;
+    if ((rc = ws_reserve(ws, g->n, g->m, 1, 0, g->n))) return rc;
     if ((rc = validate(g, ws, s, ws->row32))) return rc;
     build_reverse(g, ws, s);
     HIPCHK(hipMemcpyAsync(in_row_ptr, ws->in_row, ((uint64_t)g->n + 1) * sizeof(uint32_t),
@@ -2647,11 +2659,12 @@ static int batch_setup(const im_instance *inst, uint32_t count, bool need_out, i
 {
     int rc;
     uint64_t N = 0, M = 0, K = 0;
-    uint32_t Rmax = 0, kmax = 0;
+    uint32_t Rmax = 0, kmax = 0, nmax = 0;
     for (uint32_t i = 0; i < count; i++) {
         if ((rc = check_args(&inst[i].g, inst[i].R)))
             return im_fail(rc, "instance %u: %s", i, g_err.c_str());
         if (inst[i].k > inst[i].g.n) return im_fail(IM_EINVAL, "instance %u: k exceeds n", i);
+        nmax = std::max(nmax, inst[i].g.n);
         N += inst[i].g.n;
         M += inst[i].g.m;
         K += inst[i].k;
@@ -2663,7 +2676,7 @@ static int batch_setup(const im_instance *inst, uint32_t count, bool need_out, i
     if (K && !need_out) return im_fail(IM_EINVAL, "null seeds or gains output");
     const uint32_t W = (Rmax + 63) / 64;
     ws->batch.count = count;  // sizes the per-round key arrays
-    rc = ws_reserve(ws, (uint32_t)N, M, W, kmax);
+    rc = ws_reserve(ws, (uint32_t)N, M, W, kmax, nmax);
     ws->batch.count = 1;
     if (!rc) rc = reserve_batch(ws, count, N, M);
     if (rc) return rc;

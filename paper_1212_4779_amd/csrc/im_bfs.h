@@ -61,6 +61,8 @@ struct BfsArgs {
     uint32_t n, R, W;
     const uint32_t *node_inst;  // batches: instance of each node (nullptr: one graph)
     const uint32_t *inst_R;     // batches: snapshots per instance
+    const uint32_t *inst_off;   // batches: first node of each instance
+    uint32_t slot_n;            // length of each global-engine slot array
     HubLists hub;
     const uint64_t *prune;    // [W][n] or nullptr
     uint32_t *gain;           // [n]
@@ -86,8 +88,8 @@ struct BfsArgs {
     uint32_t *out_n;
     uint32_t *grab;           // task counter of this launch (zero before launch)
     // global-engine slots
-    uint64_t *b_reach, *b_pend, *b_fdel;   // [slots][n]
-    uint32_t *b_qa, *b_qb, *b_vis;         // [slots][n]
+    uint64_t *b_reach, *b_pend;            // [slots][slot_n], indexed by node - base
+    uint32_t *b_qa, *b_qb, *b_vis;         // [slots][slot_n], node ids
     unsigned long long *stats;
     int pass, tier;
     int st_trav;
@@ -600,27 +602,29 @@ struct BlockLds {
     HubBatch<NT, 16> H;
 };
 
-__device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, uint32_t *vis,
-                                             uint32_t *nxt, uint32_t *nvis, uint32_t *nn,
-                                             uint32_t v, uint64_t bits)
+// reach and pend are indexed by v - base (the task's instance's first node)
+__device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, uint32_t base,
+                                             uint32_t *vis, uint32_t *nxt, uint32_t *nvis,
+                                             uint32_t *nn, uint32_t v, uint64_t bits)
 {
-    uint64_t old = atomicOr((unsigned long long *)&reach[v], (unsigned long long)bits);
+    uint64_t old = atomicOr((unsigned long long *)&reach[v - base], (unsigned long long)bits);
     uint64_t nb = bits & ~old;
     if (!nb) return;
     if (old == 0) vis[atomicAdd(nvis, 1u)] = v;
-    uint64_t op = atomicOr((unsigned long long *)&pend[v], (unsigned long long)nb);
+    uint64_t op = atomicOr((unsigned long long *)&pend[v - base], (unsigned long long)nb);
     if (op == 0) nxt[atomicAdd(nn, 1u)] = v;
 }
 
 // Run one task to its fixpoint; afterwards vis[0..L.nvis) lists every node
 // with reach != 0. Each thread passes its own seed (src, start); start = 0
-// means none. All threads of the workgroup must call it.
+// means none. Every node the task can reach is >= base, and reach / pend
+// hold the nodes from base on. All threads of the workgroup must call it.
 template <int NT, int U, bool PRUNE>
 __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                               const uint32_t *row, const uint32_t *col, const uint64_t *mask,
                               const HubLists &hub, uint32_t W, uint32_t w,
                               const uint64_t *prune, uint64_t *reach, uint64_t *pend,
-                              uint64_t *fdel, uint32_t *qa, uint32_t *qb, uint32_t *vis,
+                              uint32_t base, uint32_t *qa, uint32_t *qb, uint32_t *vis,
                               uint64_t &arcs)
 {
     constexpr uint32_t NONE = 0xFFFFFFFFu;
@@ -628,7 +632,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
     if (tid == 0) { L.nf = 0; L.nn = 0; L.nvis = 0; L.H.n = 0; L.levels = 0; L.entries = 0; }
     __syncthreads();
     // seeds: every lane with start bits (lanes 0..63 for multi-source tasks)
-    if (start) global_relax(reach, pend, vis, qa, &L.nvis, &L.nf, src, start);
+    if (start) global_relax(reach, pend, base, vis, qa, &L.nvis, &L.nf, src, start);
     __syncthreads();
     uint32_t *cur = qa, *nxt = qb;
     for (;;) {
@@ -644,7 +648,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 rs = row[x];
                 deg = row[x + 1] - rs;
                 // bits gained since the last expansion (later ones re-queue x)
-                d = atomicExch((unsigned long long *)&pend[x], 0ull);
+                d = atomicExch((unsigned long long *)&pend[x - base], 0ull);
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, 0u, d);
                     deg = 0; d = 0;
@@ -687,7 +691,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (bb[u]) global_relax(reach, pend, vis, nxt, &L.nvis, &L.nn, vv[u], bb[u]);
+                    if (bb[u]) global_relax(reach, pend, base, vis, nxt, &L.nvis, &L.nn, vv[u], bb[u]);
             }
             __syncthreads();
             // hub expansions of this tile: only the arcs live in the delta's snapshots
@@ -696,7 +700,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 auto relax = [&](uint32_t, uint32_t v, uint64_t bits) {
                     if (!bits) return;
                     if (PRUNE) bits &= ~prune[v];
-                    if (bits) global_relax(reach, pend, vis, nxt, &L.nvis, &L.nn, v, bits);
+                    if (bits) global_relax(reach, pend, base, vis, nxt, &L.nvis, &L.nn, v, bits);
                 };
                 expand_hubs<NT, 16, U>(L.H, nhub, hub, W, word_of, relax, [] {}, arcs);
             }
@@ -714,12 +718,11 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     __shared__ uint32_t wpre[65];
     const int tid = threadIdx.x;
     const uint64_t slot = blockIdx.x;
-    uint64_t *reach = a.b_reach + slot * a.n;
-    uint64_t *pend = a.b_pend + slot * a.n;
-    uint64_t *fdel = a.b_fdel + slot * a.n;
-    uint32_t *qa = a.b_qa + slot * a.n;
-    uint32_t *qb = a.b_qb + slot * a.n;
-    uint32_t *vis = a.b_vis + slot * a.n;
+    uint64_t *reach = a.b_reach + slot * a.slot_n;
+    uint64_t *pend = a.b_pend + slot * a.slot_n;
+    uint32_t *qa = a.b_qa + slot * a.slot_n;
+    uint32_t *qb = a.b_qb + slot * a.slot_n;
+    uint32_t *vis = a.b_vis + slot * a.slot_n;
     if (tid == 0 && MODE == MODE_DEC) fill_wpre(a, wpre);
     __syncthreads();
     const uint32_t nq = *a.in_n;
@@ -742,22 +745,25 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         }
         __syncthreads();
         const uint32_t src0 = L.task;
+        // a task of a batch never leaves its instance (reverse tasks are not
+        // packed across instances), so the slot holds that instance's nodes
+        const uint32_t base = a.node_inst ? a.inst_off[a.node_inst[src0]] : 0u;
         const uint64_t *mask = a.mask + (uint64_t)w * a.m;
         const uint64_t *prune = PRUNE ? a.prune + (uint64_t)w * a.n : nullptr;
         block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.W, w, prune, reach,
-                                    pend, fdel, qa, qb, vis, arcs);
+                                    pend, base, qa, qb, vis, arcs);
         const uint32_t nvis = L.nvis;
         uint64_t cnt = 0;
         for (uint32_t i = tid; i < nvis; i += NT) {
             uint32_t x = vis[i];
-            uint32_t pc = (uint32_t)__popcll(reach[x]);
+            uint32_t pc = (uint32_t)__popcll(reach[x - base]);
             uint32_t dg = a.row[x + 1] - a.row[x];
             relax += dg;
             reached += 1;
             trav += (uint64_t)pc * dg;
             if (MODE == MODE_COUNT) cnt += pc;
             else { atomicSub(&a.gain[x], pc); dec += pc; }
-            reach[x] = 0;
+            reach[x - base] = 0;
         }
         if (MODE == MODE_COUNT) {
             cnt = group_sum<NT>(cnt, L.red);
