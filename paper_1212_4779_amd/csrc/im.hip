@@ -863,12 +863,9 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
 constexpr int PK_NT = 256;
 constexpr int PK_ZERO = 64 * 64 * 2 + 128;  // bcnt, bcur [W][64]; gcnt, mcnt [64]
 
-// pack = false (batches: a reverse task must stay inside one instance):
-// every source is its own task
 __global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, const uint32_t *tcounts,
                                                       const uint64_t *newly, uint32_t n,
-                                                      uint32_t *bcnt, uint32_t *mcnt, uint32_t *mlist,
-                                                      bool pack)
+                                                      uint32_t *bcnt, uint32_t *mcnt, uint32_t *mlist)
 {
     __shared__ uint32_t cnt[64];
     const uint32_t w = blockIdx.y;
@@ -883,7 +880,7 @@ __global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, co
         if (i < c) {
             x = tnodes[off + i];
             const uint64_t b = newly[off + x];
-            if (pack && __popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
+            if (__popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
             else multi = true;
         }
         const uint32_t p = wave_append(multi, &mcnt[w]);
@@ -908,9 +905,8 @@ __global__ __launch_bounds__(64) void k_pack_scan(const uint32_t *bcnt, uint32_t
 __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, const uint32_t *tcounts,
                                                      const uint64_t *newly, uint32_t n,
                                                      const uint32_t *boff, uint32_t *bcur,
-                                                     uint32_t *plist, bool pack)
+                                                     uint32_t *plist)
 {
-    if (!pack) return;
     __shared__ uint32_t cnt[64], base0[64];
     const uint32_t w = blockIdx.y;
     const uint64_t off = (uint64_t)w * n;
@@ -1498,12 +1494,10 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     {
         PhaseTimer pt(ws, IM_PH_PACK, s);
         dim3 pg(grid_for(n, PK_NT, 64), W);
-        const bool pack = ws->batch.count == 1;
-        k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist,
-                                          pack);
+        k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist);
         k_pack_scan<<<W, 64, 0, s>>>(bcnt, ws->boff, gcnt);
         k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, ws->boff, bcur,
-                                         ws->plist, pack);
+                                         ws->plist);
     }
     BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W);
     a.gcnt = gcnt; a.mcnt = mcnt; a.bcnt = bcnt; a.boff = ws->boff;

@@ -599,6 +599,8 @@ struct BlockLds {
     uint32_t wsum[NT / 64 + 1];
     uint32_t nf, nn, nvis, task, levels, entries;
     unsigned long long red[NT / 64];
+    uint32_t gsrc[64];
+    uint64_t gbits[64];
     HubBatch<NT, 16> H;
 };
 
@@ -726,6 +728,11 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     if (tid == 0 && MODE == MODE_DEC) fill_wpre(a, wpre);
     __syncthreads();
     const uint32_t nq = *a.in_n;
+    // In a batch a packed reverse task may hold sources of several instances;
+    // its sources are then searched one after the other, each inside its own
+    // instance (their bits are disjoint, so the decrements add up to those of
+    // the joint search). A single graph searches all sources together.
+    const bool split = a.node_inst != nullptr;
     uint64_t arcs = 0, relax = 0, reached = 0, trav = 0, dec = 0;
     for (;;) {
         if (tid == 0) L.task = atomicAdd(a.grab, 1u);
@@ -733,43 +740,50 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         const uint32_t q = L.task;
         __syncthreads();
         if (q >= nq) break;
-        uint32_t src = 0, w = 0;
-        uint64_t bits = 0;
+        uint32_t w = 0;
         {
             uint32_t ww, ss;
             uint64_t bb;
             task_source(a, MODE, a.in_q[q], wpre, (uint32_t)(tid & 63), ww, ss, bb);
             w = ww;
-            if (tid < 64) { src = ss; bits = bb; }
-            if (tid == 0) L.task = ss;  // COUNT tasks have one source, on lane 0
+            if (tid < 64) { L.gsrc[tid] = ss; L.gbits[tid] = bb; }
         }
         __syncthreads();
-        const uint32_t src0 = L.task;
-        // a task of a batch never leaves its instance (reverse tasks are not
-        // packed across instances), so the slot holds that instance's nodes
-        const uint32_t base = a.node_inst ? a.inst_off[a.node_inst[src0]] : 0u;
         const uint64_t *mask = a.mask + (uint64_t)w * a.m;
         const uint64_t *prune = PRUNE ? a.prune + (uint64_t)w * a.n : nullptr;
-        block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.W, w, prune, reach,
-                                    pend, base, qa, qb, vis, arcs);
-        const uint32_t nvis = L.nvis;
-        uint64_t cnt = 0;
-        for (uint32_t i = tid; i < nvis; i += NT) {
-            uint32_t x = vis[i];
-            uint32_t pc = (uint32_t)__popcll(reach[x - base]);
-            uint32_t dg = a.row[x + 1] - a.row[x];
-            relax += dg;
-            reached += 1;
-            trav += (uint64_t)pc * dg;
-            if (MODE == MODE_COUNT) cnt += pc;
-            else { atomicSub(&a.gain[x], pc); dec += pc; }
-            reach[x - base] = 0;
+        for (int l = 0; l < (split ? 64 : 1); l++) {
+            if (split && L.gbits[l] == 0) continue;   // uniform: read from LDS
+            // COUNT tasks have one source, on lane 0
+            const uint32_t src0 = L.gsrc[l];
+            uint32_t src = 0;
+            uint64_t bits = 0;
+            if (split) {
+                if (tid == 0) { src = src0; bits = L.gbits[l]; }
+            } else if (tid < 64) {
+                src = L.gsrc[tid]; bits = L.gbits[tid];
+            }
+            const uint32_t base = split ? a.inst_off[a.node_inst[src0]] : 0u;
+            block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.W, w, prune, reach,
+                                        pend, base, qa, qb, vis, arcs);
+            const uint32_t nvis = L.nvis;
+            uint64_t cnt = 0;
+            for (uint32_t i = tid; i < nvis; i += NT) {
+                uint32_t x = vis[i];
+                uint32_t pc = (uint32_t)__popcll(reach[x - base]);
+                uint32_t dg = a.row[x + 1] - a.row[x];
+                relax += dg;
+                reached += 1;
+                trav += (uint64_t)pc * dg;
+                if (MODE == MODE_COUNT) cnt += pc;
+                else { atomicSub(&a.gain[x], pc); dec += pc; }
+                reach[x - base] = 0;
+            }
+            if (MODE == MODE_COUNT) {
+                cnt = group_sum<NT>(cnt, L.red);
+                if (tid == 0) atomicAdd(&a.gain[src0], (uint32_t)cnt);
+            }
+            __syncthreads();
         }
-        if (MODE == MODE_COUNT) {
-            cnt = group_sum<NT>(cnt, L.red);
-            if (tid == 0) atomicAdd(&a.gain[src0], (uint32_t)cnt);
-        }
-        __syncthreads();
     }
     relax = group_sum<NT>(relax, L.red);
     reached = group_sum<NT>(reached, L.red);
