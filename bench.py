@@ -58,26 +58,27 @@ KERNEL_NAMES = {
 }
 
 
-def source_digest():
+def source_digest(files):
     h = hashlib.sha256()
-    for f in ("im.hip", "im_bfs.h", "im_device.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1212_4779_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(phase, per_launch_units):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def load_traffic(phase, workload):
+    """HBM bytes per launch of `phase` from the committed rocprofv3 counter
+    summary (profiles/traffic.json), if it was taken on this workload and on
+    the current source of that kernel; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_digest") != source_digest():
-        return None
     k = t.get("kernels", {}).get(phase)
-    if not k:
+    if t.get("workload") != workload or not k:
+        return None
+    if k.get("source_digest") != source_digest(k.get("sources", [])):
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -234,6 +235,10 @@ def main():
     ap.add_argument("--workload", default="million_uic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--schedule", default=None,
+                    help="hub,tier1,lanes,slots: use this engine schedule instead of autotuning")
+    ap.add_argument("--once", action="store_true",
+                    help="one selection and one 1 GiB read + 1 GiB write stream (counter profiling)")
     args = ap.parse_args()
 
     def log(msg):
@@ -264,8 +269,27 @@ def main():
     R, k, seed = w["R"], w["k"], w["seed"]
     W = (R + 63) // 64
     ws = im.Workspace()
-    tuning = im.autotune(dg, R, seed, ws=ws)
-    log(f"autotune: {tuning}")
+    if args.schedule:
+        hub, t1, lanes, slots = (int(x) for x in args.schedule.split(","))
+        ws.set_hub_degree(hub)
+        ws.set_tier1_table(t1)
+        ws.set_tier2_lanes(lanes)
+        ws.set_max_slots(slots)
+        tuning = {"hub_degree": hub, "tier1_table": t1, "tier2_lanes": lanes, "max_slots": slots,
+                  "tried": 0}
+    else:
+        tuning = im.autotune(dg, R, seed, ws=ws)
+    log(f"schedule: {tuning}")
+    if args.once:
+        im.select(dg, R, k, seed, ws=ws)
+        torch.cuda.synchronize()
+        # calibration for the HBM byte counters: a streaming kernel that reads
+        # 1 GiB and writes 1 GiB (elementwise multiply of 2^28 floats)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = src.mul(1.0)
+        torch.cuda.synchronize()
+        log(f"once: selection and a {4 * dst.numel()} B read+write stream done")
+        return
 
     for _ in range(args.warmup):
         im.select(dg, R, k, seed, ws=ws)
@@ -301,7 +325,7 @@ def main():
     avg_launch_ms = dprof[0] / max(1, dprof[1])
     bytes_per_launch = kb[dom] / launches_per_step
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
-    traffic = load_traffic(dom, None)
+    traffic = load_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dom], "phase": dom,

@@ -190,9 +190,10 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
 /* Schedule autotuning (synchronous). A schedule -- hub threshold, tier-1
  * table, tier-2 lanes and slots (the IM_OPT_* options above) -- decides only
  * where each reachability task runs, never a result. Each candidate schedule
- * is timed on the initial reach counts of the given graph (Algorithm 2's
- * initial loop, run by the same engines as every later pass) and the
- * fastest is set on the workspace and returned in *out (host, may be NULL).
+ * is timed on a trial selection of the given graph -- the initial reach
+ * counts (Algorithm 2's initial loop) and the first four greedy rounds --
+ * and the fastest is set on the workspace and returned in *out (host, may
+ * be NULL).
  * im_autotune caches its choice per graph signature (n, m, R and a checksum
  * of col and prob) for the life of the process; a cached choice is applied
  * without timing (out->tried = 0). im_autotune_batch tunes on the instances
@@ -202,7 +203,7 @@ typedef struct im_tuning {
     int32_t  tier1_table;
     int32_t  tier2_lanes;
     int32_t  max_slots;
-    float    ms;       /* initial-count time of the chosen schedule */
+    float    ms;       /* trial time of the chosen schedule         */
     uint32_t tried;    /* schedules timed (0: taken from the cache)  */
 } im_tuning;
 int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,

@@ -1621,23 +1621,33 @@ __device__ __forceinline__ uint32_t score_bits(float f)
 }
 
 // static inputs of the network (see im_mlp.h), from the out-CSR and the
-// reverse CSR's row offsets
-__global__ void k_features(const uint32_t *row, const uint32_t *col, const float *prob,
-                           const uint32_t *in_row, uint32_t n, float *feat)
+// reverse CSR's row offsets; one wavefront per node, so that a hub's arcs
+// are summed by 64 lanes (fixed lane order: deterministic)
+__global__ __launch_bounds__(256) void k_features(const uint32_t *row, const uint32_t *col,
+                                                  const float *prob, const uint32_t *in_row,
+                                                  uint32_t n, float *feat)
 {
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * 256u) >> 6;
+    for (uint32_t u = wave; u < n; u += nwaves) {
         const uint32_t rs = row[u], re = row[u + 1];
         float ps = 0.0f;
         uint64_t two = 0;
-        for (uint32_t e = rs; e < re; e++) {
+        for (uint32_t e = rs + lane; e < re; e += 64) {
             ps += prob[e];
             const uint32_t v = col[e];
             two += row[v + 1] - row[v];
         }
-        feat[(uint64_t)u * 4 + 0] = log1pf((float)(in_row[u + 1] - in_row[u]));
-        feat[(uint64_t)u * 4 + 1] = log1pf((float)(re - rs));
-        feat[(uint64_t)u * 4 + 2] = log1pf(ps);
-        feat[(uint64_t)u * 4 + 3] = log1pf((float)two);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) ps += __shfl_xor(ps, d, 64);
+        two = wave_sum_u64(two);
+        if (lane == 0) {
+            feat[(uint64_t)u * 4 + 0] = log1pf((float)(in_row[u + 1] - in_row[u]));
+            feat[(uint64_t)u * 4 + 1] = log1pf((float)(re - rs));
+            feat[(uint64_t)u * 4 + 2] = log1pf(ps);
+            feat[(uint64_t)u * 4 + 3] = log1pf((float)two);
+        }
     }
 }
 
@@ -2282,8 +2292,8 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
     fill<uint32_t>(ws->c_ctl, CC_COUNT, 0u, s);
     if (learned) {
         PhaseTimer pt(ws, IM_PH_SCORE, s);
-        k_features<<<grid_for(n, 256), 256, 0, s>>>(ws->row32, g->col, g->prob, ws->in_row, n,
-                                                    ws->c_feat);
+        k_features<<<grid_for((uint64_t)n * 64, 256, 16384), 256, 0, s>>>(ws->row32, g->col, g->prob,
+                                                                            ws->in_row, n, ws->c_feat);
         k_celf_score<<<grid_for(n, 256, 4096), 256, 0, s>>>(model->wb, ws->c_feat, ws->c_bound, invR,
                                                             nullptr, n, nullptr, ws->c_score);
     }
@@ -2767,17 +2777,19 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
 // A8: schedule autotuning. A schedule (hub threshold, tier-1 table, tier-2
 // lanes and slots) never changes a result, only where each reachability
 // task runs; the best one depends on the reach-size profile of the graph.
-// Candidates are timed on the initial reach counts (the same engines every
-// later pass uses) and the fastest is kept, cached per graph signature.
+// Candidates are timed on a trial -- the initial reach counts and the first
+// greedy rounds, which exercise every engine -- and the fastest is kept,
+// cached per graph signature.
 // ---------------------------------------------------------------------------
 struct Schedule {
     int32_t hub_degree, tier1_table, tier2_lanes, max_slots;
 };
 static const Schedule kSchedules[] = {
     {256, 1024, 256, 256},  {256, 1024, 1024, 256}, {256, 1024, 256, 2048},
-    {256, 1024, 256, 1024}, {1024, 1024, 1024, 256}, {256, 2048, 256, 2048},
+    {256, 1024, 256, 1024}, {256, 1024, 1024, 1024},
 };
 constexpr int N_SCHEDULES = sizeof(kSchedules) / sizeof(kSchedules[0]);
+constexpr uint32_t TUNE_ROUNDS = 4;   // greedy rounds in a trial
 
 static void apply_schedule(im_workspace *ws, const Schedule &c)
 {
@@ -2892,10 +2904,22 @@ extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_work
     tune_cached(key, ws, out, &hit);
     if (hit) return IM_OK;
     im_tuning best;
+    // the trial: initial counts and the first few greedy rounds (whose
+    // reverse steps are the largest of the selection)
+    const uint32_t kt = std::min<uint32_t>(TUNE_ROUNDS, g->n);
+    uint32_t *sd = nullptr;
+    uint64_t *gd = nullptr;
+    if ((rc = dalloc(&sd, kt)) || (rc = dalloc(&gd, kt))) { dfree(sd); return rc; }
     auto prep = [&](bool reserve) -> int {
-        return reserve ? check_and_reserve(g, R, 0, ws, s) : enqueue_prepare(g, R, seed, 0, ws, s);
+        if (reserve) return check_and_reserve(g, R, kt, ws, s);
+        int r = enqueue_prepare(g, R, seed, kt, ws, s);
+        return r ? r : enqueue_rounds(g, R, kt, sd, gd, nullptr, ws, s);
     };
-    if ((rc = tune(ws, s, prep, &best))) return rc;
+    rc = tune(ws, s, prep, &best);
+    (void)hipStreamSynchronize(s);
+    dfree(sd);
+    dfree(gd);
+    if (rc) return rc;
     g_tune_cache.push_back({key, best});
     if (out) *out = best;
     return IM_OK;
@@ -2911,14 +2935,24 @@ extern "C" int im_autotune_batch(const im_instance *inst, uint32_t count, im_wor
     im_graph mg;
     uint32_t Rmax = 0, kmax = 0;
     im_tuning best;
+    uint64_t K = 0;
+    for (uint32_t i = 0; i < count; i++) K += inst[i].k;
+    uint32_t *sd = nullptr;
+    uint64_t *gd = nullptr;
+    if ((rc = dalloc(&sd, K)) || (rc = dalloc(&gd, K))) { dfree(sd); return rc; }
     auto prep = [&](bool reserve) -> int {
         if (reserve) {
             ws->batch = kSingle;
             return batch_setup(inst, count, true, ws, s, &mg, &Rmax, &kmax);
         }
-        return enqueue_prepare(&mg, Rmax, 0, 0, ws, s);
+        const uint32_t kt = std::min<uint32_t>(TUNE_ROUNDS, kmax);
+        int r = enqueue_prepare(&mg, Rmax, 0, kt, ws, s);
+        return r ? r : enqueue_rounds(&mg, Rmax, kt, sd, gd, nullptr, ws, s);
     };
     rc = tune(ws, s, prep, &best);
+    (void)hipStreamSynchronize(s);
+    dfree(sd);
+    dfree(gd);
     ws->batch = kSingle;
     if (rc) return rc;
     if (out) *out = best;
@@ -2953,8 +2987,8 @@ extern "C" int im_node_features(const im_graph *g, float *feat_out, im_workspace
     if ((rc = check_and_reserve(g, 1, 0, ws, s))) return rc;
     if (g->n == 0) return IM_OK;
     build_reverse(g, ws, s);
-    k_features<<<grid_for(g->n, 256), 256, 0, s>>>(ws->row32, g->col, g->prob, ws->in_row, g->n,
-                                                   feat_out);
+    k_features<<<grid_for((uint64_t)g->n * 64, 256, 16384), 256, 0, s>>>(ws->row32, g->col, g->prob,
+                                                                           ws->in_row, g->n, feat_out);
     HIPCHK(hipGetLastError());
     ws->last_stream = s;
     return IM_OK;
