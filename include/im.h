@@ -76,7 +76,7 @@ int im_workspace_destroy(im_workspace *ws);
  *     16 workgroups per snapshot word); smaller rounds use one workgroup per
  *     word. Default 0 (always the cooperative grid). */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
-       IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6 };
+       IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the

@@ -33,6 +33,7 @@ IM_OPT_LAZY_ENGINE = 3
 IM_OPT_MAX_SLOTS = 4
 IM_OPT_TIER1_TABLE = 5
 IM_OPT_TIER2_LANES = 6
+IM_OPT_SPARSE_LISTS = 7
 
 
 class ImGraph(ctypes.Structure):

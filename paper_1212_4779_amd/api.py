@@ -105,6 +105,10 @@ class Workspace:
         """Lanes per task of the last engine tier (256 or 1024). No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER2_LANES, int(lanes)))
 
+    def set_sparse_lists(self, on):
+        """Per-snapshot live lists for low-degree nodes (1) or masks only (0). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_SPARSE_LISTS, int(on)))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases

@@ -436,6 +436,106 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
     }
 }
 
+// Per-snapshot live lists of the nodes below the hub threshold (degree >= 2;
+// see SparseLists). A workgroup takes chunks of SPB (node, word) pairs: its
+// four wavefronts count each pair's live heads per snapshot bit, the chunk
+// reserves its range of adj with one atomic, and the pairs are filled. A
+// pair whose lists do not fit the capacity, or would hold more than 65535
+// heads, keeps base = IM_EMPTY and is expanded through the masks.
+constexpr int SPB = 64;
+
+__device__ __forceinline__ void sparse_count(const uint64_t *mw, uint32_t e0, uint32_t e1,
+                                             uint32_t *cnt, int lane)
+{
+    cnt[lane] = 0;
+    __syncthreads();
+    for (uint32_t e = e0 + lane; e < e1; e += 64) {
+        uint64_t b = mw[e];
+        while (b) {
+            atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
+            b &= b - 1;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const uint32_t *col,
+                                                      const uint64_t *mask, uint64_t m, uint32_t n,
+                                                      uint32_t W, uint32_t hub_deg, uint32_t *base,
+                                                      uint16_t *cum, uint32_t *adj,
+                                                      unsigned long long *alloc, uint64_t cap)
+{
+    __shared__ uint32_t cnt[4][64];
+    __shared__ uint32_t tot[SPB], off[SPB];
+    __shared__ unsigned long long cbase;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t P = (uint64_t)W * n;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * SPB; c0 < P; c0 += (uint64_t)gridDim.x * SPB) {
+        // count: wavefront wv takes pairs wv, wv+4, ... of the chunk (uniform trip count)
+        for (int q = wv; q < SPB; q += 4) {
+            const uint64_t p = c0 + q;
+            uint32_t w = 0, e0 = 0, e1 = 0;
+            bool elig = false;
+            if (p < P) {
+                w = (uint32_t)(p / n);
+                const uint32_t x = (uint32_t)(p - (uint64_t)w * n);
+                e0 = row[x];
+                e1 = row[x + 1];
+                const uint32_t deg = e1 - e0;
+                elig = deg >= 2 && (hub_deg == 0 || deg < hub_deg);
+            }
+            if (!elig) e1 = e0;
+            sparse_count(mask + (uint64_t)w * m, e0, e1, cnt[wv], lane);
+            const uint32_t c = cnt[wv][lane];
+            const uint32_t incl = wave_incl_scan(c);
+            const uint32_t total = __shfl(incl, 63, 64);
+            const bool keep = elig && total <= 0xFFFFu;
+            if (keep) {
+                cum[p * 65 + lane] = (uint16_t)(incl - c);
+                if (lane == 63) cum[p * 65 + 64] = (uint16_t)total;
+            }
+            if (lane == 0) tot[q] = keep ? total : IM_EMPTY;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            const uint32_t t = tot[lane] == IM_EMPTY ? 0u : tot[lane];
+            const uint32_t incl = wave_incl_scan(t);
+            off[lane] = incl - t;
+            if (lane == 63) cbase = incl ? atomicAdd(alloc, (unsigned long long)incl) : 0ull;
+        }
+        __syncthreads();
+        // fill: recount each pair's bits into cursors, then place its heads
+        for (int q = wv; q < SPB; q += 4) {
+            const uint64_t p = c0 + q;
+            uint32_t w = 0, e0 = 0, e1 = 0;
+            uint32_t b0 = IM_EMPTY;
+            if (p < P && tot[q] != IM_EMPTY && cbase + off[q] + tot[q] <= cap) {
+                w = (uint32_t)(p / n);
+                const uint32_t x = (uint32_t)(p - (uint64_t)w * n);
+                e0 = row[x];
+                e1 = row[x + 1];
+                b0 = (uint32_t)(cbase + off[q]);
+            }
+            if (p < P && lane == 0) base[p] = b0;
+            sparse_count(mask + (uint64_t)w * m, e0, e1, cnt[wv], lane);
+            const uint32_t c = cnt[wv][lane];
+            cnt[wv][lane] = wave_incl_scan(c) - c;   // each bit's list from its start
+            __syncthreads();
+            const uint64_t *mw = mask + (uint64_t)w * m;
+            for (uint32_t e = e0 + lane; e < e1; e += 64) {
+                uint64_t b = mw[e];
+                const uint32_t v = col[e];
+                while (b) {
+                    const uint32_t pos = atomicAdd(&cnt[wv][__ffsll((unsigned long long)b) - 1], 1u);
+                    adj[b0 + pos] = v;
+                    b &= b - 1;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // A4: argmax of (gain, lowest id) over unselected nodes
 // ---------------------------------------------------------------------------
@@ -827,8 +927,9 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
         return;
     }
     uint64_t arcs = 0;
-    block_bfs_run<FWB_NT, 8, true>(L, v, tid == 0 ? start : 0ull, a.row, a.col, a.mask + (uint64_t)w * a.m, a.hub,
-                                   a.W, w, a.covered + off, a.newly + off, a.pend + off, 0u,
+    const SparseLists no_lists = {nullptr, nullptr, nullptr};
+    block_bfs_run<FWB_NT, 8, true, false>(L, v, tid == 0 ? start : 0ull, a.row, a.col, a.mask + (uint64_t)w * a.m, a.hub,
+                                   no_lists, a.n, a.W, w, a.covered + off, a.newly + off, a.pend + off, 0u,
                                    a.bq0 + off, a.bq1 + off, a.tnodes + off, arcs);
     const uint32_t nvis = L.nvis;
     uint64_t relax = 0, trav = 0;
@@ -1022,6 +1123,12 @@ struct im_workspace {
     uint32_t *hslot[2] = {}, *hlist[2] = {}, *hcnt[2] = {}, *hoff[2] = {}, *hadj[2] = {};
     unsigned long long *hbase[2] = {};
     uint32_t *hnum = nullptr;            // [2] hub counts
+    // per-snapshot live lists of the other nodes, per direction
+    int sparse = 1;
+    uint64_t sp_nW = 0, sp_cap = 0;
+    uint32_t *sp_base[2] = {}, *sp_adj[2] = {};
+    uint16_t *sp_cum[2] = {};
+    unsigned long long *sp_alloc = nullptr;  // [2]
     unsigned long long *halloc = nullptr;  // [2] allocation counters
     // block engine slots
     uint64_t *b_reach = nullptr, *b_pend = nullptr;
@@ -1154,6 +1261,8 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
         dfree(ws->hadj[d]); dfree(ws->hbase[d]);
     }
     dfree(ws->hnum); dfree(ws->halloc);
+    for (int d = 0; d < 2; d++) { dfree(ws->sp_base[d]); dfree(ws->sp_cum[d]); dfree(ws->sp_adj[d]); }
+    dfree(ws->sp_alloc);
     dfree(ws->b_node_inst); dfree(ws->b_mcol); dfree(ws->b_mprob); dfree(ws->b_u32);
     dfree(ws->b_u64); dfree(ws->b_desc);
     if (ws->b_host) (void)hipHostFree(ws->b_host);
@@ -1256,6 +1365,22 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
                 (rc = dalloc(&ws->hcnt[d], ch * cW * 64)) || (rc = dalloc(&ws->hoff[d], ch * cW * 65)))
                 return rc;
         ws->cap_hub = ch;
+    }
+    if (ws->sparse) {
+        const uint64_t nW = (uint64_t)ws->cap_n * cW;
+        if (nW > ws->sp_nW) {
+            for (int d = 0; d < 2; d++)
+                if ((rc = dalloc(&ws->sp_base[d], nW)) || (rc = dalloc(&ws->sp_cum[d], nW * 65)))
+                    return rc;
+            if ((rc = dalloc(&ws->sp_alloc, 2))) return rc;
+            ws->sp_nW = nW;
+        }
+        const uint64_t cap = std::min<uint64_t>(16ull * ws->cap_m * cW, 0x7FFFFFFFull);
+        if (cap > ws->sp_cap) {
+            for (int d = 0; d < 2; d++)
+                if ((rc = dalloc(&ws->sp_adj[d], cap))) return rc;
+            ws->sp_cap = cap;
+        }
     }
     const uint64_t nkeys = (uint64_t)(k + 1) * ws->batch.count;
     if (nkeys > ws->cap_keys) {
@@ -1370,6 +1495,29 @@ static void build_hubs(int d, const uint32_t *row, const uint32_t *col, const ui
                                       ws->hadj[d]);
 }
 
+// A2c: per-snapshot live lists of the non-hub nodes for one direction
+static void build_sparse(int d, const uint32_t *row, const uint32_t *col, const uint64_t *mask,
+                         uint32_t n, uint64_t m, uint32_t W, im_workspace *ws, hipStream_t s)
+{
+    if (!ws->sparse || n == 0) return;
+    fill<unsigned long long>(ws->sp_alloc + d, 1, 0ull, s);
+    const uint64_t P = (uint64_t)W * n;
+    const unsigned grid = (unsigned)std::min<uint64_t>((P + SPB - 1) / SPB, 8192);
+    k_sparse_build<<<grid, 256, 0, s>>>(row, col, mask, m, n, W, ws->hub_deg, ws->sp_base[d],
+                                        ws->sp_cum[d], ws->sp_adj[d], ws->sp_alloc + d, ws->sp_cap);
+}
+
+static SparseLists sparse_lists(im_workspace *ws, int d)
+{
+    SparseLists l = {nullptr, nullptr, nullptr};
+    if (ws->sparse) {
+        l.base = ws->sp_base[d];
+        l.cum = ws->sp_cum[d];
+        l.adj = ws->sp_adj[d];
+    }
+    return l;
+}
+
 static HubLists hub_lists(im_workspace *ws, int d)
 {
     HubLists h;
@@ -1450,6 +1598,7 @@ static void initial_gains(const im_graph *g, uint32_t R, im_workspace *ws, uint3
     BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W);
     a.ntasks = n * W;
     a.hub = hub_lists(ws, 0);
+    a.sp = sparse_lists(ws, 0);
     a.pass = PASS_INIT;
     a.st_trav = ST_TRAV_INIT;
     run_tiers<MODE_COUNT, false>(a, ws, ctr, IM_PH_INIT_T0, s);
@@ -1503,6 +1652,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     a.gcnt = gcnt; a.mcnt = mcnt; a.bcnt = bcnt; a.boff = ws->boff;
     a.plist = ws->plist; a.mlist = ws->mlist; a.tbits = ws->newly;
     a.hub = hub_lists(ws, 1);
+    a.sp = sparse_lists(ws, 1);
     a.pass = PASS_REV;
     a.st_trav = ST_TRAV_REV;
     run_tiers<MODE_DEC, false>(a, ws, ctr, IM_PH_REV_T0, s);
@@ -1542,6 +1692,8 @@ static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_
         PhaseTimer pt(ws, IM_PH_HUBS, s);
         build_hubs(0, ws->row32, g->col, ws->mask_out, n, g->m, W, ws, s);
         build_hubs(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
+        build_sparse(0, ws->row32, g->col, ws->mask_out, n, g->m, W, ws, s);
+        build_sparse(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
     }
     initial_gains(g, R, ws, ws->ctrs, s);
     HIPCHK(hipGetLastError());
@@ -2341,6 +2493,7 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
                 a.gain = ws->c_ev;
                 a.prune = ws->covered;
                 a.hub = hub_lists(ws, 0);
+                a.sp = sparse_lists(ws, 0);
                 a.pass = PASS_EVAL;
                 a.st_trav = ST_TRAV_EVAL;
                 run_tiers<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T0, s);
@@ -2607,6 +2760,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
     case IM_OPT_TIER2_LANES:
         if (value != 256 && value != 1024) return im_fail(IM_EINVAL, "tier-2 lanes must be 256 or 1024");
         ws->tier2_wide = value == 1024;
+        return IM_OK;
+    case IM_OPT_SPARSE_LISTS:
+        if (value != 0 && value != 1) return im_fail(IM_EINVAL, "sparse lists must be 0 or 1");
+        ws->sparse = (int)value;
         return IM_OK;
     case IM_OPT_LAZY_ENGINE:
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");

@@ -52,6 +52,55 @@ struct HubLists {
     const uint32_t *adj;
 };
 
+// Per-snapshot live lists of the other nodes (degree >= 2, below the hub
+// threshold): for node x and word w (p = w*n + x) the heads live in snapshot
+// 64w+b are adj[base[p] + cum[p*65+b] .. base[p] + cum[p*65+b+1]);
+// base[p] = IM_EMPTY: x has no lists in word w. A frontier entry whose delta
+// has at most SP_BITS bits is expanded through them when they hold no more
+// heads than x has arcs: the heads carry their single snapshot bit, so only
+// arcs live in the delta's snapshots are read.
+struct SparseLists {
+    const uint32_t *base;   // [W][n], nullptr: no lists
+    const uint16_t *cum;    // [W][n][65]
+    const uint32_t *adj;
+};
+constexpr int SP_BITS = 2;
+
+// Plan the sparse expansion of x with delta d in word w. On success the
+// entry's work is the number of listed heads and (rs, del, aux) encode its
+// two ranges: rs = start of the first, del = start of the second | len0 << 32
+// | len1 << 48, aux = bit0 | bit1 << 8 | 1 << 16 (aux = 0: dense entry).
+__device__ __forceinline__ bool sparse_plan(const SparseLists &sp, uint32_t n, uint32_t w,
+                                            uint32_t x, uint64_t d, uint32_t deg, uint32_t &work,
+                                            uint32_t &rs, uint64_t &del, uint32_t &aux)
+{
+    if (!sp.base || d == 0 || __popcll(d) > SP_BITS || deg < 2) return false;
+    const uint64_t p = (uint64_t)w * n + x;
+    const uint32_t b0 = sp.base[p];
+    if (b0 == IM_EMPTY) return false;
+    const uint16_t *c = sp.cum + p * 65;
+    const uint32_t i0 = (uint32_t)__ffsll((unsigned long long)d) - 1;
+    const uint64_t d1 = d & (d - 1);
+    const uint32_t i1 = d1 ? (uint32_t)__ffsll((unsigned long long)d1) - 1 : i0;
+    const uint32_t c00 = c[i0], c01 = c[i0 + 1], c10 = c[i1], c11 = c[i1 + 1];
+    const uint32_t l0 = c01 - c00, l1 = d1 ? c11 - c10 : 0u;
+    if (l0 + l1 > deg) return false;
+    work = l0 + l1;
+    rs = b0 + c00;
+    del = (uint64_t)(b0 + c10) | ((uint64_t)l0 << 32) | ((uint64_t)l1 << 48);
+    aux = i0 | (i1 << 8) | (1u << 16);
+    return true;
+}
+
+// the r-th listed head of a sparse entry: its position in adj and its bit
+__device__ __forceinline__ void sparse_item(uint32_t rs, uint64_t del, uint32_t aux, uint32_t r,
+                                            uint32_t &pos, uint64_t &bit)
+{
+    const uint32_t l0 = (uint32_t)(del >> 32) & 0xFFFFu;
+    if (r < l0) { pos = rs + r; bit = 1ull << (aux & 63u); }
+    else { pos = (uint32_t)del + (r - l0); bit = 1ull << ((aux >> 8) & 63u); }
+}
+
 struct BfsArgs {
     // graph in the direction of this pass
     const uint32_t *row;      // [n+1]
@@ -64,6 +113,7 @@ struct BfsArgs {
     const uint32_t *inst_off;   // batches: first node of each instance
     uint32_t slot_n;            // length of each global-engine slot array
     HubLists hub;
+    SparseLists sp;
     const uint64_t *prune;    // [W][n] or nullptr
     uint32_t *gain;           // [n]
     // task ids: MODE_COUNT: t in [0, n*W) -> word t/n, node t%n (or, when
@@ -272,6 +322,7 @@ struct LdsState {
     uint32_t c_excl[NT];
     uint32_t c_rs[NT];
     uint32_t c_idx[NT];
+    uint32_t c_aux[NT];   // 0: dense entry, else the sparse plan's bits
     uint64_t c_del[NT];
     uint32_t wsum[NT / 64 + 1];
     unsigned long long red[NT / 64];
@@ -416,7 +467,7 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
         // ---- phase B: expand NT frontier entries per chunk, arcs spread over lanes
         for (uint32_t base = 0; base < nf; base += NT) {
             uint32_t i = base + tid;
-            uint32_t deg = 0, rs = 0, idx = 0;
+            uint32_t deg = 0, rs = 0, idx = 0, aux = 0;
             uint64_t d = 0;
             if (i < nf) {
                 idx = L.fr[cur][i];
@@ -437,6 +488,11 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                         L.s_ovf[s] = 1; deg = 0;
                     } else {
                         d = delta;
+                        uint32_t work, srs, saux;
+                        uint64_t sdel;
+                        if (sparse_plan(a.sp, a.n, L.s_word[s], x, delta, deg, work, srs, sdel, saux)) {
+                            deg = work; rs = srs; d = sdel; aux = saux;
+                        }
                     }
                 }
             }
@@ -446,6 +502,7 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
             L.c_rs[tid] = rs;
             L.c_idx[tid] = idx;
             L.c_del[tid] = d;
+            L.c_aux[tid] = aux;
             __syncthreads();
             const uint32_t nhub = L.H.n;
             st_arcs += total;
@@ -460,25 +517,31 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                     if (j < total) {
                         int k = upper_index<NT>(L.c_excl, j);
                         kk[u] = (uint32_t)k;
-                        ee[u] = L.c_rs[k] + (j - L.c_excl[k]);
+                        ee[u] = j - L.c_excl[k];   // rank within the entry
                     }
                 }
-                // mask word and head id are independent loads: issue all of them
+                // mask word and head id (or the listed head) are independent
+                // loads: issue all of them
 #pragma unroll
                 for (int u = 0; u < U; u++) {
                     bb[u] = 0;
                     vv[u] = 0;
                     if (kk[u] != NONE && !L.s_ovf[L.c_idx[kk[u]] >> LOG_CS]) {
-                        uint64_t w = L.s_word[L.c_idx[kk[u]] >> LOG_CS];
-                        bb[u] = a.mask[w * a.m + ee[u]];
-                        vv[u] = a.col[ee[u]];
+                        const uint32_t k = kk[u], ax = L.c_aux[k];
+                        if (ax) {
+                            uint32_t pos;
+                            sparse_item(L.c_rs[k], L.c_del[k], ax, ee[u], pos, bb[u]);
+                            vv[u] = a.sp.adj[pos];
+                        } else {
+                            const uint32_t e = L.c_rs[k] + ee[u];
+                            uint64_t w = L.s_word[L.c_idx[k] >> LOG_CS];
+                            bb[u] = a.mask[w * a.m + e] & L.c_del[k];
+                            vv[u] = a.col[e];
+                        }
                     } else {
                         kk[u] = NONE;
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < U; u++)
-                    if (kk[u] != NONE) bb[u] &= L.c_del[kk[u]];
                 if (PRUNE) {
 #pragma unroll
                     for (int u = 0; u < U; u++)
@@ -595,6 +658,7 @@ template <int NT>
 struct BlockLds {
     uint32_t scan[NT];
     uint32_t rs[NT];
+    uint32_t aux[NT];
     uint64_t del[NT];
     uint32_t wsum[NT / 64 + 1];
     uint32_t nf, nn, nvis, task, levels, entries;
@@ -621,10 +685,11 @@ __device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, ui
 // with reach != 0. Each thread passes its own seed (src, start); start = 0
 // means none. Every node the task can reach is >= base, and reach / pend
 // hold the nodes from base on. All threads of the workgroup must call it.
-template <int NT, int U, bool PRUNE>
+template <int NT, int U, bool PRUNE, bool SPARSE = true>
 __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                               const uint32_t *row, const uint32_t *col, const uint64_t *mask,
-                              const HubLists &hub, uint32_t W, uint32_t w,
+                              const HubLists &hub, const SparseLists &sp, uint32_t n,
+                              uint32_t W, uint32_t w,
                               const uint64_t *prune, uint64_t *reach, uint64_t *pend,
                               uint32_t base, uint32_t *qa, uint32_t *qb, uint32_t *vis,
                               uint64_t &arcs)
@@ -642,7 +707,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
         if (nf == 0) break;
         for (uint32_t tile = 0; tile < nf; tile += NT) {
             uint32_t i = tile + tid;
-            uint32_t deg = 0, rs = 0;
+            uint32_t deg = 0, rs = 0, aux = 0;
             uint64_t d = 0;
             if (i < nf) {
                 uint32_t x = cur[i];
@@ -654,6 +719,12 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, 0u, d);
                     deg = 0; d = 0;
+                } else if (SPARSE) {
+                    uint32_t work, srs, saux;
+                    uint64_t sdel;
+                    if (sparse_plan(sp, n, w, x, d, deg, work, srs, sdel, saux)) {
+                        deg = work; rs = srs; d = sdel; aux = saux;
+                    }
                 }
             }
             uint32_t total;
@@ -661,6 +732,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
             L.scan[tid] = ex;
             L.rs[tid] = rs;
             L.del[tid] = d;
+            L.aux[tid] = aux;
             __syncthreads();
             const uint32_t nhub = L.H.n;
             arcs += total;
@@ -675,17 +747,24 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                     if (j < total) {
                         int k = upper_index<NT>(L.scan, j);
                         kk[u] = (uint32_t)k;
-                        ee[u] = L.rs[k] + (j - L.scan[k]);
+                        ee[u] = j - L.scan[k];   // rank within the entry
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    bb[u] = kk[u] != NONE ? mask[ee[u]] : 0ull;
-                    vv[u] = kk[u] != NONE ? col[ee[u]] : 0u;
+                    bb[u] = 0;
+                    vv[u] = 0;
+                    if (kk[u] != NONE) {
+                        const uint32_t k = kk[u];
+                        const uint32_t ax = SPARSE ? L.aux[k] : 0u;
+                        uint32_t pos = L.rs[k] + ee[u];
+                        uint64_t bit = 0;
+                        if (ax) sparse_item(L.rs[k], L.del[k], ax, ee[u], pos, bit);
+                        const uint32_t *heads = ax ? sp.adj : col;
+                        vv[u] = heads[pos];
+                        bb[u] = ax ? bit : (mask[pos] & L.del[k]);
+                    }
                 }
-#pragma unroll
-                for (int u = 0; u < U; u++)
-                    if (kk[u] != NONE) bb[u] &= L.del[kk[u]];
                 if (PRUNE) {
 #pragma unroll
                     for (int u = 0; u < U; u++)
@@ -763,8 +842,8 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
                 src = L.gsrc[tid]; bits = L.gbits[tid];
             }
             const uint32_t base = split ? a.inst_off[a.node_inst[src0]] : 0u;
-            block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.W, w, prune, reach,
-                                        pend, base, qa, qb, vis, arcs);
+                block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.sp, a.n, a.W, w, prune,
+                                        reach, pend, base, qa, qb, vis, arcs);
             const uint32_t nvis = L.nvis;
             uint64_t cnt = 0;
             for (uint32_t i = tid; i < nvis; i += NT) {
