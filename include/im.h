@@ -72,11 +72,12 @@ int im_workspace_destroy(im_workspace *ws);
  *     of a pass) are expanded through per-snapshot live lists instead of the
  *     snapshot masks; 0 disables the lists; otherwise >= 16. Default 256.
  *   IM_OPT_COOP_GAIN: rounds whose seed gain (summed over snapshots) is at
- *     least this value run the forward search on a cooperative grid (about
- *     16 workgroups per snapshot word); smaller rounds use one workgroup per
- *     word. Default 0 (always the cooperative grid). */
+ *     least this value run the forward search on a cooperative grid
+ *     (IM_OPT_FWD_GROUPS workgroups per snapshot word); smaller rounds use
+ *     one workgroup per word. Default 0 (always the cooperative grid). */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
-       IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7 };
+       IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
+       IM_OPT_FWD_GROUPS = 8 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -189,7 +190,8 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
 
 /* Schedule autotuning (synchronous). A schedule -- hub threshold, tier-1
  * table, tier-2 lanes and slots (the IM_OPT_* options above) -- decides only
- * where each reachability task runs, never a result. Each candidate schedule
+ * where each reachability task runs, never a result (the forward-search
+ * engine, IM_OPT_COOP_GAIN, is part of it). Each candidate schedule
  * is timed on a trial selection of the given graph -- the initial reach
  * counts (Algorithm 2's initial loop) and the first four greedy rounds --
  * and the fastest is set on the workspace and returned in *out (host, may
@@ -203,8 +205,9 @@ typedef struct im_tuning {
     int32_t  tier1_table;
     int32_t  tier2_lanes;
     int32_t  max_slots;
-    float    ms;       /* trial time of the chosen schedule         */
-    uint32_t tried;    /* schedules timed (0: taken from the cache)  */
+    int32_t  coop_forward; /* 1: cooperative forward search (IM_OPT_COOP_GAIN 0), 0: one workgroup per word */
+    float    ms;           /* trial time of the chosen schedule         */
+    uint32_t tried;        /* schedules timed (0: taken from the cache)  */
 } im_tuning;
 int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,
                 im_tuning *out);
@@ -217,10 +220,19 @@ int im_autotune_batch(const im_instance *inst, uint32_t count, im_workspace *ws,
  * gains_out). im_plan_launch enqueues one replay on `stream`: every replay
  * recomputes everything from the graph arrays as they are at that time (they
  * must keep their shape; their contents may change). Replays of one plan must
- * not overlap. */
+ * not overlap. A schedule that im_autotune chose earlier in the process for
+ * a graph with the same signature is used by the plan. */
 typedef struct im_plan im_plan;
 int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
                    uint32_t *seeds_out, uint64_t *gains_out, void *stream, im_plan **plan);
+/* The batched selection (im_select_batch) captured into one HIP graph:
+ * validation and the instance tables are done once here (synchronous); a
+ * replay merges the instances' arrays again and runs the whole batched
+ * selection, so one launch selects the seeds of every instance. `tuned`
+ * (may be NULL) lends its engine schedule, e.g. one set by
+ * im_autotune_batch. count >= 2. */
+int im_plan_create_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
+                         uint64_t *gains_out, im_workspace *tuned, void *stream, im_plan **plan);
 int im_plan_launch(im_plan *plan, void *stream);
 int im_plan_stats(im_plan *plan, im_stats *out);   /* synchronous; last replay */
 int im_plan_destroy(im_plan *plan);

@@ -20,7 +20,7 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_select_batch", "im_mlp_create", "im_mlp_destroy", "im_mlp_set_params",
            "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
            "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy",
-           "im_autotune", "im_autotune_batch")
+           "im_autotune", "im_autotune_batch", "im_plan_create_batch")
 IM_MLP_NPARAM = 4609
 IM_PH_MAX = 24
 
@@ -34,6 +34,7 @@ IM_OPT_MAX_SLOTS = 4
 IM_OPT_TIER1_TABLE = 5
 IM_OPT_TIER2_LANES = 6
 IM_OPT_SPARSE_LISTS = 7
+IM_OPT_FWD_GROUPS = 8
 
 
 class ImGraph(ctypes.Structure):
@@ -75,7 +76,7 @@ class ImStats(ctypes.Structure):
 class ImTuning(ctypes.Structure):
     _fields_ = [("hub_degree", ctypes.c_int32), ("tier1_table", ctypes.c_int32),
                 ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("tried", ctypes.c_uint32)]
+                ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -134,6 +135,7 @@ def lib():
         L.im_select_lazy.argtypes = [G, u32, u32, u64, u32, p, p, p, p, p]
         L.im_autotune.argtypes = [G, u32, u64, p, p, ctypes.POINTER(ImTuning)]
         L.im_autotune_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, ctypes.POINTER(ImTuning)]
+        L.im_plan_create_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, p, p, ctypes.POINTER(p)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

@@ -109,6 +109,10 @@ class Workspace:
         """Per-snapshot live lists for low-degree nodes (1) or masks only (0). No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_SPARSE_LISTS, int(on)))
 
+    def set_forward_groups(self, per_word):
+        """Workgroups per snapshot word of the grid-wide forward search. No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_FWD_GROUPS, int(per_word)))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases
@@ -414,3 +418,53 @@ def select_lazy(graph, R, k, seed, batch=64, model=None, ws=None):
                                    model.handle if model is not None else ctypes.c_void_p(0),
                                    _ptr(seeds), _ptr(gains), ws.handle, _stream(dev)))
     return _u32(seeds), gains
+
+
+class BatchPlan:
+    """A batched selection captured into one HIP graph (one launch per replay).
+
+    instances: list of (Graph, R, k, seed). `tuned` lends a Workspace's engine
+    schedule (e.g. after autotune_batch). Results per instance as select_batch.
+    """
+
+    def __init__(self, instances, tuned=None):
+        dev = instances[0][0].device
+        self.device = dev
+        self.instances = instances
+        self._arr, self._keep = _instances(instances)
+        K = sum(int(x[2]) for x in instances)
+        self.seeds_raw = torch.empty(K, dtype=torch.int32, device=dev)
+        self.gains = torch.empty(K, dtype=torch.int64, device=dev)
+        h = ctypes.c_void_p()
+        N.check(N.lib().im_plan_create_batch(self._arr, len(instances), _ptr(self.seeds_raw),
+                                             _ptr(self.gains),
+                                             tuned.handle if tuned is not None else ctypes.c_void_p(0),
+                                             _stream(dev), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        N.check(N.lib().im_plan_launch(self.handle, _stream(self.device)))
+
+    def results(self):
+        s64 = _u32(self.seeds_raw)
+        out, off = [], 0
+        for (_, _, k, _) in self.instances:
+            out.append((s64[off:off + k], self.gains[off:off + k]))
+            off += k
+        return out
+
+    def stats(self):
+        st = N.ImStats()
+        N.check(N.lib().im_plan_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.handle:
+            N.lib().im_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

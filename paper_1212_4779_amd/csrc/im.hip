@@ -598,6 +598,7 @@ struct FwdArgs {
     const uint32_t *row, *col;
     const uint64_t *mask;
     HubLists hub;
+    SparseLists sp;
     uint64_t m;
     uint32_t n, R, W;
     uint64_t *covered, *newly, *pend;
@@ -623,6 +624,7 @@ struct FwdLds {
     uint32_t scan[FWD_NT];
     uint32_t rs[FWD_NT];
     uint32_t wd[FWD_NT];
+    uint32_t aux[FWD_NT];   // 0: dense entry, else its sparse plan
     uint64_t del[FWD_NT];
     uint32_t wsum[FWD_NT / 64 + 1];
     unsigned long long red[FWD_NT / 64];
@@ -779,7 +781,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
         if (gtid == 0) a.cnt[(lev + 2) % 3] = 0;
         for (uint32_t tile = blockIdx.x * FWD_NT; tile < nf; tile += gridDim.x * FWD_NT) {
             const uint32_t i = tile + tid;
-            uint32_t deg = 0, rs = 0, w = 0;
+            uint32_t deg = 0, rs = 0, w = 0, aux = 0;
             uint64_t d = 0;
             if (i < nf) {
                 uint64_t e = cur[i];
@@ -793,11 +795,17 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, w, d);
                     deg = 0; d = 0;
+                } else {
+                    uint32_t work, srs, saux;
+                    uint64_t sdel;
+                    if (sparse_plan(a.sp, a.n, w, x, d, deg, work, srs, sdel, saux)) {
+                        deg = work; rs = srs; d = sdel; aux = saux;
+                    }
                 }
             }
             uint32_t total;
             uint32_t ex = block_excl_scan<FWD_NT>(deg, L.wsum, &total);
-            L.scan[tid] = ex; L.rs[tid] = rs; L.del[tid] = d; L.wd[tid] = w;
+            L.scan[tid] = ex; L.rs[tid] = rs; L.del[tid] = d; L.wd[tid] = w; L.aux[tid] = aux;
             __syncthreads();
             const uint32_t nhub = L.H.n;
             arcs += total;
@@ -811,21 +819,26 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                     if (j < total) {
                         int k = upper_index<FWD_NT>(L.scan, j);
                         kk[u] = (uint32_t)k;
-                        ee[u] = L.rs[k] + (j - L.scan[k]);
+                        ee[u] = j - L.scan[k];   // rank within the entry
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < FWD_U; u++)
                     if (kk[u] != 0xFFFFFFFFu) {
-                        bb[u] = a.mask[(uint64_t)L.wd[kk[u]] * a.m + ee[u]];
-                        vv[u] = a.col[ee[u]];
+                        const uint32_t k = kk[u], ax = L.aux[k];
+                        uint32_t pos = L.rs[k] + ee[u];
+                        uint64_t bit = 0;
+                        if (ax) sparse_item(L.rs[k], L.del[k], ax, ee[u], pos, bit);
+                        const uint32_t *heads = ax ? a.sp.adj : a.col;
+                        vv[u] = heads[pos];
+                        bb[u] = ax ? bit : (a.mask[(uint64_t)L.wd[k] * a.m + pos] & L.del[k]);
                     }
                 uint64_t vis_e[FWD_U], nxt_e[FWD_U];
                 uint32_t nvis = 0, nnxt = 0;
 #pragma unroll
                 for (int u = 0; u < FWD_U; u++) {
                     uint32_t ww = kk[u] != 0xFFFFFFFFu ? L.wd[kk[u]] : 0u;
-                    uint64_t bits = kk[u] != 0xFFFFFFFFu ? (bb[u] & L.del[kk[u]]) : 0ull;
+                    uint64_t bits = kk[u] != 0xFFFFFFFFu ? bb[u] : 0ull;
                     bool first, push;
                     fwd_relax(a, ww, vv[u], bits, first, push);
                     const uint64_t ent = ((uint64_t)ww << 32) | vv[u];
@@ -1102,7 +1115,8 @@ struct im_workspace {
     uint32_t *pk = nullptr;    // packing counters: bcnt, bcur [64][64], gcnt, mcnt [64]
     uint32_t *boff = nullptr;  // [64][64]
     uint32_t *plist = nullptr, *mlist = nullptr;  // [W][n]
-    unsigned fwd_grid = 0;
+    unsigned fwd_grid = 0;      // co-resident workgroups of the cooperative forward search
+    unsigned fwd_per_word = 16; // forward-search workgroups per snapshot word
     unsigned long long *keys = nullptr;
     uint64_t cap_keys = 0;
     // batches
@@ -1227,7 +1241,7 @@ extern "C" int im_workspace_create(im_workspace **out)
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_forward_coop, FWD_NT, 0));
         if (b < 1) b = 1;
         // 16 workgroups per snapshot word at most: grid barriers stay cheap
-        ws->fwd_grid = std::min<unsigned>((unsigned)b * (unsigned)ws->num_cu, 16u * 64u);
+        ws->fwd_grid = (unsigned)b * (unsigned)ws->num_cu;
         int be = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_eval_coop, FWD_NT, 0));
         if (be < 1) be = 1;
@@ -1619,6 +1633,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     FwdArgs f;
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
     f.hub = hub_lists(ws, 0);
+    f.sp = sparse_lists(ws, 0);
     f.n = n; f.R = R; f.W = W;
     f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend;
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
@@ -1631,7 +1646,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
         if (ws->batch.count == 1) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
         void *args[] = {&f};
-        const unsigned fg = std::min<unsigned>(ws->fwd_grid, 16u * W);
+        const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * W);
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
                                                   dim3(FWD_NT), args, 0, s);
         if (e != hipSuccess)
@@ -2122,6 +2137,7 @@ struct EvalArgs {
     const uint32_t *row, *col;
     const uint64_t *mask;
     HubLists hub;
+    SparseLists sp;
     uint64_t m;
     uint32_t n, R, W, V;
     const uint64_t *covered;
@@ -2183,7 +2199,7 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
         const uint32_t per = std::max<uint32_t>(1u, std::min<uint32_t>(FWD_NT, (nf + gridDim.x - 1) / gridDim.x));
         for (uint64_t tile = (uint64_t)blockIdx.x * per; tile < nf; tile += (uint64_t)gridDim.x * per) {
             const uint64_t i = tile + tid;
-            uint32_t deg = 0, rs = 0, vw = 0;
+            uint32_t deg = 0, rs = 0, vw = 0, aux = 0;
             uint64_t d = 0;
             if ((uint32_t)tid < per && i < nf) {
                 const uint64_t e = cur[i];
@@ -2196,11 +2212,17 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, vw, d);
                     deg = 0; d = 0;
+                } else {
+                    uint32_t work, srs, saux;
+                    uint64_t sdel;
+                    if (sparse_plan(a.sp, a.n, vw % a.W, x, d, deg, work, srs, sdel, saux)) {
+                        deg = work; rs = srs; d = sdel; aux = saux;
+                    }
                 }
             }
             uint32_t total;
             const uint32_t ex = block_excl_scan<FWD_NT>(deg, L.wsum, &total);
-            L.scan[tid] = ex; L.rs[tid] = rs; L.del[tid] = d; L.wd[tid] = vw;
+            L.scan[tid] = ex; L.rs[tid] = rs; L.del[tid] = d; L.wd[tid] = vw; L.aux[tid] = aux;
             __syncthreads();
             const uint32_t nhub = L.H.n;
             arcs += total;
@@ -2214,21 +2236,26 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
                     if (j < total) {
                         const int k = upper_index<FWD_NT>(L.scan, j);
                         kk[u] = (uint32_t)k;
-                        ee[u] = L.rs[k] + (j - L.scan[k]);
+                        ee[u] = j - L.scan[k];   // rank within the entry
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < FWD_U; u++)
                     if (kk[u] != 0xFFFFFFFFu) {
-                        bb[u] = a.mask[(uint64_t)(L.wd[kk[u]] % a.W) * a.m + ee[u]];
-                        vv[u] = a.col[ee[u]];
+                        const uint32_t k = kk[u], ax = L.aux[k];
+                        uint32_t pos = L.rs[k] + ee[u];
+                        uint64_t bit = 0;
+                        if (ax) sparse_item(L.rs[k], L.del[k], ax, ee[u], pos, bit);
+                        const uint32_t *heads = ax ? a.sp.adj : a.col;
+                        vv[u] = heads[pos];
+                        bb[u] = ax ? bit : (a.mask[(uint64_t)(L.wd[k] % a.W) * a.m + pos] & L.del[k]);
                     }
                 uint64_t vis_e[FWD_U], nxt_e[FWD_U];
                 uint32_t nvis = 0, nnxt = 0;
 #pragma unroll
                 for (int u = 0; u < FWD_U; u++) {
                     const uint32_t ww = kk[u] != 0xFFFFFFFFu ? L.wd[kk[u]] : 0u;
-                    const uint64_t bits = kk[u] != 0xFFFFFFFFu ? (bb[u] & L.del[kk[u]]) : 0ull;
+                    const uint64_t bits = kk[u] != 0xFFFFFFFFu ? bb[u] : 0ull;
                     bool first, push;
                     eval_relax(a, ww, vv[u], bits, first, push);
                     const uint64_t ent = ((uint64_t)ww << 32) | vv[u];
@@ -2351,6 +2378,7 @@ static int eval_coop(const im_graph *g, uint32_t R, uint32_t ncand, uint32_t vma
     const uint32_t n = g->n, W = (R + 63) / 64, per = vmax / W;
     EvalArgs e;
     e.row = ws->row32; e.col = g->col; e.mask = ws->mask_out; e.hub = hub_lists(ws, 0);
+    e.sp = sparse_lists(ws, 0);
     e.m = g->m; e.n = n; e.R = R; e.W = W;
     e.covered = ws->covered; e.reach = ws->e_reach; e.pend = ws->e_pend;
     e.fq0 = ws->e_fq0; e.fq1 = ws->e_fq1; e.vis = ws->e_vis; e.cnt = ws->e_cnt;
@@ -2404,6 +2432,7 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
     FwdArgs f;
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
     f.hub = hub_lists(ws, 0);
+    f.sp = sparse_lists(ws, 0);
     f.n = n; f.R = R; f.W = W;
     f.covered = ws->covered; f.newly = ws->newly; f.pend = ws->fpend;
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
@@ -2416,7 +2445,7 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
         k_forward_block<<<W, FWB_NT, 0, s>>>(f);
         void *args[] = {&f};
-        const unsigned fg = std::min<unsigned>(ws->fwd_grid, 16u * W);
+        const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * W);
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
                                                   dim3(FWD_NT), args, 0, s);
         if (e != hipSuccess)
@@ -2644,6 +2673,10 @@ extern "C" int im_plan_destroy(im_plan *p)
     return IM_OK;
 }
 
+struct TuneKey;
+static int graph_signature(const im_graph *g, uint32_t R, im_workspace *ws, hipStream_t s, TuneKey *key);
+static int apply_cached_schedule(const im_graph *g, uint32_t R, im_workspace *ws, hipStream_t s);
+
 extern "C" int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
                               uint32_t *seeds_out, uint64_t *gains_out, void *stream,
                               im_plan **out)
@@ -2661,7 +2694,10 @@ extern "C" int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_
         im_plan_destroy(p);
         return im_fail(IM_EHIP, "hipStreamCreate failed");
     }
+    // a schedule chosen by im_autotune for this graph carries over to the plan
     rc = check_and_reserve(g, R, k, p->ws, s);
+    if (!rc) rc = apply_cached_schedule(g, R, p->ws, s);
+    if (!rc) rc = check_and_reserve(g, R, k, p->ws, s);
     if (!rc) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -2765,6 +2801,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "sparse lists must be 0 or 1");
         ws->sparse = (int)value;
         return IM_OK;
+    case IM_OPT_FWD_GROUPS:
+        if (value < 1 || value > 1024) return im_fail(IM_EINVAL, "forward workgroups per word must be in [1, 1024]");
+        ws->fwd_per_word = (unsigned)value;
+        return IM_OK;
     case IM_OPT_LAZY_ENGINE:
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");
         ws->lazy_engine = (int)value;
@@ -2809,6 +2849,18 @@ static int reserve_batch(im_workspace *ws, uint32_t count, uint64_t N, uint64_t 
         ws->cap_bm = M;
     }
     return IM_OK;
+}
+
+// merge the instances' CSRs into the workspace's block-diagonal graph
+// (instance tables already on the device)
+static void launch_merge(const im_instance *inst, uint32_t count, im_workspace *ws, hipStream_t s)
+{
+    uint64_t maxw = 0;
+    for (uint32_t i = 0; i < count; i++)
+        maxw = std::max<uint64_t>(maxw, std::max<uint64_t>((uint64_t)inst[i].g.n + 1, inst[i].g.m));
+    dim3 grid(grid_for(maxw, 256, 256), count);
+    k_batch_merge<<<grid, 256, 0, s>>>(ws->b_desc, ws->err, ws->row32, ws->b_mcol, ws->b_mprob,
+                                       ws->b_node_inst);
 }
 
 // Lay `count` instances out as one block-diagonal graph in the workspace:
@@ -2873,14 +2925,7 @@ static int batch_setup(const im_instance *inst, uint32_t count, bool need_out, i
     HIPCHK(hipMemcpyAsync(ws->b_u64, h64, (2ull * (count + 1)) * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ws->b_desc, hd, (uint64_t)count * sizeof(InstDesc), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(ws->err, 0, sizeof(uint32_t), s));
-    {
-        uint64_t maxw = 0;
-        for (uint32_t i = 0; i < count; i++)
-            maxw = std::max<uint64_t>(maxw, std::max<uint64_t>((uint64_t)inst[i].g.n + 1, inst[i].g.m));
-        dim3 grid(grid_for(maxw, 256, 256), count);
-        k_batch_merge<<<grid, 256, 0, s>>>(ws->b_desc, ws->err, ws->row32, ws->b_mcol, ws->b_mprob,
-                                           ws->b_node_inst);
-    }
+    launch_merge(inst, count, ws, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ws->host_err, ws->err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -2930,6 +2975,67 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
     return rc;
 }
 
+extern "C" int im_plan_create_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,
+                                    uint64_t *gains_out, im_workspace *tuned, void *stream,
+                                    im_plan **out)
+{
+    int rc;
+    if (!out) return im_fail(IM_EINVAL, "null plan output");
+    *out = nullptr;
+    if (!inst || count < 2) return im_fail(IM_EINVAL, "a batch plan needs at least two instances");
+    im_plan *p = new im_plan();
+    if ((rc = im_workspace_create(&p->ws))) { delete p; return rc; }
+    if (tuned) {
+        // copy the caller's engine schedule (e.g. set by im_autotune_batch)
+        p->ws->hub_deg = tuned->hub_deg;
+        p->ws->tier1_small = tuned->tier1_small;
+        p->ws->tier2_wide = tuned->tier2_wide;
+        p->ws->max_slots = tuned->max_slots;
+        p->ws->coop_gain = tuned->coop_gain;
+        p->ws->sparse = tuned->sparse;
+        p->ws->fwd_per_word = tuned->fwd_per_word;
+    }
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        im_plan_destroy(p);
+        return im_fail(IM_EHIP, "hipStreamCreate failed");
+    }
+    im_graph mg;
+    uint32_t Rmax = 0, kmax = 0;
+    // validation and the instance tables once, synchronously; the capture
+    // merges the instances again, so every replay reads their current arrays
+    rc = batch_setup(inst, count, seeds_out && gains_out, p->ws, s, &mg, &Rmax, &kmax);
+    if (!rc) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            rc = im_fail(IM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+        } else {
+            launch_merge(inst, count, p->ws, s);
+            rc = enqueue_prepare(&mg, Rmax, 0, kmax, p->ws, s);
+            if (!rc) rc = enqueue_rounds(&mg, Rmax, kmax, seeds_out, gains_out, nullptr, p->ws, s);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(s, &graph);
+            if (!rc && e != hipSuccess) rc = im_fail(IM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            p->graph = graph;
+            if (!rc) {
+                e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) rc = im_fail(IM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    p->ws->batch = kSingle;
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (rc) {
+        (void)hipGetLastError();
+        im_plan_destroy(p);
+        return rc;
+    }
+    p->ws->last_stream = (hipStream_t)stream;
+    *out = p;
+    return IM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // A8: schedule autotuning. A schedule (hub threshold, tier-1 table, tier-2
 // lanes and slots) never changes a result, only where each reachability
@@ -2939,11 +3045,12 @@ extern "C" int im_select_batch(const im_instance *inst, uint32_t count, uint32_t
 // cached per graph signature.
 // ---------------------------------------------------------------------------
 struct Schedule {
-    int32_t hub_degree, tier1_table, tier2_lanes, max_slots;
+    int32_t hub_degree, tier1_table, tier2_lanes, max_slots, coop_forward;
 };
 static const Schedule kSchedules[] = {
-    {256, 1024, 256, 256},  {256, 1024, 1024, 256}, {256, 1024, 256, 2048},
-    {256, 1024, 256, 1024}, {256, 1024, 1024, 1024},
+    {256, 1024, 256, 256, 1},  {256, 1024, 1024, 256, 1}, {256, 1024, 256, 2048, 1},
+    {256, 1024, 256, 1024, 1}, {256, 1024, 1024, 1024, 1}, {256, 1024, 1024, 256, 0},
+    {256, 1024, 256, 2048, 0},
 };
 constexpr int N_SCHEDULES = sizeof(kSchedules) / sizeof(kSchedules[0]);
 constexpr uint32_t TUNE_ROUNDS = 4;   // greedy rounds in a trial
@@ -2954,6 +3061,7 @@ static void apply_schedule(im_workspace *ws, const Schedule &c)
     ws->tier1_small = c.tier1_table == 1024;
     ws->tier2_wide = c.tier2_lanes == 1024;
     ws->max_slots = (uint32_t)c.max_slots;
+    ws->coop_gain = c.coop_forward ? 0ull : ~0ull;
 }
 
 // signature of a graph: sizes plus a checksum of its arcs (heads and probabilities)
@@ -3028,6 +3136,7 @@ static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
     best->tier1_table = kSchedules[best_i].tier1_table;
     best->tier2_lanes = kSchedules[best_i].tier2_lanes;
     best->max_slots = kSchedules[best_i].max_slots;
+    best->coop_forward = kSchedules[best_i].coop_forward;
     best->ms = best_ms;
     best->tried = N_SCHEDULES;
     return IM_OK;
@@ -3038,13 +3147,23 @@ static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, boo
     for (auto &kv : g_tune_cache)
         if (kv.first == key) {
             const im_tuning &t = kv.second;
-            apply_schedule(ws, Schedule{t.hub_degree, t.tier1_table, t.tier2_lanes, t.max_slots});
+            apply_schedule(ws, Schedule{t.hub_degree, t.tier1_table, t.tier2_lanes, t.max_slots,
+                                        t.coop_forward});
             if (out) { *out = t; out->tried = 0; }
             *hit = true;
             return IM_OK;
         }
     *hit = false;
     return IM_OK;
+}
+
+static int apply_cached_schedule(const im_graph *g, uint32_t R, im_workspace *ws, hipStream_t s)
+{
+    TuneKey key;
+    int rc = graph_signature(g, R, ws, s, &key);
+    if (rc) return rc;
+    bool hit;
+    return tune_cached(key, ws, nullptr, &hit);
 }
 
 extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws,

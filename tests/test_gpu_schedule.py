@@ -73,8 +73,8 @@ def test_autotune_choice_and_cache(im):
     ws2 = im.Workspace()
     t2 = im.autotune(d, w["R"], w["seed"], ws=ws2)
     assert t2["tried"] == 0
-    assert {k: t2[k] for k in ("hub_degree", "tier1_table", "tier2_lanes", "max_slots")} == \
-           {k: t[k] for k in ("hub_degree", "tier1_table", "tier2_lanes", "max_slots")}
+    keys = ("hub_degree", "tier1_table", "tier2_lanes", "max_slots", "coop_forward")
+    assert {k: t2[k] for k in keys} == {k: t[k] for k in keys}
 
 
 def test_autotune_batch_then_select_batch(im):
@@ -94,3 +94,30 @@ def test_autotune_batch_then_select_batch(im):
     out = im.select_batch(insts, ws=ws)
     for (s, gn), (rs, rg) in zip(out, refs):
         assert s.cpu().tolist() == rs and gn.cpu().tolist() == rg
+
+
+def test_batch_plan_replays(im):
+    # the batched selection captured into one HIP graph: every replay, with
+    # eager work and synchronisations in between, equals the oracle
+    import torch
+    rng = np.random.default_rng(5)
+    insts, refs = [], []
+    for i in range(5):
+        n = int(rng.integers(200, 2500))
+        g = gg.chung_lu_graph(n, n * 5, 2.5, 200 + i, True, None if i % 2 else 0.05)
+        R, k = int(rng.choice([64, 100, 200])), 4 + i
+        insts.append((_dev(im, g), R, k, 7 + i))
+        s, gn, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, 7 + i)
+        refs.append((s.tolist(), gn.tolist()))
+    ws = im.Workspace()
+    im.autotune_batch(insts, ws=ws)
+    plan = im.BatchPlan(insts, tuned=ws)
+    for rep in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        for (s, gn), (rs, rg) in zip(plan.results(), refs):
+            assert s.cpu().tolist() == rs and gn.cpu().tolist() == rg, rep
+        im.select_batch(insts, ws=ws)   # eager work between replays
+        torch.cuda.synchronize()
+    assert plan.stats()["trav_init"] > 0
+    plan.close()
