@@ -5,9 +5,10 @@ One step = one full im_select call on a device-resident graph: validation,
 reverse CSR, snapshot masks, initial reach counts, and k greedy rounds of
 argmax + forward search + reverse decrements. The graph is uploaded before the
 timed region. The same selection is also timed on the lazy path
-(im_select_lazy) in bound order ("plain") and in the trained network's order
-("learned"), with their exact-evaluation counts; all paths must return the
-same seeds and gains.
+(im_select_lazy) in bound order ("plain") and with the trained network
+("learned": first batch of each round sized by its predicted gain;
+"learned_score_order": batches in its score order), with their
+exact-evaluation counts; all paths must return the same seeds and gains.
 
 Prints ONE JSON line. `value` is snapshot-edge traversals per second: the
 per-snapshot work the method defines (the full out-degree of every node
@@ -101,11 +102,13 @@ def lazy_paths(im, dg, w, seeds, gains, ws, stream, steps, log):
     import torch
     from paper_1212_4779_amd.train_mlp import DEFAULT_OUT, load
     model = load(DEFAULT_OUT) if os.path.exists(DEFAULT_OUT) else None
-    out = {"dynamic_update_ms": None, "plain": [], "learned": []}
+    out = {"dynamic_update_ms": None, "plain": [], "learned": [], "learned_score_order": []}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for label, m in (("plain", None), ("learned", model)):
-        if label == "learned" and m is None:
+    for label, m, policy in (("plain", None, 2), ("learned", model, 2),
+                             ("learned_score_order", model, 1)):
+        if m is None and label != "plain":
             continue
+        ws.set_learned_policy(policy)
         for B in (1, 2, 4, 16):
             s, g = im.select_lazy(dg, w["R"], w["k"], w["seed"], batch=B, model=m, ws=ws)
             torch.cuda.synchronize()
@@ -122,7 +125,8 @@ def lazy_paths(im, dg, w, seeds, gains, ws, stream, steps, log):
                                "traversals": st["trav_init"] + st["trav_fwd"] + st["trav_eval"],
                                "same_output": same})
             log(f"lazy {label} B={B}: {ms:.2f} ms, {st['celf_evals']} evaluations, same={same}")
-    for label in ("plain", "learned"):
+    ws.set_learned_policy(2)
+    for label in ("plain", "learned", "learned_score_order"):
         if out[label]:
             best = min(out[label], key=lambda r: r["ms"])
             out[f"{label}_best_ms"] = best["ms"]

@@ -77,7 +77,7 @@ int im_workspace_destroy(im_workspace *ws);
  *     one workgroup per word. Default 0 (always the cooperative grid). */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
-       IM_OPT_FWD_GROUPS = 8 };
+       IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -293,10 +293,11 @@ int im_mlp_samples(const float *feat, const uint32_t *trace, uint32_t n, uint32_
  * round evaluates candidates exactly, `batch` at a time (1..1024), until the
  * best exact (gain, lowest id) beats the bound of every candidate not yet
  * evaluated in the round. model = NULL: candidates in bound order; otherwise
- * in the network's score order among those whose bound can still win (bound
- * order when more than 2048 can). Seeds and gains are those of im_select
+ * as IM_OPT_LEARNED_POLICY says (score order falls back to bound order when
+ * more than 2048 nodes can still win). Seeds and gains are those of im_select
  * for any model and batch. Synchronous (one host wait per batch); the
- * number of exact evaluations is reported in im_stats.celf_evals. */
+ * number of exact evaluations is reported in im_stats.celf_evals. How a
+ * model orders or sizes the batches: IM_OPT_LEARNED_POLICY. */
 int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uint32_t batch,
                    const im_mlp *model, uint32_t *seeds_out, uint64_t *gains_out,
                    im_workspace *ws, void *stream);

@@ -35,6 +35,7 @@ IM_OPT_TIER1_TABLE = 5
 IM_OPT_TIER2_LANES = 6
 IM_OPT_SPARSE_LISTS = 7
 IM_OPT_FWD_GROUPS = 8
+IM_OPT_LEARNED_POLICY = 9
 
 
 class ImGraph(ctypes.Structure):

@@ -113,6 +113,10 @@ class Workspace:
         """Workgroups per snapshot word of the grid-wide forward search. No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_FWD_GROUPS, int(per_word)))
 
+    def set_learned_policy(self, policy):
+        """1: score order among can-win nodes; 2: first batch sized by the predicted gain."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LEARNED_POLICY, int(policy)))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases

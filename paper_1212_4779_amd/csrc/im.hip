@@ -1156,6 +1156,7 @@ struct im_workspace {
     float *c_score = nullptr, *c_feat = nullptr;
     unsigned long long *c_sort = nullptr;
     int lazy_engine = 1;     // 1: cooperative batched evaluation, 0: the three tiers
+    int learned_policy = 2;  // 1: score order among can-win nodes, 2: predicted-gain batches
     unsigned eval_grid = 0;
     uint64_t cap_eval = 0;
     uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
@@ -1907,7 +1908,8 @@ __global__ void k_celf_reset(uint32_t *ctl)
 
 struct PickArgs {
     uint32_t n, t, B;
-    int learned;
+    int learned;               // 0: bound order; 1: score order; 2: predicted-gain batches
+    float R;
     const uint32_t *ordB, *ordS;
     const uint32_t *bound;
     const float *score;
@@ -1924,6 +1926,7 @@ struct PickArgs {
 struct PickLds {
     unsigned long long a[CELF_CAPW];                 // walk result, descending
     unsigned long long e[CELF_CAPW + CELF_CAPE];     // moved nodes (and the learned union)
+    unsigned long long red[CP_NT / 64];
     uint32_t wsum[CP_NT / 64 + 1];
     uint32_t na, ne, done, full, lead, first;
 };
@@ -2040,6 +2043,21 @@ __device__ uint32_t pick_merge(const PickArgs &a, PickLds &L, uint32_t na, uint3
     return min(a.B, na + ne);
 }
 
+// largest of L.a[0..na) and L.e[0..ne) (0 when both are empty); all threads call
+__device__ unsigned long long pick_max(PickLds &L, uint32_t na, uint32_t ne)
+{
+    unsigned long long m = 0;
+    for (uint32_t i = threadIdx.x; i < na; i += CP_NT) m = L.a[i] > m ? L.a[i] : m;
+    for (uint32_t i = threadIdx.x; i < ne; i += CP_NT) m = L.e[i] > m ? L.e[i] : m;
+    m = wave_max_u64(m);
+    if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = 0;
+    for (int i = 0; i < CP_NT / 64; i++) m = L.red[i] > m ? L.red[i] : m;
+    __syncthreads();
+    return m;
+}
+
 __global__ __launch_bounds__(CP_NT) void k_celf_pick(PickArgs a)
 {
     __shared__ PickLds L;
@@ -2048,7 +2066,29 @@ __global__ __launch_bounds__(CP_NT) void k_celf_pick(PickArgs a)
     auto skey = [&](uint32_t u) { return node_key(score_bits(a.score[u]), u); };
     uint32_t ncand = 0;
     bool fallback = false;
-    if (!a.learned) {
+    if (a.learned == 2 && best == 0) {
+        // first batch of the round, sized by the network: its best-scored
+        // candidate c and predicted current gain g (the network predicts
+        // ln(1 + g/R)); the batch is the top B by bound of the nodes whose
+        // bound key reaches (min(g, bound of c), c). When the prediction is
+        // right, those are exactly the nodes the round must evaluate.
+        pick_walk(a, a.ordS, CC_HEADS, skey, 0ull, 1, L);
+        pick_moved(a, skey, 0ull, L);
+        const unsigned long long top = pick_max(L, L.na, L.ne);
+        unsigned long long thr = 0;
+        if (top) {
+            const uint32_t c = key_node(top);
+            const float g = a.R * expm1f(a.score[c]);
+            const uint32_t bc = a.bound[c];
+            const uint32_t T = !(g > 0.0f) ? 0u : (g >= (float)bc ? bc : (uint32_t)g);
+            thr = node_key(T, c) - 1;
+        }
+        pick_walk(a, a.ordB, CC_HEADB, bkey, thr, a.B, L);
+        pick_moved(a, bkey, thr, L);
+        const uint32_t na = L.na, ne = L.ne;
+        lds_sort_desc(L.e, ne);
+        ncand = pick_merge(a, L, na, ne);
+    } else if (a.learned != 1) {
         pick_walk(a, a.ordB, CC_HEADB, bkey, best, a.B, L);
         pick_moved(a, bkey, best, L);
         const uint32_t na = L.na, ne = L.ne;
@@ -2482,7 +2522,7 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
     HIPCHK(hipGetLastError());
     uint64_t moved_bound = 0;  // upper bound of |E| since the last rebuild
     PickArgs pa;
-    pa.n = n; pa.B = B; pa.learned = learned ? 1 : 0;
+    pa.n = n; pa.B = B; pa.learned = learned ? ws->learned_policy : 0; pa.R = (float)R;
     pa.ordB = ws->c_ordB; pa.ordS = ws->c_ordS; pa.bound = ws->c_bound; pa.score = ws->c_score;
     pa.fresh = ws->c_fresh; pa.sel = ws->sel; pa.moved = ws->c_moved; pa.E = ws->c_E;
     pa.ctl = ws->c_ctl; pa.cand = ws->c_cand; pa.ev = ws->c_ev; pa.stats = ws->stats;
@@ -2804,6 +2844,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
     case IM_OPT_FWD_GROUPS:
         if (value < 1 || value > 1024) return im_fail(IM_EINVAL, "forward workgroups per word must be in [1, 1024]");
         ws->fwd_per_word = (unsigned)value;
+        return IM_OK;
+    case IM_OPT_LEARNED_POLICY:
+        if (value != 1 && value != 2) return im_fail(IM_EINVAL, "learned policy must be 1 or 2");
+        ws->learned_policy = (int)value;
         return IM_OK;
     case IM_OPT_LAZY_ENGINE:
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");

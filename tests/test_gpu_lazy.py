@@ -80,15 +80,17 @@ def test_lazy_batch1_evaluations_equal_oracle_celf(im, name, engine):
     assert ws.stats()["celf_evals"] == st_ref["celf_evals"]
 
 
+@pytest.mark.parametrize("policy", [1, 2])
 @pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
 @pytest.mark.parametrize("batch", [1, 16, 256])
-def test_lazy_learned_order_matches_golden(im, name, batch):
+def test_lazy_learned_order_matches_golden(im, name, batch, policy):
     gold = _gold(name)
     w = gg.WORKLOADS[name]
     g = gg.workload_graph(name)
     d = _dev(im, g)
     model = im.Mlp(_random_params(11))
     ws = im.Workspace()
+    ws.set_learned_policy(policy)
     seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=batch, model=model, ws=ws)
     assert seeds.cpu().tolist() == gold["seeds"]
     assert gains.cpu().tolist() == gold["gains"]
@@ -108,9 +110,10 @@ def test_lazy_learned_constant_and_adversarial_models(im):
     neg[320 + 64 + 0 * 64 + 0] = 1.0          # W2[0][0]
     neg[320 + 64 + 4096 + 64 + 0] = -1.0      # w3[0]
     adv = im.Mlp(neg)
-    for model in (zero, adv):
+    for model, policy in ((zero, 1), (adv, 1), (zero, 2), (adv, 2)):
         for batch in (1, 32):
             ws = im.Workspace()
+            ws.set_learned_policy(policy)
             seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=batch, model=model,
                                           ws=ws)
             assert seeds.cpu().tolist() == gold["seeds"]
@@ -275,3 +278,23 @@ def test_mlp_samples_gather(im):
     np.testing.assert_allclose(x[ok], want_x, rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(t[ok], want_t, rtol=1e-6, atol=1e-6)
     assert np.isnan(x[7]).all() and np.isnan(t[7])
+
+
+def test_trained_network_evaluations_reported(im):
+    # what the trained network changes: the number of exact evaluations and
+    # of batches; the seeds and gains never change
+    from paper_1212_4779_amd.train_mlp import load
+    gold = _gold("nethept_wc")
+    w = gg.WORKLOADS["nethept_wc"]
+    d = _dev(im, gg.workload_graph("nethept_wc"))
+    model = load()
+    rows = {}
+    for label, m, policy in (("plain", None, 2), ("score", model, 1), ("predicted", model, 2)):
+        ws = im.Workspace()
+        ws.set_learned_policy(policy)
+        seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=8, model=m, ws=ws)
+        assert seeds.cpu().tolist() == gold["seeds"] and gains.cpu().tolist() == gold["gains"]
+        st = ws.stats()
+        rows[label] = (st["celf_evals"], st["celf_batches"])
+    print("exact evaluations, batches:", rows)
+    assert all(e >= w["k"] - 1 for e, _ in rows.values())
