@@ -276,11 +276,11 @@ def main():
     if args.schedule:
         hub, t1, lanes, slots, coop = (int(x) for x in args.schedule.split(","))
         ws.set_hub_degree(hub)
-        ws.set_tier1_table(t1)
+        ws.set_tier1_shape(t1)
         ws.set_tier2_lanes(lanes)
         ws.set_max_slots(slots)
         ws.set_coop_gain(0 if coop else (1 << 62))
-        tuning = {"hub_degree": hub, "tier1_table": t1, "tier2_lanes": lanes, "max_slots": slots,
+        tuning = {"hub_degree": hub, "tier1_shape": t1, "tier2_lanes": lanes, "max_slots": slots,
                   "coop_forward": coop, "tried": 0}
     else:
         tuning = im.autotune(dg, R, seed, ws=ws)

@@ -67,16 +67,41 @@ int im_workspace_create(im_workspace **ws);
 int im_workspace_destroy(im_workspace *ws);
 
 /* Execution options of a workspace. None of them changes any result; they
- * only choose how the work is scheduled.
+ * only choose where and how the work is scheduled (im_autotune picks them).
  *   IM_OPT_HUB_DEGREE: nodes with at least this many arcs (in the direction
  *     of a pass) are expanded through per-snapshot live lists instead of the
  *     snapshot masks; 0 disables the lists; otherwise >= 16. Default 256.
  *   IM_OPT_COOP_GAIN: rounds whose seed gain (summed over snapshots) is at
  *     least this value run the forward search on a cooperative grid
  *     (IM_OPT_FWD_GROUPS workgroups per snapshot word); smaller rounds use
- *     one workgroup per word. Default 0 (always the cooperative grid). */
+ *     one workgroup per word. Default 0 (always the cooperative grid).
+ *   IM_OPT_LAZY_ENGINE: exact evaluations of the lazy path run as one
+ *     cooperative grid per batch, all (candidate, word) searches together
+ *     (1, default, when their state fits 8 GB), or through the three
+ *     per-task engine tiers (0).
+ *   IM_OPT_MAX_SLOTS: workgroups of the last engine tier, each with dense
+ *     per-node state (28 bytes per node of the largest instance; at most
+ *     48 GB in total). 8..65536, default 256.
+ *   IM_OPT_TIER1_SHAPE: tasks per workgroup x LDS table entries of the
+ *     middle engine tier: 0 (default) 4 x 256, 1: 2 x 512, 2: 1 x 1024; a
+ *     task reaching more nodes than three quarters of its table moves on to
+ *     the last tier.
+ *   IM_OPT_TIER2_LANES: lanes per task of the last tier, 256 (default) or
+ *     1024.
+ *   IM_OPT_SPARSE_LISTS: 1 (default) builds per-snapshot live lists of the
+ *     nodes below the hub threshold as well, so that a node reached in at
+ *     most two of a word's snapshots reads only its arcs live there; 0 reads
+ *     every arc's mask word instead.
+ *   IM_OPT_FWD_GROUPS: workgroups per snapshot word of the cooperative
+ *     forward search (capped by co-residency), 1..1024, default 16.
+ *   IM_OPT_LEARNED_POLICY: how im_select_lazy uses a network. 1: every batch
+ *     in score order among the nodes whose bound can still win. 2 (default):
+ *     the first batch of a round holds the nodes whose bound reaches the
+ *     network's predicted gain of its best-scored node (the round's
+ *     must-evaluate set when the prediction is right), later batches in
+ *     bound order. */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
-       IM_OPT_TIER1_TABLE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
+       IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
        IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
@@ -189,7 +214,7 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
                     uint64_t *gains_out, im_workspace *ws, void *stream);
 
 /* Schedule autotuning (synchronous). A schedule -- hub threshold, tier-1
- * table, tier-2 lanes and slots (the IM_OPT_* options above) -- decides only
+ * shape, tier-2 lanes and slots (the IM_OPT_* options above) -- decides only
  * where each reachability task runs, never a result (the forward-search
  * engine, IM_OPT_COOP_GAIN, is part of it). Each candidate schedule
  * is timed on a trial selection of the given graph -- the initial reach
@@ -202,7 +227,7 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
  * it is given (a caller may pass a representative subset of a batch). */
 typedef struct im_tuning {
     int32_t  hub_degree;
-    int32_t  tier1_table;
+    int32_t  tier1_shape;
     int32_t  tier2_lanes;
     int32_t  max_slots;
     int32_t  coop_forward; /* 1: cooperative forward search (IM_OPT_COOP_GAIN 0), 0: one workgroup per word */

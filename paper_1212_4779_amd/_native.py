@@ -31,7 +31,7 @@ IM_OPT_HUB_DEGREE = 1
 IM_OPT_COOP_GAIN = 2
 IM_OPT_LAZY_ENGINE = 3
 IM_OPT_MAX_SLOTS = 4
-IM_OPT_TIER1_TABLE = 5
+IM_OPT_TIER1_SHAPE = 5
 IM_OPT_TIER2_LANES = 6
 IM_OPT_SPARSE_LISTS = 7
 IM_OPT_FWD_GROUPS = 8
@@ -75,7 +75,7 @@ class ImStats(ctypes.Structure):
 
 
 class ImTuning(ctypes.Structure):
-    _fields_ = [("hub_degree", ctypes.c_int32), ("tier1_table", ctypes.c_int32),
+    _fields_ = [("hub_degree", ctypes.c_int32), ("tier1_shape", ctypes.c_int32),
                 ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32)]
 

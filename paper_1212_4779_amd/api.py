@@ -97,9 +97,9 @@ class Workspace:
         """Workgroups of the last engine tier (8..65536). No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_MAX_SLOTS, int(slots)))
 
-    def set_tier1_table(self, entries):
-        """LDS table entries of the middle engine tier (1024 or 2048). No result changes."""
-        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER1_TABLE, int(entries)))
+    def set_tier1_shape(self, shape):
+        """Middle-tier tasks x table entries: 0: 4 x 256, 1: 2 x 512, 2: 1 x 1024. No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER1_SHAPE, int(shape)))
 
     def set_tier2_lanes(self, lanes):
         """Lanes per task of the last engine tier (256 or 1024). No result changes."""

@@ -1075,10 +1075,9 @@ __global__ void k_copy_u32(const uint32_t *src, uint32_t *dst, uint64_t cnt)
 // tier 0: 64 lanes, T0_T tasks of up to T0_LIM nodes, degrees <= T0_DMAX
 constexpr int T0_T = 8, T0_CS = 32, T0_LIM = 24, T0_U = 8;
 constexpr uint32_t T0_DMAX = 1024;
-// tier 1: 256 lanes, T1_T tasks of up to T1_LIM nodes, any degree
-constexpr int T1_NT = 256, T1_T = 1, T1_CS = 2048, T1_LIM = 1536, T1_U = 8;
-// the smaller tier-1 table (more workgroups per CU, earlier hand-over)
-constexpr int T1S_CS = 1024, T1S_LIM = 768;
+// tier 1: 256 lanes, T1_T tasks of up to T1_LIM nodes, any degree (the
+// default shape; two others: 2 tasks x 512 entries, 1 task x 1024 entries)
+constexpr int T1_NT = 256, T1_T = 4, T1_CS = 256, T1_LIM = 192, T1_U = 8;
 // tier 2: dense global arrays
 constexpr int T2_NT = 256, T2_U = 8;
 constexpr int T2W_NT = 1024;   // the wide variant: more lanes per task
@@ -1096,7 +1095,7 @@ struct im_workspace {
     uint32_t cap_n = 0, cap_W = 0, cap_k = 0, slots = 0;
     uint32_t max_slots = 256, slots_n = 0;  // tier-2: slot limit, length of each slot in use
     uint64_t slots_entries = 0;             // allocated slot entries
-    int tier1_small = 1;     // tier-1 table of 1024 entries instead of 2048
+    int tier1_shape = 0;     // tier-1 tasks x table entries: 0: 4 x 256, 1: 2 x 512, 2: 1 x 1024
     int tier2_wide = 0;      // 1024 lanes per tier-2 task instead of 256
     uint64_t cap_m = 0;
     // graph-derived
@@ -1297,8 +1296,8 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
 
 static uint32_t slots_for(uint32_t n, uint32_t max_slots)
 {
-    // dense global-engine state: 36 bytes per node per slot, at most 48 GB
-    uint64_t per = 36ull * (n ? n : 1);
+    // dense global-engine state: 28 bytes per node per slot, at most 48 GB
+    uint64_t per = 28ull * (n ? n : 1);
     uint64_t s = (48ull << 30) / per;
     if (s > max_slots) s = max_slots;
     if (s < 8) s = 8;
@@ -1583,14 +1582,24 @@ static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipSt
     a.out_q = ws->ovf_q2; a.out_n = ctr + 3; a.grab = ctr + 2; a.tier = 1;
     {
         PhaseTimer pt(ws, ph0 + 1, s);
-        if (ws->tier1_small) {
-            auto k1 = k_lds_bfs<MODE, T1_NT, T1_T, T1S_CS, T1S_LIM, 0xFFFFFFFFu, T1_U, PRUNE>;
+        switch (ws->tier1_shape) {
+        case 1: {
+            auto k1 = k_lds_bfs<MODE, T1_NT, 2, 512, 384, 0xFFFFFFFFu, T1_U, PRUNE>;
             static const unsigned g1 = per_cu(k1, T1_NT);
             k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
-        } else {
+            break;
+        }
+        case 2: {
+            auto k1 = k_lds_bfs<MODE, T1_NT, 1, 1024, 768, 0xFFFFFFFFu, T1_U, PRUNE>;
+            static const unsigned g1 = per_cu(k1, T1_NT);
+            k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
+            break;
+        }
+        default: {
             auto k1 = k_lds_bfs<MODE, T1_NT, T1_T, T1_CS, T1_LIM, 0xFFFFFFFFu, T1_U, PRUNE>;
             static const unsigned g1 = per_cu(k1, T1_NT);
             k1<<<(unsigned)ws->num_cu * g1, T1_NT, 0, s>>>(a);
+        }
         }
     }
     a.in_q = ws->ovf_q2; a.in_n = ctr + 3;
@@ -2829,9 +2838,9 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         if (value < 8 || value > 65536) return im_fail(IM_EINVAL, "slots must be in [8, 65536]");
         ws->max_slots = (uint32_t)value;
         return IM_OK;
-    case IM_OPT_TIER1_TABLE:
-        if (value != 1024 && value != 2048) return im_fail(IM_EINVAL, "tier-1 table must be 1024 or 2048");
-        ws->tier1_small = value == 1024;
+    case IM_OPT_TIER1_SHAPE:
+        if (value < 0 || value > 2) return im_fail(IM_EINVAL, "tier-1 shape must be 0, 1 or 2");
+        ws->tier1_shape = (int)value;
         return IM_OK;
     case IM_OPT_TIER2_LANES:
         if (value != 256 && value != 1024) return im_fail(IM_EINVAL, "tier-2 lanes must be 256 or 1024");
@@ -3032,7 +3041,7 @@ extern "C" int im_plan_create_batch(const im_instance *inst, uint32_t count, uin
     if (tuned) {
         // copy the caller's engine schedule (e.g. set by im_autotune_batch)
         p->ws->hub_deg = tuned->hub_deg;
-        p->ws->tier1_small = tuned->tier1_small;
+        p->ws->tier1_shape = tuned->tier1_shape;
         p->ws->tier2_wide = tuned->tier2_wide;
         p->ws->max_slots = tuned->max_slots;
         p->ws->coop_gain = tuned->coop_gain;
@@ -3089,12 +3098,12 @@ extern "C" int im_plan_create_batch(const im_instance *inst, uint32_t count, uin
 // cached per graph signature.
 // ---------------------------------------------------------------------------
 struct Schedule {
-    int32_t hub_degree, tier1_table, tier2_lanes, max_slots, coop_forward;
+    int32_t hub_degree, tier1_shape, tier2_lanes, max_slots, coop_forward;
 };
 static const Schedule kSchedules[] = {
-    {256, 1024, 256, 256, 1},  {256, 1024, 1024, 256, 1}, {256, 1024, 256, 2048, 1},
-    {256, 1024, 256, 1024, 1}, {256, 1024, 1024, 1024, 1}, {256, 1024, 1024, 256, 0},
-    {256, 1024, 256, 2048, 0},
+    {256, 0, 256, 256, 1},  {256, 0, 1024, 256, 1}, {256, 0, 256, 2048, 1},
+    {256, 0, 256, 1024, 1}, {256, 0, 1024, 1024, 1}, {256, 0, 1024, 256, 0},
+    {256, 0, 256, 2048, 0}, {256, 1, 1024, 256, 1},
 };
 constexpr int N_SCHEDULES = sizeof(kSchedules) / sizeof(kSchedules[0]);
 constexpr uint32_t TUNE_ROUNDS = 4;   // greedy rounds in a trial
@@ -3102,7 +3111,7 @@ constexpr uint32_t TUNE_ROUNDS = 4;   // greedy rounds in a trial
 static void apply_schedule(im_workspace *ws, const Schedule &c)
 {
     ws->hub_deg = (uint32_t)c.hub_degree;
-    ws->tier1_small = c.tier1_table == 1024;
+    ws->tier1_shape = c.tier1_shape;
     ws->tier2_wide = c.tier2_lanes == 1024;
     ws->max_slots = (uint32_t)c.max_slots;
     ws->coop_gain = c.coop_forward ? 0ull : ~0ull;
@@ -3177,7 +3186,7 @@ static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
     if (rc) return rc;
     apply_schedule(ws, kSchedules[best_i]);
     best->hub_degree = kSchedules[best_i].hub_degree;
-    best->tier1_table = kSchedules[best_i].tier1_table;
+    best->tier1_shape = kSchedules[best_i].tier1_shape;
     best->tier2_lanes = kSchedules[best_i].tier2_lanes;
     best->max_slots = kSchedules[best_i].max_slots;
     best->coop_forward = kSchedules[best_i].coop_forward;
@@ -3191,7 +3200,7 @@ static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, boo
     for (auto &kv : g_tune_cache)
         if (kv.first == key) {
             const im_tuning &t = kv.second;
-            apply_schedule(ws, Schedule{t.hub_degree, t.tier1_table, t.tier2_lanes, t.max_slots,
+            apply_schedule(ws, Schedule{t.hub_degree, t.tier1_shape, t.tier2_lanes, t.max_slots,
                                         t.coop_forward});
             if (out) { *out = t; out->tried = 0; }
             *hit = true;

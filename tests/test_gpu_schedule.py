@@ -13,9 +13,9 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
-SCHEDULES = [  # (hub degree, tier-1 table, tier-2 lanes, tier-2 slots)
-    (256, 1024, 256, 256), (256, 1024, 1024, 256), (256, 1024, 256, 2048),
-    (1024, 2048, 256, 8), (0, 2048, 1024, 8), (16, 1024, 1024, 64),
+SCHEDULES = [  # (hub degree, tier-1 shape, tier-2 lanes, tier-2 slots)
+    (256, 0, 256, 256), (256, 1, 1024, 256), (256, 2, 256, 2048),
+    (1024, 0, 256, 8), (0, 1, 1024, 8), (16, 2, 1024, 64),
 ]
 
 
@@ -48,7 +48,7 @@ def test_every_schedule_gives_the_oracle_trace(im, case):
     for hub, t1, lanes, slots in SCHEDULES:
         ws = im.Workspace()
         ws.set_hub_degree(hub)
-        ws.set_tier1_table(t1)
+        ws.set_tier1_shape(t1)
         ws.set_tier2_lanes(lanes)
         ws.set_max_slots(slots)
         seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
@@ -66,14 +66,14 @@ def test_autotune_choice_and_cache(im):
     ws = im.Workspace()
     t = im.autotune(d, w["R"], w["seed"], ws=ws)
     assert t["tried"] >= 2 and t["ms"] > 0
-    assert t["tier1_table"] in (1024, 2048) and t["tier2_lanes"] in (256, 1024)
+    assert t["tier1_shape"] in (0, 1, 2) and t["tier2_lanes"] in (256, 1024)
     seeds, gains, _ = im.select(d, w["R"], w["k"], w["seed"], ws=ws)
     assert seeds.cpu().tolist() == gold["seeds"]
     assert gains.cpu().tolist() == gold["gains"]
     ws2 = im.Workspace()
     t2 = im.autotune(d, w["R"], w["seed"], ws=ws2)
     assert t2["tried"] == 0
-    keys = ("hub_degree", "tier1_table", "tier2_lanes", "max_slots", "coop_forward")
+    keys = ("hub_degree", "tier1_shape", "tier2_lanes", "max_slots", "coop_forward")
     assert {k: t2[k] for k in keys} == {k: t[k] for k in keys}
 
 
