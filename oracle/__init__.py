@@ -58,6 +58,7 @@ def _load():
         lib.oracle_select_alg1.argtypes = graph + [u32, u64, p, p]
         lib.oracle_select_celf.argtypes = graph + [u32, u64, p, p, p]
         lib.oracle_spread.argtypes = graph + [u64, p, u32, p]
+        lib.oracle_spread_prefix.argtypes = graph + [u64, p, u32, p, p]
         lib.oracle_mlp_nparams.restype = ctypes.c_int
         lib.oracle_bf16_round.argtypes = [u64, p, p]
         lib.oracle_node_features.argtypes = [u32, u64, p, p, p, p]
@@ -153,6 +154,18 @@ def spread(row_ptr, col, prob, R, seed, S):
     _check(_load().oracle_spread(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, seed,
                                  _ptr(S), len(S), ctypes.byref(out)), "spread")
     return int(out.value)
+
+
+def spread_prefix(row_ptr, col, prob, R, seed, S):
+    """(marg uint64 [len(S)], per uint32 [R]): marg[i] = f(S[:i+1]) - f(S[:i]),
+    per[r] = |R_r(S)| (Sec. 3.1 estimator; every prefix searched from scratch)."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    S = np.ascontiguousarray(S, dtype=np.uint32)
+    marg = np.zeros(len(S), dtype=np.uint64)
+    per = np.zeros(R, dtype=np.uint32)
+    _check(_load().oracle_spread_prefix(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, seed,
+                                        _ptr(S), len(S), _ptr(marg), _ptr(per)), "spread_prefix")
+    return marg, per
 
 
 # ---------------------------------------------------------------------------

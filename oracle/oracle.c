@@ -603,3 +603,37 @@ int oracle_spread(uint32_t n, uint64_t m, const uint64_t *row_ptr,
     snaps_free(&g);
     return ORACLE_OK;
 }
+
+/* Prefix spreads (Sec. 3.1 estimator, used to score seed sets on snapshots
+ * independent of the ones that chose them, Sec. 6):
+ *   marg[i] = f(S[0..i]) - f(S[0..i-1]),  per[r] = |R(G'_r, S)|.
+ * Every prefix is searched from scratch, straight from the definition of f.
+ * marg or per may be NULL. */
+int oracle_spread_prefix(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                         const uint32_t *col, const float *prob, uint32_t R,
+                         uint64_t seed, const uint32_t *S, uint32_t nS,
+                         uint64_t *marg, uint32_t *per)
+{
+    int rc = check_graph(n, m, row_ptr, col, prob, R);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < nS; i++) if (S[i] >= n) return ORACLE_EINVAL;
+    snaps_t g;
+    if ((rc = snaps_build(&g, n, m, row_ptr, col, prob, R, seed))) return rc;
+    bfs_ws ws;
+    if (ws_init(&ws, n)) { snaps_free(&g); return ORACLE_ENOMEM; }
+    if (marg) memset(marg, 0, (size_t)nS * sizeof(uint64_t));
+    for (uint32_t r = 0; r < R; r++) {
+        if (marg) {
+            uint32_t prev = 0;
+            for (uint32_t i = 0; i < nS; i++) {
+                uint32_t cur = reach_fwd(&g, r, S, i + 1, NULL, &ws, row_ptr, NULL);
+                marg[i] += cur - prev;
+                prev = cur;
+            }
+        }
+        if (per) per[r] = nS ? reach_fwd(&g, r, S, nS, NULL, &ws, row_ptr, NULL) : 0;
+    }
+    ws_free(&ws);
+    snaps_free(&g);
+    return ORACLE_OK;
+}

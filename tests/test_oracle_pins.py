@@ -322,6 +322,57 @@ def test_workload_invariants(name):
         assert np.flatnonzero(unsel & (tr[t] == gains[t]))[0] == seeds[t]
 
 
+# ---------------------------------------------------------------- spread evaluation
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_spread_prefix_bruteforce(case):
+    # prefix increments and per-snapshot reach sizes against brute-force
+    # reachability on the pinned live bits; repeated seeds add nothing
+    rng = np.random.default_rng(400 + case)
+    n = int(rng.integers(5, 14))
+    row_ptr, col, prob = _random_graph(rng, n, int(rng.integers(n, 3 * n)), 0.1, 0.9)
+    R, seed = int(rng.choice([1, 7, 64, 100])), int(rng.integers(1, 1000))
+    S = [int(x) for x in rng.integers(0, n, size=int(rng.integers(1, 7)))]
+    marg, per = oracle.spread_prefix(row_ptr, col, prob, R, seed, S)
+    adj = _snapshots(row_ptr, col, prob, R, seed)
+    prev = 0
+    for i in range(len(S)):
+        cur = _f(adj, S[: i + 1])
+        assert int(marg[i]) == cur - prev
+        if S[i] in S[:i]:
+            assert marg[i] == 0
+        prev = cur
+    assert per.tolist() == [len(_reach(adj[r], S)) for r in range(R)]
+    assert int(marg.sum()) == int(per.sum()) == oracle.spread(row_ptr, col, prob, R, seed, S)
+
+
+def test_spread_prefix_closed_forms():
+    # p = 1: every snapshot is the graph, f(T) = R * |reach_G(T)|;
+    # p = 0: f(T) = R * |distinct T|
+    arcs = [(0, 1), (1, 2), (2, 0), (3, 4), (5, 6), (6, 7)]
+    row_ptr, col, prob = _csr(9, arcs, 1.0)
+    R = 130
+    S = [3, 0, 1, 5, 8, 4, 6]
+    marg, per = oracle.spread_prefix(row_ptr, col, prob, R, 9, S)
+    assert marg.tolist() == [2 * R, 3 * R, 0, 3 * R, R, 0, 0]
+    assert per.tolist() == [9] * R
+    row_ptr, col, prob = _csr(9, arcs, 0.0)
+    marg, per = oracle.spread_prefix(row_ptr, col, prob, R, 9, S)
+    assert marg.tolist() == [R] * 7 and per.tolist() == [7] * R
+
+
+def test_spread_prefix_of_greedy_seeds_is_the_gain_sequence():
+    # on the snapshots that chose them, the greedy seeds' prefix increments
+    # are exactly the DU gains (Algorithm 2 keeps s_v = f(S + v) - f(S))
+    g = gg.chung_lu_graph(400, 2400, 2.4, 5, True, 0.1)
+    R, k, seed = 100, 8, 3
+    seeds, gains, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
+    marg, per = oracle.spread_prefix(g.row_ptr, g.col, g.prob, R, seed, seeds)
+    assert marg.tolist() == gains.tolist()
+    assert int(per.sum()) == int(gains.sum())
+
+
 # ---------------------------------------------------------------- semantics
 
 
