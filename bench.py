@@ -97,6 +97,34 @@ def cpu_baseline(g, w, log):
             "seconds": round(dt, 3)}, seeds, gains
 
 
+def spread_leg(im, dg, R, seed, seeds, gains, stream, log):
+    """Score the selected seeds: on the selection's own snapshots (the prefix
+    increments must equal the gains) and on independent snapshots, R of them
+    and 20,000 (the paper's simulation count), with the time of each."""
+    import torch
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ws = im.Workspace()
+    for label, r, sd in (("same_snapshots", R, seed), ("independent", R, seed + 1000),
+                         ("independent_20000", 20000, seed + 1000)):
+        marg, per = im.spread(dg, r, sd, seeds, ws=ws, per_snapshot=True)   # warm-up, allocation
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        marg, per = im.spread(dg, r, sd, seeds, ws=ws, per_snapshot=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        f = int(marg.sum().item())
+        p = per.double()
+        est, half = f / r, 1.96 * float(p.std()) / r ** 0.5 if r > 1 else 0.0
+        out[label] = {"R": r, "seed": sd, "ms": round(ev0.elapsed_time(ev1), 3), "f": f,
+                      "spread": round(est, 2), "ci95_half_width": round(half, 2)}
+        log(f"spread {label}: R={r} {out[label]['ms']:.2f} ms, spread {est:.1f} +- {half:.1f}")
+    out["same_snapshots"]["equals_gains"] = bool(
+        im.spread(dg, R, seed, seeds, ws=ws)[0].cpu().tolist() == gains.cpu().tolist())
+    ws.close()
+    return out
+
+
 def lazy_paths(im, dg, w, seeds, gains, ws, stream, steps, log):
     """Lazy exact evaluation, plain (bound order) vs learned (network order)."""
     import torch
@@ -353,6 +381,7 @@ def main():
 
     lazy = lazy_paths(im, dg, w, seeds, gains, ws, stream, max(1, min(args.steps, 3)), log)
     lazy["dynamic_update_ms"] = round(ms_per_step, 3)
+    spread_eval = spread_leg(im, dg, R, seed, seeds, gains, stream, log)
 
     gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
     parity = None
@@ -385,6 +414,7 @@ def main():
         "schedule": tuning,
         "roofline": roofline,
         "learned_vs_plain": lazy,
+        "spread_eval": spread_eval,
         "cpu_baseline": cpu,
         "parity_vs_oracle_golden": parity,
     }

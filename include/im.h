@@ -46,6 +46,7 @@ extern "C" {
 #define IM_EHIP      (-4)   /* a HIP runtime call failed                  */
 
 #define IM_R_MAX 4096u
+#define IM_SPREAD_R_MAX (1u << 20)
 
 /* Graph in CSR form, device-resident, caller-owned, read-only.
  * Arc e (0 <= e < m) is the e-th entry of col; its tail is the u with
@@ -326,6 +327,25 @@ int im_mlp_samples(const float *feat, const uint32_t *trace, uint32_t n, uint32_
 int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uint32_t batch,
                    const im_mlp *model, uint32_t *seeds_out, uint64_t *gains_out,
                    im_workspace *ws, void *stream);
+
+/* Spread evaluation (the snapshot estimator of Sec. 3.1; the paper scores
+ * seed sets on independent simulations, Sec. 6). With f(T) = sum_r |R_r(T)|
+ * over R snapshots drawn from `seed` by the same live-edge rule as selection
+ * (another seed gives snapshots independent of those a selection used):
+ *   marg_out[i] = f(S[0..i]) - f(S[0..i-1]), uint64 [nS] (device), so the
+ *     spread estimate of the first i+1 seeds is (marg_out[0] + ... +
+ *     marg_out[i]) / R; a repeated seed adds 0;
+ *   per_snapshot_out[r] = |R_r(S)|, uint32 [R] (device): the spread of the
+ *     whole sequence in each snapshot, for confidence intervals.
+ * Either output may be NULL (marg_out NULL: one search per word from all
+ * seeds at once). S: device array of nS node ids, each < n, checked on the
+ * host before any output is written. 1 <= R <= IM_SPREAD_R_MAX (R is not
+ * bounded by IM_R_MAX: snapshot words are processed in chunks whose masks
+ * and search state stay within a fixed device-memory budget). Synchronous
+ * for the seed check, then asynchronous on `stream`. Errors: IM_EINVAL for
+ * null pointers, R out of range, a seed >= n or a malformed graph. */
+int im_spread(const im_graph *g, uint32_t R, uint64_t seed, const uint32_t *S, uint32_t nS,
+              uint64_t *marg_out, uint32_t *per_snapshot_out, im_workspace *ws, void *stream);
 
 #ifdef __cplusplus
 }

@@ -614,7 +614,9 @@ int oracle_spread_prefix(uint32_t n, uint64_t m, const uint64_t *row_ptr,
                          uint64_t seed, const uint32_t *S, uint32_t nS,
                          uint64_t *marg, uint32_t *per)
 {
-    int rc = check_graph(n, m, row_ptr, col, prob, R);
+    /* an evaluation may use more snapshots than a selection: up to 2^20 */
+    if (R == 0 || R > (1u << 20) || (uint64_t)n * R >= (1ULL << 32)) return ORACLE_EINVAL;
+    int rc = check_graph(n, m, row_ptr, col, prob, 1);
     if (rc) return rc;
     for (uint32_t i = 0; i < nS; i++) if (S[i] >= n) return ORACLE_EINVAL;
     snaps_t g;

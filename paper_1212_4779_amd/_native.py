@@ -20,8 +20,9 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_select_batch", "im_mlp_create", "im_mlp_destroy", "im_mlp_set_params",
            "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
            "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy",
-           "im_autotune", "im_autotune_batch", "im_plan_create_batch")
+           "im_autotune", "im_autotune_batch", "im_plan_create_batch", "im_spread")
 IM_MLP_NPARAM = 4609
+IM_SPREAD_R_MAX = 1 << 20
 IM_PH_MAX = 24
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
@@ -137,6 +138,7 @@ def lib():
         L.im_autotune.argtypes = [G, u32, u64, p, p, ctypes.POINTER(ImTuning)]
         L.im_autotune_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, ctypes.POINTER(ImTuning)]
         L.im_plan_create_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, p, p, ctypes.POINTER(p)]
+        L.im_spread.argtypes = [G, u32, u64, p, u32, p, p, p, p]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

@@ -424,6 +424,28 @@ def select_lazy(graph, R, k, seed, batch=64, model=None, ws=None):
     return _u32(seeds), gains
 
 
+def spread(graph, R, seed, seeds, ws=None, marginals=True, per_snapshot=False):
+    """Snapshot spread of a seed sequence on R snapshots drawn from `seed`.
+
+    Returns (marg int64 [len(seeds)] or None, per_snapshot int64 [R] or None):
+    marg[i] = f(S[:i+1]) - f(S[:i]) with f(T) = sum_r |R_r(T)|, so
+    marg.cumsum() / R are the spread estimates of the prefixes;
+    per_snapshot[r] = |R_r(S)|.
+    """
+    dev = graph.device
+    S = torch.as_tensor(seeds, dtype=torch.int64).to(torch.int32).to(dev).contiguous()
+    nS = S.numel()
+    marg = torch.empty(nS, dtype=torch.int64, device=dev) if marginals else None
+    per = torch.empty(R, dtype=torch.int32, device=dev) if per_snapshot else None
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_spread(ctypes.byref(g), R, seed, _ptr(S) if nS else ctypes.c_void_p(0), nS,
+                              _ptr(marg) if marginals else ctypes.c_void_p(0),
+                              _ptr(per) if per_snapshot else ctypes.c_void_p(0), ws.handle,
+                              _stream(dev)))
+    return marg, (_u32(per) if per_snapshot else None)
+
+
 class BatchPlan:
     """A batched selection captured into one HIP graph (one launch per replay).
 

@@ -279,11 +279,13 @@ __global__ void k_scan_add(uint32_t *out, uint64_t len, const uint32_t *sums)
 // are below floor(p_e * 2^32). One thread per (arc, word).
 // In a batch, arc e belongs to instance i and is arc e - arc_off[i] of it:
 // the instance's own seed and R apply (its words beyond R are all zero).
+// word w0 + blockIdx.y of every arc, stored at mask[blockIdx.y][e]
 __global__ __launch_bounds__(256) void k_mask_gen(const float *prob, uint64_t m, uint32_t R,
-                                                  uint64_t seed, uint64_t *mask, Batch b)
+                                                  uint64_t seed, uint64_t *mask, Batch b,
+                                                  uint32_t w0 = 0)
 {
     uint64_t e = blockIdx.x * 256ull + threadIdx.x;
-    uint32_t w = blockIdx.y;
+    uint32_t w = w0 + blockIdx.y;
     if (e >= m) return;
     uint64_t el = e;
     if (b.arc_off) {
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void k_mask_gen(const float *prob, uint64_t m,
             }
         }
     }
-    mask[(uint64_t)w * m + e] = word;
+    mask[(uint64_t)blockIdx.y * m + e] = word;
 }
 
 __global__ __launch_bounds__(256) void k_mask_gather(const uint32_t *in2out, uint64_t m,
@@ -798,7 +800,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 } else {
                     uint32_t work, srs, saux;
                     uint64_t sdel;
-                    if (sparse_plan(a.sp, a.n, w, x, d, deg, work, srs, sdel, saux)) {
+                    if (sparse_use(sparse_fetch(a.sp, a.n, w, x, d), deg, work, srs, sdel, saux)) {
                         deg = work; rs = srs; d = sdel; aux = saux;
                     }
                 }
@@ -1073,11 +1075,11 @@ __global__ void k_copy_u32(const uint32_t *src, uint32_t *dst, uint64_t cnt)
 // wavefront engine: T tasks per wavefront, CS table entries per task,
 // LIM entries before hand-over, DMAX largest degree expanded in LDS
 // tier 0: 64 lanes, T0_T tasks of up to T0_LIM nodes, degrees <= T0_DMAX
-constexpr int T0_T = 8, T0_CS = 32, T0_LIM = 24, T0_U = 8;
+constexpr int T0_T = 8, T0_CS = 32, T0_LIM = 24, T0_U = 4;
 constexpr uint32_t T0_DMAX = 1024;
 // tier 1: 256 lanes, T1_T tasks of up to T1_LIM nodes, any degree (the
 // default shape; two others: 2 tasks x 512 entries, 1 task x 1024 entries)
-constexpr int T1_NT = 256, T1_T = 4, T1_CS = 256, T1_LIM = 192, T1_U = 8;
+constexpr int T1_NT = 256, T1_T = 4, T1_CS = 256, T1_LIM = 192, T1_U = 4;
 // tier 2: dense global arrays
 constexpr int T2_NT = 256, T2_U = 8;
 constexpr int T2W_NT = 1024;   // the wide variant: more lanes per task
@@ -1161,6 +1163,12 @@ struct im_workspace {
     uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
              *e_vis = nullptr;
     uint32_t *e_cnt = nullptr;
+    // spread evaluator: one chunk of snapshot words at a time
+    uint32_t cap_sp_n = 0, cap_sp_words = 0;
+    uint64_t cap_sp_m = 0;
+    uint32_t *v_row32 = nullptr;
+    uint64_t *v_mask = nullptr, *v_reach = nullptr, *v_pend = nullptr, *v_cov = nullptr;
+    uint32_t *v_qa = nullptr, *v_qb = nullptr, *v_vis = nullptr;
     // misc
     unsigned long long *stats = nullptr;
     uint32_t *err = nullptr;
@@ -1285,6 +1293,8 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->c_feat); dfree(ws->c_sort);
     dfree(ws->e_reach); dfree(ws->e_pend); dfree(ws->e_fq0); dfree(ws->e_fq1); dfree(ws->e_vis);
     dfree(ws->e_cnt);
+    dfree(ws->v_row32); dfree(ws->v_mask); dfree(ws->v_reach); dfree(ws->v_pend); dfree(ws->v_cov);
+    dfree(ws->v_qa); dfree(ws->v_qb); dfree(ws->v_vis);
     dfree(ws->stats); dfree(ws->err);
     if (ws->host_err) (void)hipHostFree(ws->host_err);
     if (ws->host_stats) (void)hipHostFree(ws->host_stats);
@@ -2264,7 +2274,7 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
                 } else {
                     uint32_t work, srs, saux;
                     uint64_t sdel;
-                    if (sparse_plan(a.sp, a.n, vw % a.W, x, d, deg, work, srs, sdel, saux)) {
+                    if (sparse_use(sparse_fetch(a.sp, a.n, vw % a.W, x, d), deg, work, srs, sdel, saux)) {
                         deg = work; rs = srs; d = sdel; aux = saux;
                     }
                 }
@@ -2594,6 +2604,162 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Spread evaluator: f(T) = sum_r |R_r(T)| (the snapshot estimator of Sec. 3.1,
+// times R) for the prefixes of a seed sequence, on snapshots of any seed, so
+// a seed set can be scored on snapshots independent of those that chose it
+// (the evaluation protocol of Sec. 6). One workgroup per snapshot word covers
+// the seeds group by group: each group's search is pruned at the nodes the
+// earlier groups covered, so its reach count is the group's marginal gain.
+// ---------------------------------------------------------------------------
+constexpr int SPR_NT = 1024, SPR_U = 8;
+constexpr uint64_t SPR_BUDGET = 8ull << 30;   // masks + search state of one chunk
+constexpr uint32_t SPR_MAX_WORDS = 256;
+
+struct SpreadArgs {
+    const uint32_t *row, *col;
+    const uint64_t *mask;          // [chunk words][m]
+    uint64_t m;
+    uint32_t n, R, W, w0;          // this launch: words w0 .. w0 + gridDim.x - 1
+    const uint32_t *S;
+    uint32_t nS, group;            // seeds per search
+    uint64_t *reach, *pend, *cov;  // [chunk words][n]; reach, pend zero at rest, cov zero on entry
+    uint32_t *qa, *qb, *vis;       // [chunk words][n]
+    unsigned long long *marg;      // [ceil(nS / group)] (accumulated over words) or nullptr
+    uint32_t *per_snapshot;        // [R] or nullptr
+};
+
+__global__ __launch_bounds__(SPR_NT) void k_spread(SpreadArgs a)
+{
+    __shared__ BlockLds<SPR_NT> L;
+    __shared__ uint32_t bitcnt[64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t wl = blockIdx.x, w = a.w0 + wl;
+    const uint64_t off = (uint64_t)wl * a.n;
+    const uint64_t valid = im_valid_bits(a.R, w);
+    uint64_t *reach = a.reach + off, *pend = a.pend + off, *cov = a.cov + off;
+    uint32_t *qa = a.qa + off, *qb = a.qb + off, *vis = a.vis + off;
+    const uint64_t *mask = a.mask + (uint64_t)wl * a.m;
+    const HubLists nohub = {nullptr, nullptr, nullptr};
+    const SparseLists nosp = {nullptr, nullptr, nullptr};
+    if (tid < 64) bitcnt[tid] = 0;
+    __syncthreads();
+    uint32_t mine = 0;   // this lane's count of snapshot 64w + lane (per wavefront)
+    uint64_t arcs = 0;
+    for (uint32_t g0 = 0; g0 < a.nS; g0 += a.group) {
+        const uint32_t gn = min(a.group, a.nS - g0);
+        uint32_t src = 0;
+        uint64_t start = 0;
+        if ((uint32_t)tid < gn) {
+            src = a.S[g0 + tid];
+            start = valid & ~cov[src];
+        }
+        block_bfs_run<SPR_NT, SPR_U, true, false>(L, src, start, a.row, a.col, mask, nohub, nosp,
+                                                  a.n, a.W, w, cov, reach, pend, 0u, qa, qb, vis,
+                                                  arcs);
+        // fold the group's reach into the cover; wavefront-uniform tiles
+        const uint32_t nvis = L.nvis;
+        uint64_t cnt = 0;
+        for (uint32_t base = (uint32_t)(tid & ~63); base < nvis; base += SPR_NT) {
+            const uint32_t j = base + (uint32_t)lane;
+            uint64_t b = 0;
+            if (j < nvis) {
+                const uint32_t x = vis[j];
+                b = reach[x];
+                cov[x] |= b;
+                reach[x] = 0;
+            }
+            cnt += (uint64_t)__popcll(b);
+            if (a.per_snapshot && __ballot(b != 0) != 0ull) {
+                for (int t = 0; t < 64; t++) {
+                    const uint64_t bal = __ballot((b >> t) & 1ull);
+                    if (lane == t) mine += (uint32_t)__popcll(bal);
+                }
+            }
+        }
+        cnt = group_sum<SPR_NT>(cnt, L.red);
+        if (tid == 0 && a.marg && cnt) atomicAdd(&a.marg[g0 / a.group], (unsigned long long)cnt);
+        __syncthreads();
+    }
+    if (a.per_snapshot) {
+        atomicAdd(&bitcnt[lane], mine);
+        __syncthreads();
+        if (tid < 64 && w * 64u + (uint32_t)tid < a.R) a.per_snapshot[w * 64u + tid] = bitcnt[tid];
+    }
+}
+
+static int reserve_spread(im_workspace *ws, uint32_t n, uint64_t m, uint32_t words)
+{
+    int rc;
+    if (n > ws->cap_sp_n || m > ws->cap_sp_m || words > ws->cap_sp_words || !ws->v_row32) {
+        const uint32_t cn = std::max(n, ws->cap_sp_n), cw = std::max(words, ws->cap_sp_words);
+        const uint64_t cm = std::max(m, ws->cap_sp_m), nw = (uint64_t)cn * cw;
+        if ((rc = dalloc(&ws->v_row32, (uint64_t)cn + 1)) || (rc = dalloc(&ws->v_mask, cm * cw)) ||
+            (rc = dalloc(&ws->v_reach, nw)) || (rc = dalloc(&ws->v_pend, nw)) ||
+            (rc = dalloc(&ws->v_cov, nw)) || (rc = dalloc(&ws->v_qa, nw)) ||
+            (rc = dalloc(&ws->v_qb, nw)) || (rc = dalloc(&ws->v_vis, nw)))
+            return rc;
+        HIPCHK(hipMemset(ws->v_reach, 0, nw * sizeof(uint64_t)));
+        HIPCHK(hipMemset(ws->v_pend, 0, nw * sizeof(uint64_t)));
+        ws->cap_sp_n = cn; ws->cap_sp_m = cm; ws->cap_sp_words = cw;
+    }
+    return IM_OK;
+}
+
+extern "C" int im_spread(const im_graph *g, uint32_t R, uint64_t seed, const uint32_t *S,
+                         uint32_t nS, uint64_t *marg_out, uint32_t *per_snapshot_out,
+                         im_workspace *ws, void *stream)
+{
+    int rc;
+    if (!g || !ws) return im_fail(IM_EINVAL, "null graph or workspace");
+    if ((rc = check_args(g, 1))) return rc;
+    if (R == 0 || R > IM_SPREAD_R_MAX)
+        return im_fail(IM_EINVAL, "R = %u must be in [1, %u]", R, IM_SPREAD_R_MAX);
+    if (nS && !S) return im_fail(IM_EINVAL, "null seed array");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t n = g->n, W = (R + 63) / 64;
+    const uint64_t m = g->m;
+    // seeds are checked on the host before any output is touched
+    std::vector<uint32_t> hs(nS);
+    if (nS) {
+        HIPCHK(hipMemcpyAsync(hs.data(), S, nS * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (uint32_t i = 0; i < nS; i++)
+            if (hs[i] >= n) return im_fail(IM_EINVAL, "S[%u] = %u is not a node (n = %u)", i, hs[i], n);
+    }
+    const uint64_t per_word = 8 * m + 36ull * n + 1;
+    const uint32_t cw = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>({(uint64_t)W, SPR_MAX_WORDS, SPR_BUDGET / per_word}));
+    if ((rc = reserve_spread(ws, n, m, cw))) return rc;
+    if ((rc = validate(g, ws, s, ws->v_row32))) return rc;
+    if (marg_out && nS) fill<unsigned long long>((unsigned long long *)marg_out, nS, 0ull, s);
+    if (per_snapshot_out) fill<uint32_t>(per_snapshot_out, R, 0u, s);
+    if (nS && n) {
+        SpreadArgs a;
+        a.row = ws->v_row32; a.col = g->col; a.mask = ws->v_mask; a.m = m;
+        a.n = n; a.R = R; a.W = W; a.S = S; a.nS = nS;
+        a.group = marg_out ? 1u : (uint32_t)SPR_NT;
+        a.reach = ws->v_reach; a.pend = ws->v_pend; a.cov = ws->v_cov;
+        a.qa = ws->v_qa; a.qb = ws->v_qb; a.vis = ws->v_vis;
+        a.marg = (unsigned long long *)marg_out;
+        a.per_snapshot = per_snapshot_out;
+        Batch nob = {};
+        for (uint32_t w0 = 0; w0 < W; w0 += cw) {
+            const uint32_t c = std::min(cw, W - w0);
+            if (m) {
+                dim3 grid((unsigned)((m + 255) / 256), c);
+                k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, ws->v_mask, nob, w0);
+            }
+            fill<uint64_t>(ws->v_cov, (uint64_t)c * n, 0ull, s);
+            a.w0 = w0;
+            k_spread<<<c, SPR_NT, 0, s>>>(a);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    ws->last_stream = s;
+    return IM_OK;
+}
+
 extern "C" int im_validate(const im_graph *g, uint32_t R, void *stream)
 {
     if (!g) return im_fail(IM_EINVAL, "null graph");

@@ -70,25 +70,45 @@ constexpr int SP_BITS = 2;
 // entry's work is the number of listed heads and (rs, del, aux) encode its
 // two ranges: rs = start of the first, del = start of the second | len0 << 32
 // | len1 << 48, aux = bit0 | bit1 << 8 | 1 << 16 (aux = 0: dense entry).
-__device__ __forceinline__ bool sparse_plan(const SparseLists &sp, uint32_t n, uint32_t w,
-                                            uint32_t x, uint64_t d, uint32_t deg, uint32_t &work,
-                                            uint32_t &rs, uint64_t &del, uint32_t &aux)
+// The plan is split in two so that its loads can be issued together with the
+// entry's row and hub-slot loads: sparse_fetch reads the list base and the
+// four cumulative counts that the delta's bits select (in bounds for every
+// x < n, w < W; the counts are unused when the base is empty), sparse_use
+// decides once the degree is known.
+struct SparsePre {
+    uint32_t b0, c00, c01, c10, c11, i0, i1;
+    bool ok, two;
+};
+
+__device__ __forceinline__ SparsePre sparse_fetch(const SparseLists &sp, uint32_t n, uint32_t w,
+                                                  uint32_t x, uint64_t d)
 {
-    if (!sp.base || d == 0 || __popcll(d) > SP_BITS || deg < 2) return false;
-    const uint64_t p = (uint64_t)w * n + x;
-    const uint32_t b0 = sp.base[p];
-    if (b0 == IM_EMPTY) return false;
-    const uint16_t *c = sp.cum + p * 65;
-    const uint32_t i0 = (uint32_t)__ffsll((unsigned long long)d) - 1;
-    const uint64_t d1 = d & (d - 1);
-    const uint32_t i1 = d1 ? (uint32_t)__ffsll((unsigned long long)d1) - 1 : i0;
-    const uint32_t c00 = c[i0], c01 = c[i0 + 1], c10 = c[i1], c11 = c[i1 + 1];
-    const uint32_t l0 = c01 - c00, l1 = d1 ? c11 - c10 : 0u;
+    SparsePre q;
+    q.ok = sp.base && d != 0 && __popcll(d) <= SP_BITS;
+    q.b0 = IM_EMPTY; q.c00 = q.c01 = q.c10 = q.c11 = 0; q.i0 = q.i1 = 0; q.two = false;
+    if (q.ok) {
+        const uint64_t p = (uint64_t)w * n + x;
+        const uint64_t d1 = d & (d - 1);
+        q.two = d1 != 0;
+        q.i0 = (uint32_t)__ffsll((unsigned long long)d) - 1;
+        q.i1 = q.two ? (uint32_t)__ffsll((unsigned long long)d1) - 1 : q.i0;
+        const uint16_t *c = sp.cum + p * 65;
+        q.b0 = sp.base[p];
+        q.c00 = c[q.i0]; q.c01 = c[q.i0 + 1]; q.c10 = c[q.i1]; q.c11 = c[q.i1 + 1];
+    }
+    return q;
+}
+
+__device__ __forceinline__ bool sparse_use(const SparsePre &q, uint32_t deg, uint32_t &work,
+                                           uint32_t &rs, uint64_t &del, uint32_t &aux)
+{
+    if (!q.ok || deg < 2 || q.b0 == IM_EMPTY) return false;
+    const uint32_t l0 = q.c01 - q.c00, l1 = q.two ? q.c11 - q.c10 : 0u;
     if (l0 + l1 > deg) return false;
     work = l0 + l1;
-    rs = b0 + c00;
-    del = (uint64_t)(b0 + c10) | ((uint64_t)l0 << 32) | ((uint64_t)l1 << 48);
-    aux = i0 | (i1 << 8) | (1u << 16);
+    rs = q.b0 + q.c00;
+    del = (uint64_t)(q.b0 + q.c10) | ((uint64_t)l0 << 32) | ((uint64_t)l1 << 48);
+    aux = q.i0 | (q.i1 << 8) | (1u << 16);
     return true;
 }
 
@@ -440,21 +460,32 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
             }
         }
         __syncthreads();
-        // ---- seed the new tasks: lane l of the first wavefront inserts source l
-        for (int s = 0; s < T; s++) {
-            if (L.s_new[s] == NONE) continue;
-            if (tid < 64) {
-                const uint32_t t = a.in_q ? a.in_q[L.s_new[s]] : L.s_new[s];
-                uint32_t w, src;
-                uint64_t bits;
-                task_source(a, MODE, t, L.wpre, (uint32_t)tid, w, src, bits);
+        // ---- seed the new tasks: lane l of the first wavefront inserts source l.
+        // The sources of all new slots are looked up first, so that their
+        // dependent load chains overlap instead of running one slot after another.
+        if (tid < 64) {
+            uint32_t tt[T], ww[T], ss[T];
+            uint64_t bb[T];
+#pragma unroll
+            for (int s = 0; s < T; s++) {
+                const uint32_t sn = L.s_new[s];
+                tt[s] = NONE; ww[s] = 0; ss[s] = 0; bb[s] = 0;
+                if (sn != NONE) tt[s] = a.in_q ? a.in_q[sn] : sn;
+            }
+#pragma unroll
+            for (int s = 0; s < T; s++)
+                if (tt[s] != NONE) task_source(a, MODE, tt[s], L.wpre, (uint32_t)tid, ww[s], ss[s], bb[s]);
+#pragma unroll
+            for (int s = 0; s < T; s++) {
+                if (tt[s] == NONE) continue;
                 // a task without start bits (e.g. a word beyond an instance's R)
                 // leaves the slot idle: an active slot must own frontier entries
-                const bool any = __ballot(bits != 0) != 0ull;
+                const bool any = __ballot(bb[s] != 0) != 0ull;
                 if (tid == 0) {
-                    L.s_task[s] = t; L.s_src[s] = src; L.s_word[s] = w; L.s_act[s] = any ? 1u : 0u;
+                    L.s_task[s] = tt[s]; L.s_src[s] = ss[s]; L.s_word[s] = ww[s];
+                    L.s_act[s] = any ? 1u : 0u;
                 }
-                if (bits) lds_relax<NT, T, CS, LIM>(L, s, src, bits, cur, true);
+                if (bb[s]) lds_relax<NT, T, CS, LIM>(L, s, ss[s], bb[s], cur, true);
             }
         }
         __syncthreads();
@@ -477,9 +508,12 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                     // arrive later re-queue the entry for the next level
                     const uint64_t delta = atomicExch((unsigned long long *)&L.pend[idx], 0ull);
                     uint32_t x = L.keys[idx];
+                    // independent loads: hub slot, row bounds, sparse lists
                     uint32_t hs = a.hub.slot ? a.hub.slot[x] : IM_EMPTY;
                     rs = a.row[x];
-                    deg = a.row[x + 1] - rs;
+                    const uint32_t re = a.row[x + 1];
+                    const SparsePre sq = sparse_fetch(a.sp, a.n, L.s_word[s], x, delta);
+                    deg = re - rs;
                     L.deg[idx] = deg;
                     if (hs != IM_EMPTY) {
                         hub_push(L.H, hs, idx, delta);
@@ -490,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                         d = delta;
                         uint32_t work, srs, saux;
                         uint64_t sdel;
-                        if (sparse_plan(a.sp, a.n, L.s_word[s], x, delta, deg, work, srs, sdel, saux)) {
+                        if (sparse_use(sq, deg, work, srs, sdel, saux)) {
                             deg = work; rs = srs; d = sdel; aux = saux;
                         }
                     }
@@ -722,7 +756,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 } else if (SPARSE) {
                     uint32_t work, srs, saux;
                     uint64_t sdel;
-                    if (sparse_plan(sp, n, w, x, d, deg, work, srs, sdel, saux)) {
+                    if (sparse_use(sparse_fetch(sp, n, w, x, d), deg, work, srs, sdel, saux)) {
                         deg = work; rs = srs; d = sdel; aux = saux;
                     }
                 }

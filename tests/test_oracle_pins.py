@@ -332,7 +332,7 @@ def test_spread_prefix_bruteforce(case):
     rng = np.random.default_rng(400 + case)
     n = int(rng.integers(5, 14))
     row_ptr, col, prob = _random_graph(rng, n, int(rng.integers(n, 3 * n)), 0.1, 0.9)
-    R, seed = int(rng.choice([1, 7, 64, 100])), int(rng.integers(1, 1000))
+    R, seed = int(rng.choice([1, 7, 64, 100, 5000])), int(rng.integers(1, 1000))
     S = [int(x) for x in rng.integers(0, n, size=int(rng.integers(1, 7)))]
     marg, per = oracle.spread_prefix(row_ptr, col, prob, R, seed, S)
     adj = _snapshots(row_ptr, col, prob, R, seed)
@@ -345,6 +345,21 @@ def test_spread_prefix_bruteforce(case):
         prev = cur
     assert per.tolist() == [len(_reach(adj[r], S)) for r in range(R)]
     assert int(marg.sum()) == int(per.sum()) == oracle.spread(row_ptr, col, prob, R, seed, S)
+
+
+def test_spread_prefix_beyond_selection_R():
+    # evaluations may draw more snapshots than a selection (R > 4096); the
+    # snapshots are a prefix family, so the first 4096 agree with R = 4096
+    rng = np.random.default_rng(77)
+    row_ptr, col, prob = _random_graph(rng, 6, 12, 0.2, 0.7)
+    S = [2, 0, 2, 5]
+    marg, per = oracle.spread_prefix(row_ptr, col, prob, 5000, 11, S)
+    adj = _snapshots(row_ptr, col, prob, 5000, 11)
+    assert per.tolist() == [len(_reach(a, S)) for a in adj]
+    assert marg.tolist() == [_f(adj, S[:1]), _f(adj, S[:2]) - _f(adj, S[:1]), 0,
+                             _f(adj, S) - _f(adj, S[:2])]
+    _, per4096 = oracle.spread_prefix(row_ptr, col, prob, 4096, 11, S)
+    assert per4096.tolist() == per[:4096].tolist()
 
 
 def test_spread_prefix_closed_forms():
