@@ -59,6 +59,10 @@ def _load():
         lib.oracle_select_celf.argtypes = graph + [u32, u64, p, p, p]
         lib.oracle_spread.argtypes = graph + [u64, p, u32, p]
         lib.oracle_spread_prefix.argtypes = graph + [u64, p, u32, p, p]
+        lib.oracle_live_bits_keyed.argtypes = [u64, p, u32, u64, p, p]
+        lib.oracle_pair_ids.argtypes = [u32, u64, p, p, p, p]
+        lib.oracle_select_du_pairs.argtypes = graph + [u32, u64, p, p, p, p]
+        lib.oracle_select_components.argtypes = graph + [u32, u64, p, p, p]
         lib.oracle_mlp_nparams.restype = ctypes.c_int
         lib.oracle_bf16_round.argtypes = [u64, p, p]
         lib.oracle_node_features.argtypes = [u32, u64, p, p, p, p]
@@ -93,12 +97,18 @@ def splitmix64_output(state, i):
     return int(_load().oracle_splitmix64_output(state, i))
 
 
-def live_bits(prob, R, seed):
-    """Arc-major live bits: uint64[m, W]; bit b of word w = snapshot 64w+b."""
+def live_bits(prob, R, seed, key_of=None):
+    """Arc-major live bits: uint64[m, W]; bit b of word w = snapshot 64w+b.
+    key_of[e]: the index arc e's coins are drawn under (default e)."""
     prob = np.ascontiguousarray(prob, dtype=np.float32)
     W = (R + 63) // 64
     out = np.zeros((len(prob), W), dtype=np.uint64)
-    _check(_load().oracle_live_bits(len(prob), _ptr(prob), R, seed, _ptr(out)), "live_bits")
+    if key_of is None:
+        _check(_load().oracle_live_bits(len(prob), _ptr(prob), R, seed, _ptr(out)), "live_bits")
+    else:
+        key_of = np.ascontiguousarray(key_of, dtype=np.uint32)
+        _check(_load().oracle_live_bits_keyed(len(prob), _ptr(prob), R, seed, _ptr(key_of),
+                                              _ptr(out)), "live_bits")
     return out
 
 
@@ -154,6 +164,43 @@ def spread(row_ptr, col, prob, R, seed, S):
     _check(_load().oracle_spread(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, seed,
                                  _ptr(S), len(S), ctypes.byref(out)), "spread")
     return int(out.value)
+
+
+def pair_ids(row_ptr, col, prob):
+    """Canonical arc (the direction with the smaller tail) of every arc's
+    undirected pair; raises unless the CSR is symmetric as the undirected
+    reading requires."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    out = np.zeros(m, dtype=np.uint32)
+    _check(_load().oracle_pair_ids(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), _ptr(out)),
+           "pair_ids")
+    return out
+
+
+def select_du_pairs(row_ptr, col, prob, R, k, seed, trace=False):
+    """Algorithm 2 on pair-coin snapshots of a symmetric CSR."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    seeds = np.zeros(k, dtype=np.uint32)
+    gains = np.zeros(k, dtype=np.uint64)
+    tr = np.zeros((k + 1, n), dtype=np.uint32) if trace else None
+    stats = np.zeros(NSTATS, dtype=np.uint64)
+    _check(_load().oracle_select_du_pairs(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, k, seed,
+                                          _ptr(seeds), _ptr(gains),
+                                          _ptr(tr) if trace else None, _ptr(stats)),
+           "select_du_pairs")
+    return seeds, gains, tr
+
+
+def select_components(row_ptr, col, prob, R, k, seed, trace=False):
+    """The undirected component method (Sec. 4) on pair-coin snapshots."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    seeds = np.zeros(k, dtype=np.uint32)
+    gains = np.zeros(k, dtype=np.uint64)
+    tr = np.zeros((k + 1, n), dtype=np.uint32) if trace else None
+    _check(_load().oracle_select_components(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, k,
+                                            seed, _ptr(seeds), _ptr(gains),
+                                            _ptr(tr) if trace else None), "select_components")
+    return seeds, gains, tr
 
 
 def spread_prefix(row_ptr, col, prob, R, seed, S):

@@ -94,13 +94,15 @@ static uint64_t arc_threshold(float p)
     return (uint64_t)floor((double)p * 4294967296.0);
 }
 
-/* live bits, arc-major: bits[e*W + w], bit b of word w is snapshot 64w+b */
-int oracle_live_bits(uint64_t m, const float *prob, uint32_t R, uint64_t seed,
-                     uint64_t *bits)
+/* live bits, arc-major: bits[e*W + w], bit b of word w is snapshot 64w+b.
+ * The coin of arc e is drawn under the index key_of[e] (NULL: e itself), so
+ * arcs that share an index share every coin (one coin per undirected pair). */
+int oracle_live_bits_keyed(uint64_t m, const float *prob, uint32_t R, uint64_t seed,
+                           const uint32_t *key_of, uint64_t *bits)
 {
     uint32_t W = (R + 63u) / 64u;
     for (uint64_t e = 0; e < m; e++) {
-        uint64_t key = sm64_output(seed, e + 1u);
+        uint64_t key = sm64_output(seed, (key_of ? (uint64_t)key_of[e] : e) + 1u);
         uint64_t thr = arc_threshold(prob[e]);
         for (uint32_t w = 0; w < W; w++) bits[e * W + w] = 0;
         for (uint32_t r = 0; r < R; r++)
@@ -108,6 +110,12 @@ int oracle_live_bits(uint64_t m, const float *prob, uint32_t R, uint64_t seed,
                 bits[e * W + r / 64u] |= 1ULL << (r % 64u);
     }
     return ORACLE_OK;
+}
+
+int oracle_live_bits(uint64_t m, const float *prob, uint32_t R, uint64_t seed,
+                     uint64_t *bits)
+{
+    return oracle_live_bits_keyed(m, prob, R, seed, NULL, bits);
 }
 
 /* ---------------- input checks ---------------- */
@@ -145,9 +153,9 @@ static void snaps_free(snaps_t *g)
     memset(g, 0, sizeof(*g));
 }
 
-static int snaps_build(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_ptr,
-                       const uint32_t *col, const float *prob, uint32_t R,
-                       uint64_t seed)
+static int snaps_build_keyed(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                             const uint32_t *col, const float *prob, uint32_t R,
+                             uint64_t seed, const uint32_t *key_of)
 {
     uint32_t W = (R + 63u) / 64u;
     uint64_t stride = (uint64_t)n + 1u;
@@ -161,7 +169,7 @@ static int snaps_build(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_p
     if (!bits || !g->fbase || !g->rbase || !g->fptr || !g->rptr) {
         free(bits); snaps_free(g); return ORACLE_ENOMEM;
     }
-    oracle_live_bits(m, prob, R, seed, bits);
+    oracle_live_bits_keyed(m, prob, R, seed, key_of, bits);
 
     /* count live out-arcs and in-arcs per (snapshot, node) */
     for (uint32_t u = 0; u < n; u++)
@@ -210,6 +218,13 @@ static int snaps_build(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_p
     }
     free(bits);
     return ORACLE_OK;
+}
+
+static int snaps_build(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                       const uint32_t *col, const float *prob, uint32_t R,
+                       uint64_t seed)
+{
+    return snaps_build_keyed(g, n, m, row_ptr, col, prob, R, seed, NULL);
 }
 
 /* ---------------- reachability inside one snapshot ---------------- */
@@ -383,10 +398,10 @@ int oracle_initial_gains(uint32_t n, uint64_t m, const uint64_t *row_ptr,
  * over snapshots). trace (nullable, [k+1][n]): the gain vector s at the
  * start of every round and after the last one.
  */
-int oracle_select_du(uint32_t n, uint64_t m, const uint64_t *row_ptr,
-                     const uint32_t *col, const float *prob, uint32_t R,
-                     uint32_t k, uint64_t seed, uint32_t *seeds, uint64_t *gains,
-                     uint32_t *trace, uint64_t *stats)
+static int select_du_keyed(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                           const uint32_t *col, const float *prob, uint32_t R,
+                           uint32_t k, uint64_t seed, const uint32_t *key_of,
+                           uint32_t *seeds, uint64_t *gains, uint32_t *trace, uint64_t *stats)
 {
     int rc = check_graph(n, m, row_ptr, col, prob, R);
     if (rc) return rc;
@@ -394,7 +409,7 @@ int oracle_select_du(uint32_t n, uint64_t m, const uint64_t *row_ptr,
     uint64_t st[NSTATS] = {0};
     uint64_t nw = ((uint64_t)n + 63u) / 64u;
     snaps_t g;
-    if ((rc = snaps_build(&g, n, m, row_ptr, col, prob, R, seed))) return rc;
+    if ((rc = snaps_build_keyed(&g, n, m, row_ptr, col, prob, R, seed, key_of))) return rc;
     st[4] = g.nlive;
     int64_t *s = (int64_t *)malloc((n ? n : 1) * sizeof(int64_t));
     uint8_t *sel = (uint8_t *)calloc(n ? n : 1, 1);
@@ -440,6 +455,15 @@ out:
     free(s); free(sel); free(covered); free(indeg); free(newly);
     snaps_free(&g);
     return rc;
+}
+
+int oracle_select_du(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                     const uint32_t *col, const float *prob, uint32_t R,
+                     uint32_t k, uint64_t seed, uint32_t *seeds, uint64_t *gains,
+                     uint32_t *trace, uint64_t *stats)
+{
+    return select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, NULL, seeds, gains, trace,
+                           stats);
 }
 
 /*
@@ -638,4 +662,174 @@ int oracle_spread_prefix(uint32_t n, uint64_t m, const uint64_t *row_ptr,
     ws_free(&ws);
     snaps_free(&g);
     return ORACLE_OK;
+}
+
+/* ======================================================================
+ * Undirected graphs with one coin per undirected pair (Sec. 4: in an
+ * undirected snapshot R(G'_i,v) = U(G'_i,v), so the connected components
+ * of each snapshot carry all the information; the update after a pick is
+ * a subtraction over the picked node's components).
+ * Reading: the caller's CSR stores both directions of every pair with the
+ * same probability and no parallel arcs; the pair's coin is drawn under the
+ * index of its canonical arc (the direction whose tail is the smaller id);
+ * a self-loop is its own pair and never changes a component.
+ * ====================================================================== */
+
+typedef struct { uint32_t lo, hi, tail; uint64_t e; } pair_rec;
+
+static int pair_cmp(const void *a, const void *b)
+{
+    const pair_rec *x = (const pair_rec *)a, *y = (const pair_rec *)b;
+    if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+    if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+    if (x->tail != y->tail) return x->tail < y->tail ? -1 : 1;
+    return 0;
+}
+
+/* pair[e] = the canonical arc of e's undirected pair; ORACLE_EINVAL unless
+ * every arc's reverse is stored exactly once with the same probability */
+int oracle_pair_ids(uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
+                    const float *prob, uint32_t *pair)
+{
+    int rc = check_graph(n, m, row_ptr, col, prob, 1);
+    if (rc) return rc;
+    pair_rec *a = (pair_rec *)malloc((m ? m : 1) * sizeof(pair_rec));
+    if (!a) return ORACLE_ENOMEM;
+    for (uint32_t u = 0; u < n; u++)
+        for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+            uint32_t v = col[e];
+            a[e].lo = u < v ? u : v;
+            a[e].hi = u < v ? v : u;
+            a[e].tail = u;
+            a[e].e = e;
+        }
+    qsort(a, m, sizeof(pair_rec), pair_cmp);
+    rc = ORACLE_OK;
+    for (uint64_t i = 0; i < m && rc == ORACLE_OK;) {
+        if (a[i].lo == a[i].hi) {                       /* self-loop: its own pair */
+            if (i + 1 < m && a[i + 1].lo == a[i].lo && a[i + 1].hi == a[i].hi) rc = ORACLE_EINVAL;
+            pair[a[i].e] = (uint32_t)a[i].e;
+            i += 1;
+            continue;
+        }
+        /* exactly two arcs: lo -> hi (canonical), then hi -> lo */
+        if (i + 1 >= m || a[i + 1].lo != a[i].lo || a[i + 1].hi != a[i].hi ||
+            a[i].tail != a[i].lo || a[i + 1].tail != a[i].hi ||
+            (i + 2 < m && a[i + 2].lo == a[i].lo && a[i + 2].hi == a[i].hi) ||
+            prob[a[i].e] != prob[a[i + 1].e]) {
+            rc = ORACLE_EINVAL;
+            break;
+        }
+        pair[a[i].e] = (uint32_t)a[i].e;
+        pair[a[i + 1].e] = (uint32_t)a[i].e;
+        i += 2;
+    }
+    free(a);
+    return rc;
+}
+
+/* Algorithm 2 on the pair-coin snapshots (the directed machinery, for
+ * cross-checking the component method) */
+int oracle_select_du_pairs(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                           const uint32_t *col, const float *prob, uint32_t R,
+                           uint32_t k, uint64_t seed, uint32_t *seeds, uint64_t *gains,
+                           uint32_t *trace, uint64_t *stats)
+{
+    uint32_t *pair = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+    if (!pair) return ORACLE_ENOMEM;
+    int rc = oracle_pair_ids(n, m, row_ptr, col, prob, pair);
+    if (rc == ORACLE_OK)
+        rc = select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, pair, seeds, gains, trace,
+                             stats);
+    free(pair);
+    return rc;
+}
+
+static uint32_t uf_find(uint32_t *parent, uint32_t x)
+{
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];   /* path halving */
+        x = parent[x];
+    }
+    return x;
+}
+
+/*
+ * The component method. Per snapshot r: union-find over the live pairs
+ * gives comp_r(u); s_u = sum_r |comp_r(u)| (every node of a component
+ * reaches every other, itself included). A pick v* covers, in every
+ * snapshot where it is still uncovered, its whole component C; each member
+ * u loses |C| (the decrements of Algorithm 2 for the |C| newly covered
+ * nodes, each of which every member reaches).
+ */
+int oracle_select_components(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                             const uint32_t *col, const float *prob, uint32_t R,
+                             uint32_t k, uint64_t seed, uint32_t *seeds, uint64_t *gains,
+                             uint32_t *trace)
+{
+    int rc = check_graph(n, m, row_ptr, col, prob, R);
+    if (rc) return rc;
+    if (k > n) return ORACLE_EINVAL;
+    uint64_t nR = (uint64_t)n * R;
+    uint32_t *pair = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t *root = (uint32_t *)malloc((nR ? nR : 1) * sizeof(uint32_t));   /* [R][n] */
+    uint32_t *size = (uint32_t *)calloc(nR ? nR : 1, sizeof(uint32_t));     /* [R][n] by root */
+    uint32_t *start = (uint32_t *)malloc((nR ? nR : 1) * sizeof(uint32_t)); /* [R][n] by root */
+    uint32_t *member = (uint32_t *)malloc((nR ? nR : 1) * sizeof(uint32_t));/* [R][n] */
+    uint8_t *covered = (uint8_t *)calloc(nR ? nR : 1, 1);                   /* [R][n] by root */
+    int64_t *s = (int64_t *)calloc(n ? n : 1, sizeof(int64_t));
+    uint8_t *sel = (uint8_t *)calloc(n ? n : 1, 1);
+    if (!pair || !root || !size || !start || !member || !covered || !s || !sel) {
+        rc = ORACLE_ENOMEM;
+        goto out;
+    }
+    if ((rc = oracle_pair_ids(n, m, row_ptr, col, prob, pair))) goto out;
+    for (uint32_t r = 0; r < R; r++) {
+        uint32_t *par = root + (uint64_t)r * n;
+        uint32_t *sz = size + (uint64_t)r * n, *st = start + (uint64_t)r * n;
+        uint32_t *mem = member + (uint64_t)r * n;
+        for (uint32_t u = 0; u < n; u++) par[u] = u;
+        /* the live pairs of snapshot r (Sec. 3.1, one coin per pair) */
+        for (uint32_t u = 0; u < n; u++)
+            for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+                if (pair[e] != e || col[e] == u) continue;
+                if (!arc_live(sm64_output(seed, e + 1u), r, arc_threshold(prob[e]))) continue;
+                uint32_t a = uf_find(par, u), b = uf_find(par, col[e]);
+                if (a != b) par[a < b ? b : a] = a < b ? a : b;
+            }
+        for (uint32_t u = 0; u < n; u++) par[u] = uf_find(par, u);
+        for (uint32_t u = 0; u < n; u++) sz[par[u]]++;
+        /* members of each component, grouped by root (counting sort) */
+        uint32_t acc = 0;
+        for (uint32_t x = 0; x < n; x++) { st[x] = acc; acc += sz[x]; }
+        for (uint32_t u = 0; u < n; u++) mem[st[par[u]]++] = u;
+        for (uint32_t x = 0; x < n; x++) st[x] -= sz[x];
+        for (uint32_t u = 0; u < n; u++) s[u] += sz[par[u]];
+    }
+    for (uint32_t t = 0; t < k; t++) {
+        if (trace)
+            for (uint32_t u = 0; u < n; u++) trace[(uint64_t)t * n + u] = (uint32_t)s[u];
+        uint32_t best = argmax_unselected(n, s, sel);
+        seeds[t] = best;
+        gains[t] = (uint64_t)s[best];
+        sel[best] = 1;
+        for (uint32_t r = 0; r < R; r++) {
+            uint64_t o = (uint64_t)r * n;
+            uint32_t c = root[o + best];
+            if (covered[o + c]) continue;
+            covered[o + c] = 1;
+            uint32_t csz = size[o + c];
+            for (uint32_t i = 0; i < csz; i++) {
+                uint32_t u = member[o + start[o + c] + i];
+                s[u] -= csz;
+                if (s[u] < 0) { rc = ORACLE_EINTERNAL; goto out; }
+            }
+        }
+    }
+    if (trace)
+        for (uint32_t u = 0; u < n; u++) trace[(uint64_t)k * n + u] = (uint32_t)s[u];
+out:
+    free(pair); free(root); free(size); free(start); free(member); free(covered);
+    free(s); free(sel);
+    return rc;
 }

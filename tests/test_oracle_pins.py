@@ -388,6 +388,120 @@ def test_spread_prefix_of_greedy_seeds_is_the_gain_sequence():
     assert int(per.sum()) == int(gains.sum())
 
 
+# ---------------------------------------------------------------- undirected, pair coins
+
+
+def _sym(n, pairs, p):
+    """Symmetric CSR of undirected pairs; p: one probability per pair or a scalar."""
+    ps = list(p) if np.ndim(p) else [p] * len(pairs)
+    arcs = {}
+    for (u, v), q in zip(pairs, ps):
+        arcs[(u, v)] = q
+        arcs[(v, u)] = q
+    keys = sorted(arcs)
+    row_ptr, col, _ = _csr(n, keys, 0.0)
+    prob = np.array([arcs[k] for k in keys], np.float32)
+    return row_ptr, col, prob
+
+
+def _random_sym(rng, n, npairs, pmin, pmax):
+    pairs = set()
+    while len(pairs) < npairs:
+        u, v = (int(x) for x in rng.integers(0, n, 2))
+        if u != v:
+            pairs.add((min(u, v), max(u, v)))
+    pairs = sorted(pairs)
+    return _sym(n, pairs, rng.uniform(pmin, pmax, len(pairs)).astype(np.float32))
+
+
+def test_pair_ids_and_symmetry_checks():
+    # arcs in CSR order: 0->1, 0->2, 1->0, 2->0, 2->2 (self-loop)
+    row_ptr = np.array([0, 2, 3, 5], np.uint64)
+    col = np.array([1, 2, 0, 0, 2], np.uint32)
+    prob = np.array([0.5, 0.25, 0.5, 0.25, 0.9], np.float32)
+    assert oracle.pair_ids(row_ptr, col, prob).tolist() == [0, 1, 0, 1, 4]
+    with pytest.raises(oracle.OracleError):      # 2->0 missing
+        oracle.pair_ids(np.array([0, 2, 3, 3], np.uint64), col[:3], prob[:3])
+    with pytest.raises(oracle.OracleError):      # probabilities differ
+        oracle.pair_ids(row_ptr, col, np.array([0.5, 0.25, 0.5, 0.3, 0.9], np.float32))
+    # a parallel arc 0->1 (and its reverse) is rejected
+    rp = np.array([0, 2, 4], np.uint64)
+    with pytest.raises(oracle.OracleError):
+        oracle.pair_ids(rp, np.array([1, 1, 0, 0], np.uint32), np.full(4, 0.5, np.float32))
+
+
+def test_pair_coins_follow_the_generator_rule():
+    # both directions of a pair carry the coins of the canonical arc's index,
+    # drawn by the independent big-integer reading of the generator
+    rng = np.random.default_rng(8)
+    row_ptr, col, prob = _random_sym(rng, 9, 14, 0.1, 0.9)
+    pair = oracle.pair_ids(row_ptr, col, prob)
+    R, seed = 130, 21
+    bits = oracle.live_bits(prob, R, seed, key_of=pair)
+    tails = np.repeat(np.arange(9), np.diff(row_ptr.astype(np.int64)))
+    for e in range(len(col)):
+        assert tails[pair[e]] < col[pair[e]] and {tails[e], col[e]} == {tails[pair[e]], col[pair[e]]}
+        for r in range(R):
+            live = _py_live(seed, int(pair[e]), r, float(prob[e]))
+            assert ((int(bits[e, r // 64]) >> (r % 64)) & 1) == live
+        assert (bits[e] == bits[pair[e]]).all()
+
+
+def _pair_snapshots(row_ptr, col, prob, R, seed):
+    n = len(row_ptr) - 1
+    pair = oracle.pair_ids(row_ptr, col, prob)
+    adj = [[[] for _ in range(n)] for _ in range(R)]
+    for u in range(n):
+        for e in range(int(row_ptr[u]), int(row_ptr[u + 1])):
+            for r in range(R):
+                if _py_live(seed, int(pair[e]), r, float(prob[e])):
+                    adj[r][u].append(int(col[e]))
+    return adj
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_components_equal_bruteforce_greedy(case):
+    rng = np.random.default_rng(700 + case)
+    n = int(rng.integers(4, 11))
+    npairs = min(int(rng.integers(2, 2 * n)), n * (n - 1) // 2)
+    row_ptr, col, prob = _random_sym(rng, n, npairs, 0.1, 0.9)
+    R, k = int(rng.choice([1, 5, 64, 70])), int(rng.integers(1, n + 1))
+    seed = int(rng.integers(1, 99))
+    adj = _pair_snapshots(row_ptr, col, prob, R, seed)
+    S_ref, g_ref = _greedy_by_definition(adj, n, k)
+    s, g, _ = oracle.select_components(row_ptr, col, prob, R, k, seed)
+    assert s.tolist() == S_ref and g.tolist() == g_ref
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_components_equal_du_on_pair_coins(case):
+    # the component method against Algorithm 2's reverse decrements on the
+    # same pair-coin snapshots: every round's full gain vector
+    g = gg.chung_lu_graph(2500 + 500 * case, 10000 + 3000 * case, 2.3 + 0.1 * case, 60 + case,
+                          False, [0.02, 0.1, None, 0.3][case])
+    if case == 2:   # weighted cascade is not symmetric: give each pair one probability
+        g.prob[:] = 0.15
+    R, k, seed = [64, 100, 130, 33][case], 12, 5 + case
+    a = oracle.select_components(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    b = oracle.select_du_pairs(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all() and (a[2] == b[2]).all()
+
+
+def test_components_closed_forms():
+    R = 70
+    # p = 1: an undirected path is one component; a second path and an
+    # isolated node follow, each picked once, then zeros
+    row_ptr, col, prob = _sym(10, [(0, 1), (1, 2), (2, 3), (5, 6), (6, 7)], 1.0)
+    s, g, tr = oracle.select_components(row_ptr, col, prob, R, 6, 3, trace=True)
+    assert s.tolist() == [0, 5, 4, 8, 9, 1]
+    assert g.tolist() == [4 * R, 3 * R, R, R, R, 0]
+    assert tr[0].tolist() == [4 * R] * 4 + [R] + [3 * R] * 3 + [R, R]
+    # p = 0: every node is alone in every snapshot
+    row_ptr, col, prob = _sym(6, [(0, 1), (2, 3)], 0.0)
+    s, g, _ = oracle.select_components(row_ptr, col, prob, R, 3, 3)
+    assert s.tolist() == [0, 1, 2] and g.tolist() == [R] * 3
+
+
 # ---------------------------------------------------------------- semantics
 
 
