@@ -100,10 +100,15 @@ int im_workspace_destroy(im_workspace *ws);
  *     the first batch of a round holds the nodes whose bound reaches the
  *     network's predicted gain of its best-scored node (the round's
  *     must-evaluate set when the prediction is right), later batches in
- *     bound order. */
+ *     bound order.
+ *   IM_OPT_PAIR_COINS: 1 draws one coin per undirected pair (see
+ *     im_pair_ids) instead of one per stored arc, for the single-graph calls
+ *     (im_snapshot_masks, im_initial_gains, im_select, im_select_lazy,
+ *     im_autotune) on a symmetric CSR; the results are then those of
+ *     im_select_undirected. Default 0. Not for batches or plans. */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
-       IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9 };
+       IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -346,6 +351,31 @@ int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uin
  * null pointers, R out of range, a seed >= n or a malformed graph. */
 int im_spread(const im_graph *g, uint32_t R, uint64_t seed, const uint32_t *S, uint32_t nS,
               uint64_t *marg_out, uint32_t *per_snapshot_out, im_workspace *ws, void *stream);
+
+/* Undirected graphs (Sec. 4: in an undirected snapshot the nodes a node
+ * reaches are the nodes that reach it, so each snapshot is described by its
+ * connected components). The CSR must store both directions of every
+ * undirected pair, with the same probability, and no pair twice in one
+ * direction (self-loops are allowed and ignored); each pair then has one
+ * coin per snapshot, drawn by the arc generator rule under the index of its
+ * canonical arc (the direction whose tail is the smaller node id).
+ * im_pair_ids: pair_out [m] uint32 (device) = the canonical arc of each
+ * arc's pair (a self-loop is its own). Synchronous. IM_EINVAL if the CSR
+ * is not symmetric in this sense (the message names the defect). */
+int im_pair_ids(const im_graph *g, uint32_t *pair_out, im_workspace *ws, void *stream);
+
+/* k-seed selection on an undirected graph by the component method: per
+ * snapshot a union-find forest of the live pairs; s_u = sum_r |C_r(u)|;
+ * a pick covers the picked node's uncovered components, whose members lose
+ * their size. Results (seeds_out [k], gains_out [k], trace_out [k+1][n] or
+ * NULL, device) equal im_select's with IM_OPT_PAIR_COINS on the same
+ * graph. Argument rules as im_select; IM_EINVAL also for a CSR that is not
+ * symmetric as im_pair_ids requires. Device memory: 8 n R bytes for the
+ * forests and component sizes. Returns after validation and pair matching
+ * (host-synchronous), the rest asynchronous on `stream`. */
+int im_select_undirected(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                         uint32_t *seeds_out, uint64_t *gains_out, uint32_t *trace_out,
+                         im_workspace *ws, void *stream);
 
 #ifdef __cplusplus
 }

@@ -8,4 +8,5 @@ passes torch tensors' device pointers and the current stream to it.
 from ._native import ImError  # noqa: F401
 from .api import (Workspace, Graph, Plan, BatchPlan, Mlp, select, select_batch, select_lazy,  # noqa: F401
                   initial_gains, snapshot_masks, transpose, validate, node_features,
-                  mlp_samples, autotune, autotune_batch, spread)
+                  mlp_samples, autotune, autotune_batch, spread,
+                  pair_ids, select_undirected)

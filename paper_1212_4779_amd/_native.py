@@ -20,7 +20,8 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_select_batch", "im_mlp_create", "im_mlp_destroy", "im_mlp_set_params",
            "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
            "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy",
-           "im_autotune", "im_autotune_batch", "im_plan_create_batch", "im_spread")
+           "im_autotune", "im_autotune_batch", "im_plan_create_batch", "im_spread",
+           "im_pair_ids", "im_select_undirected")
 IM_MLP_NPARAM = 4609
 IM_SPREAD_R_MAX = 1 << 20
 IM_PH_MAX = 24
@@ -37,6 +38,7 @@ IM_OPT_TIER2_LANES = 6
 IM_OPT_SPARSE_LISTS = 7
 IM_OPT_FWD_GROUPS = 8
 IM_OPT_LEARNED_POLICY = 9
+IM_OPT_PAIR_COINS = 10
 
 
 class ImGraph(ctypes.Structure):
@@ -139,6 +141,8 @@ def lib():
         L.im_autotune_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, ctypes.POINTER(ImTuning)]
         L.im_plan_create_batch.argtypes = [ctypes.POINTER(ImInstance), u32, p, p, p, p, ctypes.POINTER(p)]
         L.im_spread.argtypes = [G, u32, u64, p, u32, p, p, p, p]
+        L.im_pair_ids.argtypes = [G, p, p, p]
+        L.im_select_undirected.argtypes = [G, u32, u32, u64, p, p, p, p, p]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

@@ -117,6 +117,10 @@ class Workspace:
         """1: score order among can-win nodes; 2: first batch sized by the predicted gain."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LEARNED_POLICY, int(policy)))
 
+    def set_pair_coins(self, on):
+        """One coin per undirected pair (symmetric CSR) for single-graph calls."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_PAIR_COINS, int(bool(on))))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases
@@ -422,6 +426,34 @@ def select_lazy(graph, R, k, seed, batch=64, model=None, ws=None):
                                    model.handle if model is not None else ctypes.c_void_p(0),
                                    _ptr(seeds), _ptr(gains), ws.handle, _stream(dev)))
     return _u32(seeds), gains
+
+
+def pair_ids(graph, ws=None):
+    """Canonical arc of every arc's undirected pair (int64 [m]); ImError
+    unless the CSR is symmetric (both directions, equal probabilities, no
+    pair twice in one direction)."""
+    dev = graph.device
+    out = torch.empty(graph.m, dtype=torch.int32, device=dev)
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_pair_ids(ctypes.byref(g), _ptr(out), ws.handle, _stream(dev)))
+    return _u32(out)
+
+
+def select_undirected(graph, R, k, seed, ws=None, trace=False):
+    """k seeds on an undirected graph by the component method (one coin per
+    pair). Returns (seeds int64 [k], gains int64 [k], trace int64 [k+1, n] or None),
+    the results of select() with pair coins."""
+    dev = graph.device
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    gains = torch.empty(k, dtype=torch.int64, device=dev)
+    tr = torch.empty((k + 1, graph.n), dtype=torch.int32, device=dev) if trace else None
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    N.check(N.lib().im_select_undirected(ctypes.byref(g), R, k, seed, _ptr(seeds), _ptr(gains),
+                                         _ptr(tr) if trace else ctypes.c_void_p(0), ws.handle,
+                                         _stream(dev)))
+    return _u32(seeds), gains, (_u32(tr) if trace else None)
 
 
 def spread(graph, R, seed, seeds, ws=None, marginals=True, per_snapshot=False):

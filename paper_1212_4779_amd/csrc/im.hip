@@ -280,14 +280,16 @@ __global__ void k_scan_add(uint32_t *out, uint64_t len, const uint32_t *sums)
 // In a batch, arc e belongs to instance i and is arc e - arc_off[i] of it:
 // the instance's own seed and R apply (its words beyond R are all zero).
 // word w0 + blockIdx.y of every arc, stored at mask[blockIdx.y][e]
+// key_of (single graphs): the index arc e's coins are drawn under (one coin
+// per undirected pair: both directions use the canonical arc's index)
 __global__ __launch_bounds__(256) void k_mask_gen(const float *prob, uint64_t m, uint32_t R,
                                                   uint64_t seed, uint64_t *mask, Batch b,
-                                                  uint32_t w0 = 0)
+                                                  uint32_t w0 = 0, const uint32_t *key_of = nullptr)
 {
     uint64_t e = blockIdx.x * 256ull + threadIdx.x;
     uint32_t w = w0 + blockIdx.y;
     if (e >= m) return;
-    uint64_t el = e;
+    uint64_t el = key_of ? key_of[e] : e;
     if (b.arc_off) {
         const uint32_t i = find_instance<uint64_t>(b.arc_off, b.count, e);
         el = e - b.arc_off[i];
@@ -1169,6 +1171,11 @@ struct im_workspace {
     uint32_t *v_row32 = nullptr;
     uint64_t *v_mask = nullptr, *v_reach = nullptr, *v_pend = nullptr, *v_cov = nullptr;
     uint32_t *v_qa = nullptr, *v_qb = nullptr, *v_vis = nullptr;
+    // undirected graphs: one coin per pair (directed engines), component method state
+    int pair_coins = 0;
+    uint32_t *pair = nullptr;
+    uint64_t cap_pair = 0;
+    UndState *und = nullptr;
     // misc
     unsigned long long *stats = nullptr;
     uint32_t *err = nullptr;
@@ -1293,6 +1300,9 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->c_feat); dfree(ws->c_sort);
     dfree(ws->e_reach); dfree(ws->e_pend); dfree(ws->e_fq0); dfree(ws->e_fq1); dfree(ws->e_vis);
     dfree(ws->e_cnt);
+    und_state_free(ws->und);
+    ws->und = nullptr;
+    dfree(ws->pair);
     dfree(ws->v_row32); dfree(ws->v_mask); dfree(ws->v_reach); dfree(ws->v_pend); dfree(ws->v_cov);
     dfree(ws->v_qa); dfree(ws->v_qb); dfree(ws->v_vis);
     dfree(ws->stats); dfree(ws->err);
@@ -1492,7 +1502,8 @@ static void build_masks(const im_graph *g, uint32_t R, uint64_t seed, im_workspa
     dim3 grid((unsigned)((m + 255) / 256), W);
     {
         PhaseTimer pt(ws, IM_PH_MASK_GEN, s);
-        k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, mask_out, ws->batch);
+        k_mask_gen<<<grid, 256, 0, s>>>(g->prob, m, R, seed, mask_out, ws->batch, 0u,
+                                        ws->pair_coins ? ws->pair : nullptr);
     }
     if (reverse) {
         PhaseTimer pt(ws, IM_PH_MASK_GATHER, s);
@@ -1704,7 +1715,17 @@ static int check_and_reserve(const im_graph *g, uint32_t R, uint32_t k, im_works
 {
     int rc;
     if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, k, g->n))) return rc;
-    return validate(g, ws, s, ws->row32);
+    if ((rc = validate(g, ws, s, ws->row32))) return rc;
+    if (ws->pair_coins) {
+        // the pair of every arc (host-synchronous; before any capture)
+        if (ws->batch.count > 1) return im_fail(IM_EINVAL, "pair coins apply to single graphs only");
+        if (g->m > ws->cap_pair || !ws->pair) {
+            if ((rc = dalloc(&ws->pair, g->m))) return rc;
+            ws->cap_pair = g->m;
+        }
+        if ((rc = und_pair_ids(g, ws->row32, ws->pair, ws, s))) return rc;
+    }
+    return IM_OK;
 }
 
 // everything after validation up to (and including) the initial gains:
@@ -2760,6 +2781,16 @@ extern "C" int im_spread(const im_graph *g, uint32_t R, uint64_t seed, const uin
     return IM_OK;
 }
 
+// accessors for the other translation units
+UndState **im_ws_und(im_workspace *ws) { return &ws->und; }
+
+int im_ws_validate(const im_graph *g, im_workspace *ws, hipStream_t s, uint32_t *row32)
+{
+    return validate(g, ws, s, row32);
+}
+
+void im_ws_set_last_stream(im_workspace *ws, hipStream_t s) { ws->last_stream = s; }
+
 extern "C" int im_validate(const im_graph *g, uint32_t R, void *stream)
 {
     if (!g) return im_fail(IM_EINVAL, "null graph");
@@ -3027,6 +3058,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
     case IM_OPT_LAZY_ENGINE:
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");
         ws->lazy_engine = (int)value;
+        return IM_OK;
+    case IM_OPT_PAIR_COINS:
+        if (value != 0 && value != 1) return im_fail(IM_EINVAL, "pair coins must be 0 or 1");
+        ws->pair_coins = (int)value;
         return IM_OK;
     default:
         return im_fail(IM_EINVAL, "unknown option %d", option);

@@ -131,6 +131,15 @@ WORKLOADS = {
     # R=256, k=50
     "million_uic": dict(n=1000000, m=10000000, gamma=2.1, graph_seed=3, directed=True,
                         p=0.01, R=256, k=50, seed=1),
+    # the NetHEPT-shaped undirected graph under uniform IC p=0.01 with one coin
+    # per undirected pair, R=100, k=50
+    "nethept_uic": dict(n=15000, m=59000, gamma=2.5, graph_seed=2, directed=False, p=0.01,
+                        R=100, k=50, seed=1),
+    # undirected power law 2.1, 1,000,000 nodes, 5,000,000 pairs (10,000,000 stored
+    # arcs), uniform IC p=0.01 with one coin per pair, R=256, k=50: a DBLP-like
+    # scale, large enough that every snapshot has a giant component
+    "million_undirected_uic": dict(n=1000000, m=10000000, gamma=2.1, graph_seed=5,
+                                   directed=False, p=0.01, R=256, k=50, seed=1),
 }
 
 
