@@ -334,7 +334,7 @@ int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uin
                    im_workspace *ws, void *stream);
 
 /* Spread evaluation (the snapshot estimator of Sec. 3.1; the paper scores
- * seed sets on independent simulations, Sec. 6). With f(T) = sum_r |R_r(T)|
+ * seed sets on independent simulations, Sec. 5.2). With f(T) = sum_r |R_r(T)|
  * over R snapshots drawn from `seed` by the same live-edge rule as selection
  * (another seed gives snapshots independent of those a selection used):
  *   marg_out[i] = f(S[0..i]) - f(S[0..i-1]), uint64 [nS] (device), so the

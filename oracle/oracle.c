@@ -629,7 +629,7 @@ int oracle_spread(uint32_t n, uint64_t m, const uint64_t *row_ptr,
 }
 
 /* Prefix spreads (Sec. 3.1 estimator, used to score seed sets on snapshots
- * independent of the ones that chose them, Sec. 6):
+ * independent of the ones that chose them, Sec. 5.2):
  *   marg[i] = f(S[0..i]) - f(S[0..i-1]),  per[r] = |R(G'_r, S)|.
  * Every prefix is searched from scratch, straight from the definition of f.
  * marg or per may be NULL. */

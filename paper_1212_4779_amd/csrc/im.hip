@@ -2629,7 +2629,7 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
 // Spread evaluator: f(T) = sum_r |R_r(T)| (the snapshot estimator of Sec. 3.1,
 // times R) for the prefixes of a seed sequence, on snapshots of any seed, so
 // a seed set can be scored on snapshots independent of those that chose it
-// (the evaluation protocol of Sec. 6). One workgroup per snapshot word covers
+// (the evaluation protocol of Sec. 5.2). One workgroup per snapshot word covers
 // the seeds group by group: each group's search is pruned at the nodes the
 // earlier groups covered, so its reach count is the group's marginal gain.
 // ---------------------------------------------------------------------------
@@ -2783,6 +2783,14 @@ extern "C" int im_spread(const im_graph *g, uint32_t R, uint64_t seed, const uin
 
 // accessors for the other translation units
 UndState **im_ws_und(im_workspace *ws) { return &ws->und; }
+
+uint64_t im_scan_sums_len(uint64_t len) { return (len + SCAN_TILE - 1) / SCAN_TILE + 2; }
+
+void im_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t len, uint32_t *sums,
+                       hipStream_t s)
+{
+    if (len) exclusive_scan(in, out, len, sums, s);
+}
 
 int im_ws_validate(const im_graph *g, im_workspace *ws, hipStream_t s, uint32_t *row32)
 {

@@ -26,3 +26,8 @@ int und_pair_ids(const im_graph *g, const uint32_t *row32, uint32_t *pair, im_wo
 UndState **im_ws_und(im_workspace *ws);              // im.hip
 int im_ws_validate(const im_graph *g, im_workspace *ws, hipStream_t s, uint32_t *row32);
 void im_ws_set_last_stream(im_workspace *ws, hipStream_t s);
+// exclusive prefix sum of len uint32 values (in and out may not alias);
+// sums: scratch of im_scan_sums_len(len) uint32
+uint64_t im_scan_sums_len(uint64_t len);
+void im_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t len, uint32_t *sums,
+                       hipStream_t s);

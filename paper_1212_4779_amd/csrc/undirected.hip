@@ -23,11 +23,12 @@
 //       snapshot a lock-free union of the end points in that snapshot's
 //       union-find forest (roots are component minima: a larger root is
 //       hooked under a smaller one by compare-and-swap)
-//   U3  labels flattened to roots, component sizes counted at the roots
-//       (wavefront-aggregated), s_u = sum_r size_r(root_r(u)), round-0 key
-//   per round: U4 pick v*, mark its uncovered components covered, then
-//       U5 one pass over the nodes subtracts the covered sizes and computes
-//       the next round's argmax key
+//   U3  labels flattened to roots; every non-root member ranked among its
+//       root's members (wavefront-aggregated atomics); the member lists of
+//       all (snapshot, root) pairs placed by one prefix sum over their
+//       counts and filled; s_u = sum_r |C_r(u)|, round-0 key
+//   per round: U4 one workgroup per snapshot covers v*'s component if it is
+//       still uncovered (its members lose |C|), U5 the next argmax key
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -135,45 +136,54 @@ __global__ __launch_bounds__(256) void k_pair_insert(const uint32_t *row, const 
 }
 
 // every used slot: both directions present with equal probabilities; append
-// the canonical arc (lo -> hi) to the pair list; pair ids of both arcs
+// the canonical arc (lo -> hi) to the pair list (one atomic per block and
+// chunk of PC_SLOTS slots); pair ids of both arcs
+constexpr int PC_PER = 16, PC_SLOTS = 256 * PC_PER;
+
+__device__ __forceinline__ bool pair_ok(const unsigned long long *keys, const uint32_t *val,
+                                        uint64_t cap, const float *prob, uint64_t h,
+                                        uint32_t *err)
+{
+    if (h >= cap || keys[h] == KEY_EMPTY) return false;
+    const uint32_t c = val[h], r = val[cap + h];
+    if (c == NONE || r == NONE) { atomicOr(err, (uint32_t)UE_MISSING); return false; }
+    if (__float_as_uint(prob[c]) != __float_as_uint(prob[r])) {
+        atomicOr(err, (uint32_t)UE_PROB);
+        return false;
+    }
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k_pair_collect(const unsigned long long *keys,
                                                       const uint32_t *val, uint64_t cap,
                                                       const float *prob, uint32_t *pu,
                                                       uint32_t *pv, uint32_t *pe, uint32_t *np,
                                                       uint32_t *pair, uint32_t *err)
 {
-    for (uint64_t base = blockIdx.x * 256ull; base < cap; base += (uint64_t)gridDim.x * 256) {
-        const uint64_t h = base + threadIdx.x;
-        bool keep = false;
-        uint32_t c = NONE, r = NONE;
-        unsigned long long key = KEY_EMPTY;
-        if (h < cap) {
-            key = keys[h];
-            if (key != KEY_EMPTY) {
-                c = val[h];
-                r = val[cap + h];
-                if (c == NONE || r == NONE) atomicOr(err, (uint32_t)UE_MISSING);
-                else if (__float_as_uint(prob[c]) != __float_as_uint(prob[r]))
-                    atomicOr(err, (uint32_t)UE_PROB);
-                else keep = true;
-            }
-        }
-        // wavefront-aggregated append
-        const unsigned long long bal = __ballot(keep);
-        const uint32_t lane = threadIdx.x & 63;
-        uint32_t basepos = 0;
-        if (bal) {
-            const int leader = __ffsll((unsigned long long)bal) - 1;
-            if ((int)lane == leader) basepos = atomicAdd(np, (uint32_t)__popcll(bal));
-            basepos = __shfl(basepos, leader, 64);
-        }
-        if (keep) {
-            const uint32_t q = basepos + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+    __shared__ uint32_t s_w[256 / 64 + 1];
+    __shared__ uint32_t s_base;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * PC_SLOTS; c0 < cap; c0 += (uint64_t)gridDim.x * PC_SLOTS) {
+        uint32_t mine = 0;
+        for (int j = 0; j < PC_PER; j++)
+            mine += pair_ok(keys, val, cap, prob, c0 + (uint64_t)j * 256 + threadIdx.x, err) ? 1u : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<256>(mine, s_w, &total);
+        if (threadIdx.x == 0) s_base = total ? atomicAdd(np, total) : 0u;
+        __syncthreads();
+        uint32_t q = s_base + ex;
+        for (int j = 0; j < PC_PER && mine; j++) {
+            const uint64_t h = c0 + (uint64_t)j * 256 + threadIdx.x;
+            if (h >= cap || keys[h] == KEY_EMPTY) continue;
+            const uint32_t c = val[h], r = val[cap + h];
+            if (c == NONE || r == NONE || __float_as_uint(prob[c]) != __float_as_uint(prob[r])) continue;
+            const unsigned long long key = keys[h];
             pu[q] = (uint32_t)(key >> 32);
             pv[q] = (uint32_t)key;
             pe[q] = c;
             if (pair) { pair[c] = c; pair[r] = c; }
+            q++;
         }
+        __syncthreads();
     }
 }
 
@@ -251,136 +261,145 @@ __global__ __launch_bounds__(256) void k_und_init_labels(uint32_t *lab, uint32_t
         lab[i] = (uint32_t)(i % n);
 }
 
-// lab[r][u] = root of u; size[r][root] counts the members (one atomic per
-// distinct root of a wavefront)
-__global__ __launch_bounds__(256) void k_und_flatten(uint32_t *lab, uint32_t *size, uint32_t n,
-                                                     uint64_t total)
+// Per wavefront, lanes whose keys (a, b) agree form groups; the first lane
+// of each group adds the group's size to cnt[idx] atomically and every lane
+// gets its rank: returns the value cnt[idx] had plus the lane's rank in its group.
+__device__ __forceinline__ uint32_t wave_group_add(bool act, uint64_t idx, uint32_t *cnt)
 {
     const uint32_t lane = threadIdx.x & 63;
+    uint32_t rank = 0;
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+        const int leader = __ffsll(pending) - 1;
+        const uint64_t li = __shfl(idx, leader, 64);
+        const unsigned long long same = __ballot(act && idx == li) & pending;
+        uint32_t base = 0;
+        if ((int)lane == leader) base = atomicAdd(&cnt[li], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    return rank;
+}
+
+// lab[r][u] = root of u. A non-root member takes a rank among its root's
+// other members (cnt[r][root] counts them; roots are component minima, so
+// the root itself is the member with the smallest id).
+__global__ __launch_bounds__(256) void k_und_flatten(uint32_t *lab, uint32_t *cnt, uint32_t *rk,
+                                                     uint32_t n, uint64_t total)
+{
     for (uint64_t base = blockIdx.x * 256ull; base < total; base += (uint64_t)gridDim.x * 256) {
         const uint64_t i = base + threadIdx.x;
-        const bool act = i < total;
-        uint32_t root = NONE;
+        uint32_t root = 0, x = 0;
         uint64_t off = 0;
-        if (act) {
+        if (i < total) {
             // the forests are final here: a read-only walk to the root. Other
             // threads replace parents by roots meanwhile; a replaced entry
             // still leads to the same root, and no entry is ever changed to
             // anything but its root (no path compression in this pass).
-            off = i - i % n;
+            x = (uint32_t)(i % n);
+            off = i - x;
             const uint32_t *par = lab + off;
-            root = (uint32_t)(i % n);
+            root = x;
             for (uint32_t p = par[root]; p != root; p = par[root]) root = p;
             lab[i] = root;
         }
-        unsigned long long pending = __ballot(act);
-        while (pending) {
-            const int leader = __ffsll(pending) - 1;
-            const uint32_t lr = __shfl(root, leader, 64);
-            const uint64_t lo = __shfl(off, leader, 64);
-            const unsigned long long same = __ballot(act && root == lr && off == lo) & pending;
-            if ((int)lane == leader) atomicAdd(&size[lo + lr], (uint32_t)__popcll(same));
-            pending &= ~same;
-        }
+        const bool member = i < total && root != x;
+        const uint32_t r = wave_group_add(member, off + root, cnt);
+        if (member) rk[i] = r;
     }
 }
 
-struct RoundArgs {
-    const uint32_t *lab, *size;
-    uint32_t n, R;
-    uint32_t *gain;
-    const uint8_t *sel;
-    const uint32_t *droot, *dsz;   // per snapshot: covered root and its size (0: none)
-    unsigned long long *key_out;   // argmax key after the update
-};
-
-// s_u -= sum over snapshots where u's component was just covered of its
-// size (initial pass: s_u = sum_r size_r(root_r(u))); then the argmax key
-// (gain << 32 | ~u) over unselected nodes
-// dynamic LDS: 3 * R uint32 (the active snapshots, their roots and sizes)
-template <bool INIT>
-__global__ __launch_bounds__(UN_NT) void k_und_update(RoundArgs a)
+// members into the lists: start = exclusive prefix sum of cnt over all
+// (snapshot, root) entries, mem[start[r][root] + rank] = u
+__global__ __launch_bounds__(256) void k_und_scatter(const uint32_t *lab, const uint32_t *rk,
+                                                     const uint32_t *start, uint32_t *mem,
+                                                     uint32_t n, uint64_t total)
 {
-    extern __shared__ uint32_t s_dyn[];
-    uint32_t *s_act = s_dyn, *s_root = s_dyn + a.R, *s_sz = s_dyn + 2 * a.R;
-    __shared__ uint32_t s_nact;
-    __shared__ unsigned long long s_red[UN_NT / 64];
-    const int tid = threadIdx.x;
-    if (!INIT) {
-        // the snapshots whose covered component changes something
-        if (tid == 0) s_nact = 0;
-        __syncthreads();
-        for (uint32_t r = tid; r < a.R; r += UN_NT) {
-            const uint32_t z = a.dsz[r];
-            if (z) {
-                const uint32_t q = atomicAdd(&s_nact, 1u);
-                s_act[q] = r;
-                s_root[q] = a.droot[r];
-                s_sz[q] = z;
-            }
-        }
-        __syncthreads();
-    }
-    const uint32_t nact = INIT ? 0u : s_nact;
-    unsigned long long best = 0;
-    for (uint32_t u = blockIdx.x * UN_NT + tid; u < a.n; u += gridDim.x * UN_NT) {
-        uint32_t g;
-        if (INIT) {
-            uint64_t sum = 0;
-            for (uint32_t r = 0; r < a.R; r++) {
-                const uint64_t o = (uint64_t)r * a.n;
-                sum += a.size[o + a.lab[o + u]] & ~COVERED;
-            }
-            g = (uint32_t)sum;
-        } else {
-            uint32_t dec = 0;
-            for (uint32_t q = 0; q < nact; q++)
-                if (a.lab[(uint64_t)s_act[q] * a.n + u] == s_root[q]) dec += s_sz[q];
-            g = a.gain[u] - dec;
-        }
-        if (INIT || nact) a.gain[u] = g;
-        if (!a.sel[u]) {
-            const unsigned long long k = ((unsigned long long)g << 32) | (0xFFFFFFFFu - u);
-            best = k > best ? k : best;
-        }
-    }
-    best = wave_max_u64(best);
-    if ((tid & 63) == 0) s_red[tid >> 6] = best;
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long b = 0;
-        for (int i = 0; i < UN_NT / 64; i++) b = s_red[i] > b ? s_red[i] : b;
-        if (b) atomicMax(a.key_out, b);
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < total; i += (uint64_t)gridDim.x * 256) {
+        const uint32_t x = (uint32_t)(i % n);
+        const uint64_t off = i - x;
+        const uint32_t root = lab[i];
+        if (root != x) mem[start[off + root] + rk[i]] = x;
     }
 }
 
-// U4: record the pick; per snapshot the picked node's component, its size
-// if it was uncovered (then marked covered), else 0
-__global__ __launch_bounds__(256) void k_und_pick(const unsigned long long *key, uint32_t t,
-                                                  const uint32_t *lab, uint32_t *size, uint32_t n,
-                                                  uint32_t R, uint8_t *sel, uint32_t *droot,
-                                                  uint32_t *dsz, uint32_t *seeds_out,
-                                                  uint64_t *gains_out)
+__device__ __forceinline__ void block_key_max(unsigned long long best, unsigned long long *red,
+                                              unsigned long long *key_out)
+{
+    best = wave_max_u64(best);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = 0;
+        for (int i = 0; i < UN_NT / 64; i++) b = red[i] > b ? red[i] : b;
+        if (b) atomicMax(key_out, b);
+    }
+}
+
+// s_u = sum_r |C_r(u)| and the round-0 argmax key (gain << 32 | ~u)
+__global__ __launch_bounds__(UN_NT) void k_und_gains(const uint32_t *lab, const uint32_t *cnt,
+                                                     uint32_t n, uint32_t R, uint32_t *gain,
+                                                     unsigned long long *key_out)
+{
+    __shared__ unsigned long long s_red[UN_NT / 64];
+    unsigned long long best = 0;
+    for (uint32_t u = blockIdx.x * UN_NT + threadIdx.x; u < n; u += gridDim.x * UN_NT) {
+        uint64_t sum = 0;
+        for (uint32_t r = 0; r < R; r++) {
+            const uint64_t o = (uint64_t)r * n;
+            sum += (cnt[o + lab[o + u]] & ~COVERED) + 1u;
+        }
+        gain[u] = (uint32_t)sum;
+        const unsigned long long k = (sum << 32) | (0xFFFFFFFFu - u);
+        best = k > best ? k : best;
+    }
+    block_key_max(best, s_red, key_out);
+}
+
+// U4: one workgroup per snapshot. The picked node v* covers its component C
+// if still uncovered: every member (the root and its listed members) loses
+// |C|. Workgroup 0 records the pick.
+__global__ __launch_bounds__(UN_NT) void k_und_cover(const unsigned long long *key, uint32_t t,
+                                                     const uint32_t *lab, uint32_t *cnt,
+                                                     const uint32_t *start, const uint32_t *mem,
+                                                     uint32_t n, uint8_t *sel, uint32_t *gain,
+                                                     uint32_t *seeds_out, uint64_t *gains_out)
 {
     const unsigned long long k = *key;
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull);
-    if (threadIdx.x == 0) {
+    const uint32_t r = blockIdx.x;
+    if (r == 0 && threadIdx.x == 0) {
         seeds_out[t] = v;
         gains_out[t] = k >> 32;
         sel[v] = 1;
     }
-    for (uint32_t r = threadIdx.x; r < R; r += 256) {
-        const uint64_t o = (uint64_t)r * n;
-        const uint32_t root = lab[o + v];
-        const uint32_t z = size[o + root];
-        droot[r] = root;
-        if (z & COVERED) {
-            dsz[r] = 0;
-        } else {
-            dsz[r] = z;
-            size[o + root] = z | COVERED;
-        }
+    const uint64_t o = (uint64_t)r * n;
+    const uint32_t root = lab[o + v];
+    const uint32_t z = cnt[o + root];
+    if (z & COVERED) return;   // uniform over the workgroup
+    __syncthreads();           // every thread has read z before it is marked
+    const uint32_t size = z + 1;
+    if (threadIdx.x == 0) {
+        cnt[o + root] = z | COVERED;
+        atomicSub(&gain[root], size);
     }
+    const uint32_t *m = mem + (z ? start[o + root] : 0u);
+    for (uint32_t i = threadIdx.x; i < z; i += UN_NT) atomicSub(&gain[m[i]], size);
+}
+
+// U5: the next round's key over the unselected nodes
+__global__ __launch_bounds__(UN_NT) void k_und_argmax(const uint32_t *gain, const uint8_t *sel,
+                                                      uint32_t n, unsigned long long *key_out)
+{
+    __shared__ unsigned long long s_red[UN_NT / 64];
+    unsigned long long best = 0;
+    for (uint32_t u = blockIdx.x * UN_NT + threadIdx.x; u < n; u += gridDim.x * UN_NT) {
+        if (sel[u]) continue;
+        const unsigned long long k = ((unsigned long long)gain[u] << 32) | (0xFFFFFFFFu - u);
+        best = k > best ? k : best;
+    }
+    block_key_max(best, s_red, key_out);
 }
 
 __global__ void k_und_copy(const uint32_t *src, uint32_t *dst, uint32_t n)
@@ -402,8 +421,11 @@ struct UndState {
     uint32_t *pu = nullptr, *pv = nullptr, *pe = nullptr;  // canonical pairs
     uint32_t *np = nullptr, *err = nullptr, *host_err = nullptr;
     uint32_t *row32 = nullptr;
-    uint32_t *lab = nullptr, *size = nullptr;    // [R][n]
-    uint32_t *gain = nullptr, *droot = nullptr, *dsz = nullptr;
+    uint32_t *lab = nullptr, *cnt = nullptr, *rk = nullptr, *start = nullptr,
+             *mem = nullptr;                     // [R][n]
+    uint32_t *sums = nullptr;                    // scan scratch
+    uint64_t cap_sums = 0;
+    uint32_t *gain = nullptr;
     uint8_t *sel = nullptr;
     unsigned long long *ukeys = nullptr;         // [k+1] argmax keys
     uint32_t cap_k = 0;
@@ -413,8 +435,9 @@ void und_state_free(UndState *st)
 {
     if (!st) return;
     ufree(st->keys); ufree(st->val); ufree(st->pu); ufree(st->pv); ufree(st->pe);
-    ufree(st->np); ufree(st->err); ufree(st->row32); ufree(st->lab); ufree(st->size);
-    ufree(st->gain); ufree(st->droot); ufree(st->dsz); ufree(st->sel); ufree(st->ukeys);
+    ufree(st->np); ufree(st->err); ufree(st->row32); ufree(st->lab); ufree(st->cnt);
+    ufree(st->rk); ufree(st->start); ufree(st->mem); ufree(st->sums);
+    ufree(st->gain); ufree(st->sel); ufree(st->ukeys);
     if (st->host_err) (void)hipHostFree(st->host_err);
     delete st;
 }
@@ -530,11 +553,14 @@ extern "C" int im_select_undirected(const im_graph *g, uint32_t R, uint32_t k, u
     if ((rc = und_state(ws, &st)) || (rc = reserve_pairs(st, n, g->m))) return rc;
     const uint64_t nR = (uint64_t)n * R;
     if (nR > st->cap_nR || !st->lab) {
-        if ((rc = ualloc(&st->lab, nR)) || (rc = ualloc(&st->size, nR))) return rc;
+        if ((rc = ualloc(&st->lab, nR)) || (rc = ualloc(&st->cnt, nR)) || (rc = ualloc(&st->rk, nR)) ||
+            (rc = ualloc(&st->start, nR)) || (rc = ualloc(&st->mem, nR)))
+            return rc;
         st->cap_nR = nR;
     }
-    if (!st->droot) {
-        if ((rc = ualloc(&st->droot, IM_R_MAX)) || (rc = ualloc(&st->dsz, IM_R_MAX))) return rc;
+    if (im_scan_sums_len(nR) > st->cap_sums || !st->sums) {
+        if ((rc = ualloc(&st->sums, im_scan_sums_len(nR)))) return rc;
+        st->cap_sums = im_scan_sums_len(nR);
     }
     if (k + 1 > st->cap_k || !st->ukeys) {
         if ((rc = ualloc(&st->ukeys, (uint64_t)k + 1))) return rc;
@@ -546,30 +572,27 @@ extern "C" int im_select_undirected(const im_graph *g, uint32_t R, uint32_t k, u
 
     // U2: forests of all snapshots
     k_und_init_labels<<<ugrid(nR, 256), 256, 0, s>>>(st->lab, n, nR);
-    ufill<uint32_t>(st->size, nR, 0u, s);
+    ufill<uint32_t>(st->cnt, nR, 0u, s);
     const uint32_t W = (R + 63) / 64;
     if (g->m) {
         dim3 grid(ugrid(g->m / 2 + 1, 256, 8192), W);
         k_und_union<<<grid, 256, 0, s>>>(st->pu, st->pv, st->pe, st->np, g->prob, n, R, seed,
                                          st->lab);
     }
-    // U3: roots, sizes, initial gains and the round-0 key
-    k_und_flatten<<<ugrid(nR, 256), 256, 0, s>>>(st->lab, st->size, n, nR);
+    // U3: roots, member lists, initial gains and the round-0 key
+    k_und_flatten<<<ugrid(nR, 256), 256, 0, s>>>(st->lab, st->cnt, st->rk, n, nR);
+    im_exclusive_scan(st->cnt, st->start, nR, st->sums, s);
+    k_und_scatter<<<ugrid(nR, 256), 256, 0, s>>>(st->lab, st->rk, st->start, st->mem, n, nR);
     ufill<uint8_t>(st->sel, n, (uint8_t)0, s);
     ufill<unsigned long long>(st->ukeys, (uint64_t)k + 1, 0ull, s);
-    RoundArgs a;
-    a.lab = st->lab; a.size = st->size; a.n = n; a.R = R; a.gain = st->gain; a.sel = st->sel;
-    a.droot = st->droot; a.dsz = st->dsz; a.key_out = st->ukeys;
     const unsigned ug = ugrid(n, UN_NT, 4096);
-    const size_t lds = 3 * sizeof(uint32_t) * R;
-    k_und_update<true><<<ug, UN_NT, 0, s>>>(a);
+    k_und_gains<<<ug, UN_NT, 0, s>>>(st->lab, st->cnt, n, R, st->gain, st->ukeys);
     for (uint32_t t = 0; t < k; t++) {
         if (trace_out)
             k_und_copy<<<ugrid(n, 256), 256, 0, s>>>(st->gain, trace_out + (uint64_t)t * n, n);
-        k_und_pick<<<1, 256, 0, s>>>(st->ukeys + t, t, st->lab, st->size, n, R, st->sel,
-                                     st->droot, st->dsz, seeds_out, gains_out);
-        a.key_out = st->ukeys + t + 1;
-        k_und_update<false><<<ug, UN_NT, lds, s>>>(a);
+        k_und_cover<<<R, UN_NT, 0, s>>>(st->ukeys + t, t, st->lab, st->cnt, st->start, st->mem, n,
+                                        st->sel, st->gain, seeds_out, gains_out);
+        k_und_argmax<<<ugrid(n, UN_NT, 256), UN_NT, 0, s>>>(st->gain, st->sel, n, st->ukeys + t + 1);
     }
     if (trace_out)
         k_und_copy<<<ugrid(n, 256), 256, 0, s>>>(st->gain, trace_out + (uint64_t)k * n, n);

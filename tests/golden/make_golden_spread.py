@@ -3,7 +3,7 @@
 Calls only the CPU oracle (``oracle/``) and the seeded input generator. For
 each workload it scores the oracle's own greedy seeds (from the stored
 selection golden file) on snapshots of an independent seed (the paper's
-protocol scores seed sets on fresh simulations, Sec. 6): the prefix
+protocol scores seed sets on fresh simulations, Sec. 5.2): the prefix
 increments of f and the per-snapshot reach sizes of the whole set.
 
 Usage: python tests/golden/make_golden_spread.py [workload ...]
