@@ -136,7 +136,10 @@ typedef struct im_stats {
     uint64_t fwd_entries;      /* frontier entries expanded by them               */
     uint64_t celf_batches;     /* evaluation batches of the lazy path             */
     uint64_t celf_fallbacks;   /* learned picks that fell back to bound order     */
-    uint64_t reserved[16];
+    uint64_t max_levels[3][3]; /* per pass and tier: the most search levels one   */
+                               /* workgroup ran in any launch of the call (the    */
+                               /* launch's critical path in levels)               */
+    uint64_t reserved[7];
 } im_stats;
 
 int im_stats_get(im_workspace *ws, im_stats *out);

@@ -62,11 +62,15 @@ class ImStats(ctypes.Structure):
                 [(f, (ctypes.c_uint64 * 3) * 3) for f in TIER_FIELDS] +
                 [("fwd_levels", ctypes.c_uint64), ("fwd_entries", ctypes.c_uint64),
                  ("celf_batches", ctypes.c_uint64), ("celf_fallbacks", ctypes.c_uint64),
-                 ("reserved", ctypes.c_uint64 * 16)])
+                 ("max_levels", (ctypes.c_uint64 * 3) * 3),
+                 ("reserved", ctypes.c_uint64 * 7)])
 
     def as_dict(self):
         d = {f: int(getattr(self, f)) for f in STAT_FIELDS + ("fwd_levels", "fwd_entries",
                                                                "celf_batches", "celf_fallbacks")}
+        for p, pn in enumerate(PASSES):
+            for t in range(3):
+                d[f"max_levels_{pn}_t{t}"] = int(self.max_levels[p][t])
         for f in TIER_FIELDS:
             arr = getattr(self, f)
             for p, pn in enumerate(PASSES):

@@ -2837,6 +2837,7 @@ extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
             out->reached[p][t] = h[st_tier(p, t, F_REACHED)];
             out->arcs_read[p][t] = h[st_tier(p, t, F_ARCS)];
             out->handed_over[p][t] = h[st_tier(p, t, F_OVF)];
+            out->max_levels[p][t] = h[ST_MAXLV_BASE + p * 3 + t];
         }
     return IM_OK;
 }

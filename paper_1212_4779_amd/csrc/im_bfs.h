@@ -32,6 +32,7 @@ enum {
     ST_RELAX_FWD, ST_TASKS_REV, ST_DECREMENTS, ST_CELF_EVALS,
     ST_TIER_BASE = 8,   // + pass*12 + tier*4 + field
     ST_FWD_LEVELS = 44, ST_FWD_ENTRIES = 45, ST_CELF_BATCHES = 46, ST_CELF_FALLBACKS = 47,
+    ST_MAXLV_BASE = 48,   // + pass*3 + tier: most search levels one workgroup ran in a launch
     ST_COUNT = 64
 };
 enum { PASS_INIT = 0, PASS_REV = 1, PASS_EVAL = 2 };
@@ -439,8 +440,10 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
 
     uint64_t st_relax = 0, st_reached = 0, st_arcs = 0, st_trav = 0, st_ovf = 0, st_dec = 0;
     int cur = 0;
+    uint32_t levels = 0;
 
     for (;;) {
+        levels++;
         // ---- refill: thread 0 hands task indices to idle slots
         if (tid == 0) {
             L.nn = 0;
@@ -681,6 +684,7 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_ARCS)], (unsigned long long)st_arcs);
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_OVF)], (unsigned long long)st_ovf);
         atomicAdd(&a.stats[a.st_trav], (unsigned long long)st_trav);
+        atomicMax(&a.stats[ST_MAXLV_BASE + a.pass * 3 + a.tier], (unsigned long long)levels);
     }
 }
 
@@ -846,7 +850,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     // instance (their bits are disjoint, so the decrements add up to those of
     // the joint search). A single graph searches all sources together.
     const bool split = a.node_inst != nullptr;
-    uint64_t arcs = 0, relax = 0, reached = 0, trav = 0, dec = 0;
+    uint64_t arcs = 0, relax = 0, reached = 0, trav = 0, dec = 0, levels = 0;
     for (;;) {
         if (tid == 0) L.task = atomicAdd(a.grab, 1u);
         __syncthreads();
@@ -879,6 +883,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
                 block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.sp, a.n, a.W, w, prune,
                                         reach, pend, base, qa, qb, vis, arcs);
             const uint32_t nvis = L.nvis;
+            levels += L.levels;
             uint64_t cnt = 0;
             for (uint32_t i = tid; i < nvis; i += NT) {
                 uint32_t x = vis[i];
@@ -908,5 +913,6 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)reached);
         atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_ARCS)], (unsigned long long)arcs);
         atomicAdd(&a.stats[a.st_trav], (unsigned long long)trav);
+        atomicMax(&a.stats[ST_MAXLV_BASE + a.pass * 3 + a.tier], (unsigned long long)levels);
     }
 }
