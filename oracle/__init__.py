@@ -63,6 +63,8 @@ def _load():
         lib.oracle_pair_ids.argtypes = [u32, u64, p, p, p, p]
         lib.oracle_select_du_pairs.argtypes = graph + [u32, u64, p, p, p, p]
         lib.oracle_select_components.argtypes = graph + [u32, u64, p, p, p]
+        lib.oracle_live_bits_lt.argtypes = [u32, u64, p, p, p, u32, u64, p]
+        lib.oracle_select_du_lt.argtypes = graph + [u32, u64, p, p, p, p]
         lib.oracle_mlp_nparams.restype = ctypes.c_int
         lib.oracle_bf16_round.argtypes = [u64, p, p]
         lib.oracle_node_features.argtypes = [u32, u64, p, p, p, p]
@@ -164,6 +166,30 @@ def spread(row_ptr, col, prob, R, seed, S):
     _check(_load().oracle_spread(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, seed,
                                  _ptr(S), len(S), ctypes.byref(out)), "spread")
     return int(out.value)
+
+
+def live_bits_lt(row_ptr, col, prob, R, seed):
+    """Linear-threshold live bits, arc-major uint64[m, W] (prob = the weights):
+    per snapshot each node keeps at most one in-arc."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    W = (R + 63) // 64
+    out = np.zeros((m, W), dtype=np.uint64)
+    _check(_load().oracle_live_bits_lt(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, seed,
+                                       _ptr(out)), "live_bits_lt")
+    return out
+
+
+def select_du_lt(row_ptr, col, prob, R, k, seed, trace=False):
+    """Algorithm 2 on linear-threshold snapshots. Returns (seeds, gains, trace_or_None)."""
+    n, m, row_ptr, col, prob = _graph(row_ptr, col, prob)
+    seeds = np.zeros(k, dtype=np.uint32)
+    gains = np.zeros(k, dtype=np.uint64)
+    tr = np.zeros((k + 1, n), dtype=np.uint32) if trace else None
+    stats = np.zeros(NSTATS, dtype=np.uint64)
+    _check(_load().oracle_select_du_lt(n, m, _ptr(row_ptr), _ptr(col), _ptr(prob), R, k, seed,
+                                       _ptr(seeds), _ptr(gains), _ptr(tr) if trace else None,
+                                       _ptr(stats)), "select_du_lt")
+    return seeds, gains, tr
 
 
 def pair_ids(row_ptr, col, prob):

@@ -118,6 +118,54 @@ int oracle_live_bits(uint64_t m, const float *prob, uint32_t R, uint64_t seed,
     return oracle_live_bits_keyed(m, prob, R, seed, NULL, bits);
 }
 
+/*
+ * Linear threshold model in its live-edge form (the paper states that the
+ * method extends to it): in each snapshot every node keeps at most one of
+ * its in-arcs, arc e with probability b_e, none with the rest.
+ * Reading: b_e is prob[e]; the in-arcs of v, in increasing arc id, own
+ * consecutive sub-intervals of [0, 2^32) of lengths floor(b_e * 2^32) (the
+ * part of an interval past 2^32 is cut off); in snapshot r the node's draw,
+ * the top 32 bits of output r+1 of SplitMix64 seeded with output v+1 of
+ * SplitMix64(seed), keeps the arc whose sub-interval holds it.
+ * bits: arc-major as oracle_live_bits.
+ */
+int oracle_live_bits_lt(uint32_t n, uint64_t m, const uint64_t *row_ptr, const uint32_t *col,
+                        const float *prob, uint32_t R, uint64_t seed, uint64_t *bits)
+{
+    uint32_t W = (R + 63u) / 64u;
+    /* in-arcs of every node in increasing arc id (a stable counting sort) */
+    uint64_t *start = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    uint64_t *in_arc = (uint64_t *)malloc((m ? m : 1) * sizeof(uint64_t));
+    if (!start || !in_arc) { free(start); free(in_arc); return ORACLE_ENOMEM; }
+    for (uint64_t e = 0; e < m; e++) start[col[e] + 1]++;
+    for (uint32_t v = 0; v < n; v++) start[v + 1] += start[v];
+    uint64_t *cur = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
+    if (!cur) { free(start); free(in_arc); return ORACLE_ENOMEM; }
+    memcpy(cur, start, ((size_t)n + 1) * sizeof(uint64_t));
+    for (uint32_t u = 0; u < n; u++)
+        for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) in_arc[cur[col[e]]++] = e;
+    free(cur);
+    memset(bits, 0, (m ? m : 1) * W * sizeof(uint64_t));
+    for (uint32_t v = 0; v < n; v++) {
+        uint64_t key = sm64_output(seed, (uint64_t)v + 1u);
+        for (uint32_t r = 0; r < R; r++) {
+            uint64_t d = sm64_output(key, (uint64_t)r + 1u) >> 32;
+            uint64_t lo = 0;
+            for (uint64_t i = start[v]; i < start[v + 1]; i++) {
+                uint64_t e = in_arc[i];
+                uint64_t hi = lo + arc_threshold(prob[e]);
+                if (d >= lo && d < hi) {
+                    bits[e * W + r / 64u] |= 1ULL << (r % 64u);
+                    break;
+                }
+                lo = hi;
+            }
+        }
+    }
+    free(start); free(in_arc);
+    return ORACLE_OK;
+}
+
 /* ---------------- input checks ---------------- */
 
 static int check_graph(uint32_t n, uint64_t m, const uint64_t *row_ptr,
@@ -153,9 +201,10 @@ static void snaps_free(snaps_t *g)
     memset(g, 0, sizeof(*g));
 }
 
+/* lt = 1: linear-threshold snapshots (key_of unused) */
 static int snaps_build_keyed(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_ptr,
                              const uint32_t *col, const float *prob, uint32_t R,
-                             uint64_t seed, const uint32_t *key_of)
+                             uint64_t seed, const uint32_t *key_of, int lt)
 {
     uint32_t W = (R + 63u) / 64u;
     uint64_t stride = (uint64_t)n + 1u;
@@ -169,7 +218,13 @@ static int snaps_build_keyed(snaps_t *g, uint32_t n, uint64_t m, const uint64_t 
     if (!bits || !g->fbase || !g->rbase || !g->fptr || !g->rptr) {
         free(bits); snaps_free(g); return ORACLE_ENOMEM;
     }
-    oracle_live_bits_keyed(m, prob, R, seed, key_of, bits);
+    if (lt) {
+        if (oracle_live_bits_lt(n, m, row_ptr, col, prob, R, seed, bits)) {
+            free(bits); snaps_free(g); return ORACLE_ENOMEM;
+        }
+    } else {
+        oracle_live_bits_keyed(m, prob, R, seed, key_of, bits);
+    }
 
     /* count live out-arcs and in-arcs per (snapshot, node) */
     for (uint32_t u = 0; u < n; u++)
@@ -224,7 +279,7 @@ static int snaps_build(snaps_t *g, uint32_t n, uint64_t m, const uint64_t *row_p
                        const uint32_t *col, const float *prob, uint32_t R,
                        uint64_t seed)
 {
-    return snaps_build_keyed(g, n, m, row_ptr, col, prob, R, seed, NULL);
+    return snaps_build_keyed(g, n, m, row_ptr, col, prob, R, seed, NULL, 0);
 }
 
 /* ---------------- reachability inside one snapshot ---------------- */
@@ -400,7 +455,7 @@ int oracle_initial_gains(uint32_t n, uint64_t m, const uint64_t *row_ptr,
  */
 static int select_du_keyed(uint32_t n, uint64_t m, const uint64_t *row_ptr,
                            const uint32_t *col, const float *prob, uint32_t R,
-                           uint32_t k, uint64_t seed, const uint32_t *key_of,
+                           uint32_t k, uint64_t seed, const uint32_t *key_of, int lt,
                            uint32_t *seeds, uint64_t *gains, uint32_t *trace, uint64_t *stats)
 {
     int rc = check_graph(n, m, row_ptr, col, prob, R);
@@ -409,7 +464,7 @@ static int select_du_keyed(uint32_t n, uint64_t m, const uint64_t *row_ptr,
     uint64_t st[NSTATS] = {0};
     uint64_t nw = ((uint64_t)n + 63u) / 64u;
     snaps_t g;
-    if ((rc = snaps_build_keyed(&g, n, m, row_ptr, col, prob, R, seed, key_of))) return rc;
+    if ((rc = snaps_build_keyed(&g, n, m, row_ptr, col, prob, R, seed, key_of, lt))) return rc;
     st[4] = g.nlive;
     int64_t *s = (int64_t *)malloc((n ? n : 1) * sizeof(int64_t));
     uint8_t *sel = (uint8_t *)calloc(n ? n : 1, 1);
@@ -462,7 +517,17 @@ int oracle_select_du(uint32_t n, uint64_t m, const uint64_t *row_ptr,
                      uint32_t k, uint64_t seed, uint32_t *seeds, uint64_t *gains,
                      uint32_t *trace, uint64_t *stats)
 {
-    return select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, NULL, seeds, gains, trace,
+    return select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, NULL, 0, seeds, gains, trace,
+                           stats);
+}
+
+/* Algorithm 2 on linear-threshold snapshots (prob[e] = the weight b_e) */
+int oracle_select_du_lt(uint32_t n, uint64_t m, const uint64_t *row_ptr,
+                        const uint32_t *col, const float *prob, uint32_t R,
+                        uint32_t k, uint64_t seed, uint32_t *seeds, uint64_t *gains,
+                        uint32_t *trace, uint64_t *stats)
+{
+    return select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, NULL, 1, seeds, gains, trace,
                            stats);
 }
 
@@ -739,7 +804,7 @@ int oracle_select_du_pairs(uint32_t n, uint64_t m, const uint64_t *row_ptr,
     if (!pair) return ORACLE_ENOMEM;
     int rc = oracle_pair_ids(n, m, row_ptr, col, prob, pair);
     if (rc == ORACLE_OK)
-        rc = select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, pair, seeds, gains, trace,
+        rc = select_du_keyed(n, m, row_ptr, col, prob, R, k, seed, pair, 0, seeds, gains, trace,
                              stats);
     free(pair);
     return rc;

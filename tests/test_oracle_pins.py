@@ -502,6 +502,105 @@ def test_components_closed_forms():
     assert s.tolist() == [0, 1, 2] and g.tolist() == [R] * 3
 
 
+# ---------------------------------------------------------------- linear threshold
+
+
+def _py_lt_choice(seed, v, r, in_arcs, prob):
+    # independent big-integer reading of the linear-threshold rule: the
+    # node's draw picks the in-arc (by increasing arc id) whose sub-interval
+    # of [0, 2^32) holds it; None when it falls past the weights' sum
+    def mix(z):
+        z &= MASK64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    gamma = 0x9E3779B97F4A7C15
+    key = mix(seed + (v + 1) * gamma)
+    d = mix(key + (r + 1) * gamma) >> 32
+    lo = 0
+    for e in sorted(in_arcs):
+        hi = lo + math.floor(float(np.float32(prob[e])) * 2.0 ** 32)
+        if lo <= d < hi:
+            return e
+        lo = hi
+    return None
+
+
+def _in_arcs(row_ptr, col):
+    n = len(row_ptr) - 1
+    ins = [[] for _ in range(n)]
+    for u in range(n):
+        for e in range(int(row_ptr[u]), int(row_ptr[u + 1])):
+            ins[int(col[e])].append(e)
+    return ins
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_lt_live_bits_follow_the_rule(case):
+    rng = np.random.default_rng(900 + case)
+    n = 12
+    row_ptr, col, _ = _random_graph(rng, n, 40)
+    # weights: per head, a random split of a total in [0.3, 1.1] (over 1 is cut)
+    ins = _in_arcs(row_ptr, col)
+    prob = np.zeros(len(col), np.float32)
+    for v in range(n):
+        if ins[v]:
+            w = rng.dirichlet(np.ones(len(ins[v]))) * rng.uniform(0.3, 1.1)
+            prob[ins[v]] = w.astype(np.float32)
+    R, seed = 100, 17 + case
+    bits = oracle.live_bits_lt(row_ptr, col, prob, R, seed)
+    for v in range(n):
+        for r in range(R):
+            live = [e for e in ins[v] if (int(bits[e, r // 64]) >> (r % 64)) & 1]
+            want = _py_lt_choice(seed, v, r, ins[v], prob)
+            assert live == ([] if want is None else [want])
+
+
+def test_lt_frequencies_and_closed_forms():
+    # one head with three in-arcs of weights 0.5, 0.25, 0.25: exactly one is
+    # kept in every snapshot, each about as often as its weight
+    row_ptr = np.array([0, 1, 2, 3, 3], np.uint64)
+    col = np.array([3, 3, 3], np.uint32)
+    prob = np.array([0.5, 0.25, 0.25], np.float32)
+    R = 4096
+    bits = oracle.live_bits_lt(row_ptr, col, prob, R, 5)
+    cnt = [sum(bin(int(x)).count("1") for x in bits[e]) for e in range(3)]
+    assert sum(cnt) == R
+    for c, p in zip(cnt, prob):
+        assert abs(c - p * R) < 5 * math.sqrt(R * p * (1 - p))
+    # weight 1 on a path: every snapshot is the path; weight 0: no arc
+    row_ptr, col, prob = _csr(6, [(i, i + 1) for i in range(5)], 1.0)
+    s, g, _ = oracle.select_du_lt(row_ptr, col, prob, 70, 3, 1)
+    assert s.tolist() == [0, 1, 2] and g.tolist() == [6 * 70, 0, 0]
+    row_ptr, col, prob = _csr(6, [(i, i + 1) for i in range(5)], 0.0)
+    s, g, _ = oracle.select_du_lt(row_ptr, col, prob, 70, 3, 1)
+    assert g.tolist() == [70] * 3
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_lt_greedy_equals_bruteforce(case):
+    rng = np.random.default_rng(950 + case)
+    n = int(rng.integers(4, 10))
+    row_ptr, col, _ = _random_graph(rng, n, int(rng.integers(n, 3 * n)))
+    ins = _in_arcs(row_ptr, col)
+    prob = np.zeros(len(col), np.float32)
+    for v in range(n):
+        if ins[v]:
+            prob[ins[v]] = np.float32(1.0 / len(ins[v]))   # weighted-cascade weights
+    R, k, seed = int(rng.choice([1, 30, 64, 70])), int(rng.integers(1, n + 1)), int(rng.integers(1, 50))
+    adj = [[[] for _ in range(n)] for _ in range(R)]
+    tails = np.repeat(np.arange(n), np.diff(row_ptr.astype(np.int64)))
+    for v in range(n):
+        for r in range(R):
+            e = _py_lt_choice(seed, v, r, ins[v], prob)
+            if e is not None:
+                adj[r][int(tails[e])].append(v)
+    S_ref, g_ref = _greedy_by_definition(adj, n, k)
+    s, g, _ = oracle.select_du_lt(row_ptr, col, prob, R, k, seed)
+    assert s.tolist() == S_ref and g.tolist() == g_ref
+
+
 # ---------------------------------------------------------------- semantics
 
 
