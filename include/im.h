@@ -105,10 +105,21 @@ int im_workspace_destroy(im_workspace *ws);
  *     im_pair_ids) instead of one per stored arc, for the single-graph calls
  *     (im_snapshot_masks, im_initial_gains, im_select, im_select_lazy,
  *     im_autotune) on a symmetric CSR; the results are then those of
- *     im_select_undirected. Default 0. Not for batches or plans. */
+ *     im_select_undirected. Default 0. Not for batches or plans.
+ *   IM_OPT_LIVE_EDGE: the snapshot model of the same single-graph calls.
+ *     0 (default): independent cascade, one coin per stored arc. 1: linear
+ *     threshold in live-edge form (the paper notes the method extends to
+ *     it): prob[e] is the weight b_e of arc e; per snapshot every node v
+ *     keeps at most one in-arc: its in-arcs, by increasing arc id, own
+ *     consecutive sub-intervals of [0, 2^32) of lengths floor(b_e * 2^32)
+ *     (a part past 2^32 is never drawn), and the top 32 bits of output r+1
+ *     of SplitMix64 seeded with output v+1 of SplitMix64(seed) keep the arc
+ *     whose sub-interval holds them in snapshot r. Not for batches, plans,
+ *     pair coins or im_spread. */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
-       IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10 };
+       IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10,
+       IM_OPT_LIVE_EDGE = 11 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the

@@ -39,6 +39,7 @@ IM_OPT_SPARSE_LISTS = 7
 IM_OPT_FWD_GROUPS = 8
 IM_OPT_LEARNED_POLICY = 9
 IM_OPT_PAIR_COINS = 10
+IM_OPT_LIVE_EDGE = 11
 
 
 class ImGraph(ctypes.Structure):

@@ -121,6 +121,11 @@ class Workspace:
         """One coin per undirected pair (symmetric CSR) for single-graph calls."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_PAIR_COINS, int(bool(on))))
 
+    def set_live_edge(self, model):
+        """Snapshot model of single-graph calls: 0 independent cascade, 1 linear
+        threshold (prob = in-arc weights)."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LIVE_EDGE, int(model)))
+
     def profile_enable(self, phases=None):
         """Time the named phases (None: all) with HIP events from now on."""
         names = N.PHASES if phases is None else phases

@@ -441,26 +441,31 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
 }
 
 // Per-snapshot live lists of the nodes below the hub threshold (degree >= 2;
-// see SparseLists). A workgroup takes chunks of SPB (node, word) pairs: its
-// four wavefronts count each pair's live heads per snapshot bit, the chunk
-// reserves its range of adj with one atomic, and the pairs are filled. A
-// pair whose lists do not fit the capacity, or would hold more than 65535
-// heads, keeps base = IM_EMPTY and is expanded through the masks.
-constexpr int SPB = 64;
+// see SparseLists). One thread per (node, word) pair: a bit-sliced counter
+// (eight 64-bit planes, one 8-bit count per snapshot bit) adds up the pair's
+// mask words, which gives the 65 cumulative counts; a workgroup reserves its
+// pairs' range of adj with one atomic; then the heads are placed, each at its
+// bit's start plus the count of earlier arcs live in that bit. Pairs of
+// degree >= SP_MAXDEG (the counter's range), and pairs whose lists do not fit
+// the capacity, keep base = IM_EMPTY and are expanded through the masks.
+constexpr uint32_t SP_MAXDEG = 256;
 
-__device__ __forceinline__ void sparse_count(const uint64_t *mw, uint32_t e0, uint32_t e1,
-                                             uint32_t *cnt, int lane)
+__device__ __forceinline__ void vc_add(uint64_t (&c)[8], uint64_t m)
 {
-    cnt[lane] = 0;
-    __syncthreads();
-    for (uint32_t e = e0 + lane; e < e1; e += 64) {
-        uint64_t b = mw[e];
-        while (b) {
-            atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
-            b &= b - 1;
-        }
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint64_t t = c[i] & m;
+        c[i] ^= m;
+        m = t;
     }
-    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t vc_get(const uint64_t (&c)[8], uint32_t b)
+{
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) v |= (uint32_t)((c[i] >> b) & 1ull) << i;
+    return v;
 }
 
 __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const uint32_t *col,
@@ -469,74 +474,67 @@ __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const
                                                       uint16_t *cum, uint32_t *adj,
                                                       unsigned long long *alloc, uint64_t cap)
 {
-    __shared__ uint32_t cnt[4][64];
-    __shared__ uint32_t tot[SPB], off[SPB];
-    __shared__ unsigned long long cbase;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ uint32_t s_w[256 / 64 + 1];
+    __shared__ unsigned long long s_base;
+    __shared__ __attribute__((aligned(16))) uint16_t s_cum[256 * 65];   // the chunk's counts, written out coalesced
     const uint64_t P = (uint64_t)W * n;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * SPB; c0 < P; c0 += (uint64_t)gridDim.x * SPB) {
-        // count: wavefront wv takes pairs wv, wv+4, ... of the chunk (uniform trip count)
-        for (int q = wv; q < SPB; q += 4) {
-            const uint64_t p = c0 + q;
-            uint32_t w = 0, e0 = 0, e1 = 0;
-            bool elig = false;
-            if (p < P) {
-                w = (uint32_t)(p / n);
-                const uint32_t x = (uint32_t)(p - (uint64_t)w * n);
-                e0 = row[x];
-                e1 = row[x + 1];
-                const uint32_t deg = e1 - e0;
-                elig = deg >= 2 && (hub_deg == 0 || deg < hub_deg);
+    for (uint64_t p0 = (uint64_t)blockIdx.x * 256; p0 < P; p0 += (uint64_t)gridDim.x * 256) {
+        const uint64_t p = p0 + threadIdx.x;
+        uint32_t w = 0, e0 = 0, e1 = 0, total = 0;
+        bool elig = false;
+        if (p < P) {
+            w = (uint32_t)(p / n);
+            const uint32_t x = (uint32_t)(p - (uint64_t)w * n);
+            e0 = row[x];
+            e1 = row[x + 1];
+            const uint32_t deg = e1 - e0;
+            elig = deg >= 2 && deg < SP_MAXDEG && (hub_deg == 0 || deg < hub_deg);
+        }
+        const uint64_t *mw = mask + (uint64_t)w * m;
+        uint16_t *cp = s_cum + threadIdx.x * 65;
+        if (elig) {
+            uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (uint32_t e = e0; e < e1; e++) vc_add(c, mw[e]);
+            for (uint32_t b = 0; b < 64; b++) {
+                cp[b] = (uint16_t)total;
+                total += vc_get(c, b);
             }
-            if (!elig) e1 = e0;
-            sparse_count(mask + (uint64_t)w * m, e0, e1, cnt[wv], lane);
-            const uint32_t c = cnt[wv][lane];
-            const uint32_t incl = wave_incl_scan(c);
-            const uint32_t total = __shfl(incl, 63, 64);
-            const bool keep = elig && total <= 0xFFFFu;
-            if (keep) {
-                cum[p * 65 + lane] = (uint16_t)(incl - c);
-                if (lane == 63) cum[p * 65 + 64] = (uint16_t)total;
-            }
-            if (lane == 0) tot[q] = keep ? total : IM_EMPTY;
+            cp[64] = (uint16_t)total;
+        } else {
+            for (uint32_t b = 0; b < 65; b++) cp[b] = 0;
         }
         __syncthreads();
-        if (wv == 0) {
-            const uint32_t t = tot[lane] == IM_EMPTY ? 0u : tot[lane];
-            const uint32_t incl = wave_incl_scan(t);
-            off[lane] = incl - t;
-            if (lane == 63) cbase = incl ? atomicAdd(alloc, (unsigned long long)incl) : 0ull;
-        }
-        __syncthreads();
-        // fill: recount each pair's bits into cursors, then place its heads
-        for (int q = wv; q < SPB; q += 4) {
-            const uint64_t p = c0 + q;
-            uint32_t w = 0, e0 = 0, e1 = 0;
-            uint32_t b0 = IM_EMPTY;
-            if (p < P && tot[q] != IM_EMPTY && cbase + off[q] + tot[q] <= cap) {
-                w = (uint32_t)(p / n);
-                const uint32_t x = (uint32_t)(p - (uint64_t)w * n);
-                e0 = row[x];
-                e1 = row[x + 1];
-                b0 = (uint32_t)(cbase + off[q]);
+        {
+            // 256 pairs x 65 counts = 8320 aligned 32-bit words (p0 is a multiple of 256)
+            const uint64_t npair = min((uint64_t)256, P - p0);
+            const uint32_t nwords = (uint32_t)(npair * 65 + 1) / 2;
+            const uint32_t *src = (const uint32_t *)s_cum;
+            uint32_t *dst = (uint32_t *)(cum + p0 * 65);
+            for (uint32_t j = threadIdx.x; j < nwords; j += 256) {
+                if (2 * j + 1 < npair * 65) dst[j] = src[j];
+                else cum[p0 * 65 + 2 * j] = s_cum[2 * j];   // odd tail: one u16
             }
-            if (p < P && lane == 0) base[p] = b0;
-            sparse_count(mask + (uint64_t)w * m, e0, e1, cnt[wv], lane);
-            const uint32_t c = cnt[wv][lane];
-            cnt[wv][lane] = wave_incl_scan(c) - c;   // each bit's list from its start
-            __syncthreads();
-            const uint64_t *mw = mask + (uint64_t)w * m;
-            for (uint32_t e = e0 + lane; e < e1; e += 64) {
-                uint64_t b = mw[e];
+        }
+        uint32_t blk;
+        const uint32_t ex = block_excl_scan<256>(elig ? total : 0u, s_w, &blk);
+        if (threadIdx.x == 0) s_base = blk ? atomicAdd(alloc, (unsigned long long)blk) : 0ull;
+        __syncthreads();
+        const unsigned long long b0 = s_base + ex;
+        const bool fits = elig && b0 + total <= cap;
+        if (p < P) base[p] = fits ? (uint32_t)b0 : IM_EMPTY;
+        if (fits && total) {
+            uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (uint32_t e = e0; e < e1; e++) {
+                const uint64_t mb = mw[e];
                 const uint32_t v = col[e];
-                while (b) {
-                    const uint32_t pos = atomicAdd(&cnt[wv][__ffsll((unsigned long long)b) - 1], 1u);
-                    adj[b0 + pos] = v;
-                    b &= b - 1;
+                for (uint64_t t = mb; t; t &= t - 1) {
+                    const uint32_t b = (uint32_t)__ffsll((unsigned long long)t) - 1;
+                    adj[b0 + cp[b] + vc_get(c, b)] = v;
                 }
+                vc_add(c, mb);
             }
-            __syncthreads();
         }
+        __syncthreads();   // s_base is rewritten by the next chunk
     }
 }
 
@@ -1171,6 +1169,12 @@ struct im_workspace {
     uint32_t *v_row32 = nullptr;
     uint64_t *v_mask = nullptr, *v_reach = nullptr, *v_pend = nullptr, *v_cov = nullptr;
     uint32_t *v_qa = nullptr, *v_qb = nullptr, *v_vis = nullptr;
+    // linear-threshold snapshots
+    int live_edge = 0;                   // 0: independent cascade, 1: linear threshold
+    uint64_t *lt_start = nullptr;        // [m] start of each in-arc's draw interval
+    uint32_t *lt_task = nullptr;         // [n+1] prefix of the large rows' chunk counts
+    uint64_t cap_lt_m = 0;
+    uint32_t cap_lt_n = 0;
     // undirected graphs: one coin per pair (directed engines), component method state
     int pair_coins = 0;
     uint32_t *pair = nullptr;
@@ -1303,6 +1307,7 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     und_state_free(ws->und);
     ws->und = nullptr;
     dfree(ws->pair);
+    dfree(ws->lt_start); dfree(ws->lt_task);
     dfree(ws->v_row32); dfree(ws->v_mask); dfree(ws->v_reach); dfree(ws->v_pend); dfree(ws->v_cov);
     dfree(ws->v_qa); dfree(ws->v_qb); dfree(ws->v_vis);
     dfree(ws->stats); dfree(ws->err);
@@ -1492,6 +1497,124 @@ static void build_reverse(const im_graph *g, im_workspace *ws, hipStream_t s)
                                                     ws->in_col, ws->in2out);
 }
 
+// ---------------------------------------------------------------------------
+// A2, linear-threshold snapshots in live-edge form: per snapshot every node
+// keeps at most one of its in-arcs. The in-arcs of v, by increasing arc id,
+// own consecutive sub-intervals of [0, 2^32) of lengths t_e = floor(b_e 2^32)
+// (b_e = prob[e]; a part past 2^32 is never drawn); the node's draw for
+// snapshot r, the top 32 bits of output r+1 of SplitMix64 seeded with output
+// v+1 of SplitMix64(seed), keeps the arc whose sub-interval holds it.
+// The reverse CSR lists in-arcs in no particular order, so each in-arc's
+// interval start is the sum of t over the in-arcs of its row with a smaller
+// arc id: one thread per row for rows of up to LT_SMALL in-arcs, one
+// workgroup per LT_SMALL-entry chunk (the row streamed through LDS) above.
+// ---------------------------------------------------------------------------
+constexpr uint32_t LT_SMALL = 256;
+
+__device__ __forceinline__ uint64_t lt_len(const float *prob, uint32_t e)
+{
+    return (uint64_t)((double)prob[e] * 4294967296.0);
+}
+
+__global__ __launch_bounds__(256) void k_lt_start_small(const uint32_t *in_row,
+                                                        const uint32_t *in2out, const float *prob,
+                                                        uint32_t n, uint64_t *start,
+                                                        uint32_t *chunks)
+{
+    for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+        const uint32_t a = in_row[v], b = in_row[v + 1];
+        chunks[v] = b - a > LT_SMALL ? (b - a + LT_SMALL - 1) / LT_SMALL : 0u;
+        if (b - a > LT_SMALL) continue;
+        for (uint32_t j = a; j < b; j++) {
+            const uint32_t id = in2out[j];
+            uint64_t acc = 0;
+            for (uint32_t i = a; i < b; i++) {
+                const uint32_t o = in2out[i];
+                if (o < id) acc += lt_len(prob, o);
+            }
+            start[j] = acc;
+        }
+    }
+}
+
+// chunk tasks of the large rows: task t belongs to the row v with
+// pre[v] <= t < pre[v+1] (pre: exclusive prefix of the chunk counts, pre[n] = total)
+__global__ __launch_bounds__(LT_SMALL) void k_lt_start_large(const uint32_t *in_row,
+                                                             const uint32_t *in2out,
+                                                             const float *prob, uint32_t n,
+                                                             const uint32_t *pre, uint64_t *start)
+{
+    __shared__ uint32_t s_id[LT_SMALL];
+    __shared__ uint64_t s_len[LT_SMALL];
+    const uint32_t T = pre[n];
+    for (uint32_t t = blockIdx.x; t < T; t += gridDim.x) {
+        uint32_t lo = 0, hi = n;   // largest v with pre[v] <= t
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        const uint32_t v = lo, a = in_row[v], b = in_row[v + 1];
+        const uint32_t j = a + (t - pre[v]) * LT_SMALL + threadIdx.x;
+        const uint32_t id = j < b ? in2out[j] : 0xFFFFFFFFu;
+        uint64_t acc = 0;
+        for (uint32_t c = a; c < b; c += LT_SMALL) {
+            const uint32_t i = c + threadIdx.x;
+            s_id[threadIdx.x] = i < b ? in2out[i] : 0xFFFFFFFFu;
+            s_len[threadIdx.x] = i < b ? lt_len(prob, in2out[i]) : 0ull;
+            __syncthreads();
+            const uint32_t lim = min(LT_SMALL, b - c);
+            for (uint32_t q = 0; q < lim; q++)
+                if (s_id[q] < id) acc += s_len[q];
+            __syncthreads();
+        }
+        if (j < b) start[j] = acc;
+    }
+}
+
+// one wavefront per (node, word): lane r draws snapshot 64w + r, then every
+// in-arc of the node gets the snapshots whose draw falls in its interval;
+// word-major masks for both directions are written directly
+__global__ __launch_bounds__(256) void k_lt_masks(const uint32_t *in_row, const uint32_t *in2out,
+                                                  const float *prob, const uint64_t *start,
+                                                  uint32_t n, uint64_t m, uint32_t R, uint64_t seed,
+                                                  uint64_t *mask_out, uint64_t *mask_in)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t waves = (uint64_t)gridDim.x * 4;
+    const uint32_t W = (R + 63) / 64;
+    for (uint64_t p = blockIdx.x * 4ull + (threadIdx.x >> 6); p < (uint64_t)W * n; p += waves) {
+        const uint32_t w = (uint32_t)(p / n), v = (uint32_t)(p - (uint64_t)w * n);
+        const uint32_t a = in_row[v], b = in_row[v + 1];
+        if (a == b) continue;   // uniform over the wavefront
+        const uint32_t r = w * 64 + lane;
+        uint64_t d = ~0ull;   // beyond every interval (an interval may pass 2^32)
+        if (r < R) {
+            const uint64_t key = sm64_finalise(seed + ((uint64_t)v + 1ull) * IM_GOLDEN);
+            d = sm64_finalise(key + ((uint64_t)r + 1ull) * IM_GOLDEN) >> 32;
+        }
+        for (uint32_t base = a; base < b; base += 64) {
+            const uint32_t j = base + lane;
+            uint64_t lo = 0, len = 0;
+            uint32_t e = 0;
+            if (j < b) {
+                e = in2out[j];
+                lo = start[j];
+                len = lt_len(prob, e);
+            }
+            uint64_t bits = 0;
+            for (int q = 0; q < 64; q++) {
+                const uint64_t dq = __shfl(d, q, 64);
+                bits |= (uint64_t)(dq >= lo && dq - lo < len) << q;
+            }
+            bits &= im_valid_bits(R, w);
+            if (j < b) {
+                mask_in[(uint64_t)w * m + j] = bits;
+                mask_out[(uint64_t)w * m + e] = bits;
+            }
+        }
+    }
+}
+
 // A2: masks for both directions
 static void build_masks(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws,
                         uint64_t *mask_out, bool reverse, hipStream_t s)
@@ -1499,6 +1622,19 @@ static void build_masks(const im_graph *g, uint32_t R, uint64_t seed, im_workspa
     uint32_t W = (R + 63) / 64;
     uint64_t m = g->m;
     if (m == 0) return;
+    if (ws->live_edge == 1) {
+        // linear threshold (the reverse CSR is built): interval starts, then masks
+        PhaseTimer pt(ws, IM_PH_MASK_GEN, s);
+        const uint32_t n = g->n;
+        k_lt_start_small<<<grid_for(n, 256), 256, 0, s>>>(ws->in_row, ws->in2out, g->prob, n,
+                                                          ws->lt_start, ws->cnt);
+        exclusive_scan(ws->cnt, ws->lt_task, (uint64_t)n + 1, ws->scan_sums, s);
+        k_lt_start_large<<<2048, LT_SMALL, 0, s>>>(ws->in_row, ws->in2out, g->prob, n,
+                                                   ws->lt_task, ws->lt_start);
+        k_lt_masks<<<grid_for((uint64_t)n * W, 4, 16384), 256, 0, s>>>(
+            ws->in_row, ws->in2out, g->prob, ws->lt_start, n, m, R, seed, mask_out, ws->mask_in);
+        return;
+    }
     dim3 grid((unsigned)((m + 255) / 256), W);
     {
         PhaseTimer pt(ws, IM_PH_MASK_GEN, s);
@@ -1537,7 +1673,7 @@ static void build_sparse(int d, const uint32_t *row, const uint32_t *col, const 
     if (!ws->sparse || n == 0) return;
     fill<unsigned long long>(ws->sp_alloc + d, 1, 0ull, s);
     const uint64_t P = (uint64_t)W * n;
-    const unsigned grid = (unsigned)std::min<uint64_t>((P + SPB - 1) / SPB, 8192);
+    const unsigned grid = (unsigned)std::min<uint64_t>((P + 255) / 256, 8192);
     k_sparse_build<<<grid, 256, 0, s>>>(row, col, mask, m, n, W, ws->hub_deg, ws->sp_base[d],
                                         ws->sp_cum[d], ws->sp_adj[d], ws->sp_alloc + d, ws->sp_cap);
 }
@@ -1716,6 +1852,18 @@ static int check_and_reserve(const im_graph *g, uint32_t R, uint32_t k, im_works
     int rc;
     if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, k, g->n))) return rc;
     if ((rc = validate(g, ws, s, ws->row32))) return rc;
+    if (ws->live_edge == 1) {
+        if (ws->batch.count > 1) return im_fail(IM_EINVAL, "linear-threshold snapshots apply to single graphs only");
+        if (ws->pair_coins) return im_fail(IM_EINVAL, "pair coins and linear-threshold snapshots exclude each other");
+        if (g->m > ws->cap_lt_m || !ws->lt_start) {
+            if ((rc = dalloc(&ws->lt_start, g->m))) return rc;
+            ws->cap_lt_m = g->m;
+        }
+        if (g->n + 1 > ws->cap_lt_n || !ws->lt_task) {
+            if ((rc = dalloc(&ws->lt_task, (uint64_t)g->n + 1))) return rc;
+            ws->cap_lt_n = g->n + 1;
+        }
+    }
     if (ws->pair_coins) {
         // the pair of every arc (host-synchronous; before any capture)
         if (ws->batch.count > 1) return im_fail(IM_EINVAL, "pair coins apply to single graphs only");
@@ -2737,6 +2885,8 @@ extern "C" int im_spread(const im_graph *g, uint32_t R, uint64_t seed, const uin
     if (R == 0 || R > IM_SPREAD_R_MAX)
         return im_fail(IM_EINVAL, "R = %u must be in [1, %u]", R, IM_SPREAD_R_MAX);
     if (nS && !S) return im_fail(IM_EINVAL, "null seed array");
+    if (ws->live_edge || ws->pair_coins)
+        return im_fail(IM_EINVAL, "the spread evaluator draws one coin per stored arc");
     hipStream_t s = (hipStream_t)stream;
     const uint32_t n = g->n, W = (R + 63) / 64;
     const uint64_t m = g->m;
@@ -2849,8 +2999,8 @@ extern "C" int im_snapshot_masks(const im_graph *g, uint32_t R, uint64_t seed, u
     if ((rc = check_args(g, R))) return rc;
     if (!ws || (g->m && !mask_out)) return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, 0, g->n))) return rc;
-    if ((rc = validate(g, ws, s, nullptr))) return rc;
+    if ((rc = check_and_reserve(g, R, 0, ws, s))) return rc;
+    if (ws->live_edge == 1) build_reverse(g, ws, s);   // linear threshold draws per in-row
     build_masks(g, R, seed, ws, mask_out, false, s);
     HIPCHK(hipGetLastError());
     ws->last_stream = s;
@@ -3072,6 +3222,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "pair coins must be 0 or 1");
         ws->pair_coins = (int)value;
         return IM_OK;
+    case IM_OPT_LIVE_EDGE:
+        if (value != 0 && value != 1) return im_fail(IM_EINVAL, "live-edge model must be 0 or 1");
+        ws->live_edge = (int)value;
+        return IM_OK;
     default:
         return im_fail(IM_EINVAL, "unknown option %d", option);
     }
@@ -3136,6 +3290,8 @@ static int batch_setup(const im_instance *inst, uint32_t count, bool need_out, i
     int rc;
     uint64_t N = 0, M = 0, K = 0;
     uint32_t Rmax = 0, kmax = 0, nmax = 0;
+    if (ws->live_edge || ws->pair_coins)
+        return im_fail(IM_EINVAL, "batches draw one coin per stored arc (independent cascade)");
     for (uint32_t i = 0; i < count; i++) {
         if ((rc = check_args(&inst[i].g, inst[i].R)))
             return im_fail(rc, "instance %u: %s", i, g_err.c_str());

@@ -140,6 +140,13 @@ WORKLOADS = {
     # scale, large enough that every snapshot has a giant component
     "million_undirected_uic": dict(n=1000000, m=10000000, gamma=2.1, graph_seed=5,
                                    directed=False, p=0.01, R=256, k=50, seed=1),
+    # linear threshold with weighted-cascade weights b(u,v) = 1/indeg(v) (every
+    # node's in-weights sum to 1): the NetHEPT-shaped graph, R=100, k=50 ...
+    "nethept_lt": dict(n=15000, m=59000, gamma=2.5, graph_seed=2, directed=False, p=None,
+                       R=100, k=50, seed=1, model="lt"),
+    # ... and the million-node directed graph, R=256, k=50
+    "million_lt": dict(n=1000000, m=10000000, gamma=2.1, graph_seed=3, directed=True, p=None,
+                       R=256, k=50, seed=1, model="lt"),
 }
 
 
