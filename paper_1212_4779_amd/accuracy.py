@@ -21,6 +21,7 @@ Usage: python -m paper_1212_4779_amd.accuracy [--workload nethept_uic] [--runs 1
 import argparse
 import json
 import math
+import sys
 import time
 from collections import Counter
 
@@ -29,7 +30,8 @@ def entropy(solutions):
     """H = -sum p log p over the distinct solutions (order-free sets)."""
     counts = Counter(frozenset(s) for s in solutions)
     total = sum(counts.values())
-    return -sum(c / total * math.log(c / total) for c in counts.values())
+    h = -sum(c / total * math.log(c / total) for c in counts.values())
+    return h if h > 0.0 else 0.0
 
 
 def relative_differences(ref_spread, spreads):
@@ -93,7 +95,8 @@ def main():
     g = gg.workload_graph(args.workload)
     d = api.Graph.from_numpy(g.row_ptr, g.col, g.prob)
     res = study(d, [int(x) for x in args.R.split(",")], args.k, args.runs, args.R_eval,
-                args.eval_seed, R_ref=args.R_ref)
+                args.eval_seed, R_ref=args.R_ref,
+                log=lambda msg: print(msg, file=sys.stderr, flush=True))
     res["workload"] = args.workload
     print(json.dumps(res))
 

@@ -95,7 +95,7 @@ def test_lt_selection_matches_oracle(im, case):
     assert ls.cpu().tolist() == s_ref.tolist() and lg.cpu().tolist() == g_ref.tolist()
 
 
-@pytest.mark.parametrize("name", ["nethept_lt"])
+@pytest.mark.parametrize("name", ["nethept_lt", "million_lt"])
 def test_lt_workload_golden(im, name):
     path = os.path.join(GOLDEN, f"{name}.json")
     if not os.path.exists(path):
