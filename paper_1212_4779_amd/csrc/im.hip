@@ -494,7 +494,12 @@ __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const
         uint16_t *cp = s_cum + threadIdx.x * 65;
         if (elig) {
             uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (uint32_t e = e0; e < e1; e++) vc_add(c, mw[e]);
+            uint32_t e = e0;
+            for (; e + 4 <= e1; e += 4) {   // four independent loads in flight
+                const uint64_t m0 = mw[e], m1 = mw[e + 1], m2 = mw[e + 2], m3 = mw[e + 3];
+                vc_add(c, m0); vc_add(c, m1); vc_add(c, m2); vc_add(c, m3);
+            }
+            for (; e < e1; e++) vc_add(c, mw[e]);
             for (uint32_t b = 0; b < 64; b++) {
                 cp[b] = (uint16_t)total;
                 total += vc_get(c, b);
@@ -1267,12 +1272,12 @@ extern "C" int im_workspace_create(im_workspace **out)
         ws->eval_grid = (unsigned)be * (unsigned)ws->num_cu;
     }
     int rc;
-    if ((rc = dalloc(&ws->stats, ST_COUNT))) { delete ws; return rc; }
+    if ((rc = dalloc(&ws->stats, ST_COUNT * ST_STRIPES))) { delete ws; return rc; }
     if ((rc = dalloc(&ws->err, 1))) { delete ws; return rc; }
     HIPCHK(hipHostMalloc((void **)&ws->host_err, sizeof(uint32_t), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&ws->host_stats, ST_COUNT * sizeof(unsigned long long),
+    HIPCHK(hipHostMalloc((void **)&ws->host_stats, ST_COUNT * ST_STRIPES * sizeof(unsigned long long),
                          hipHostMallocDefault));
-    HIPCHK(hipMemset(ws->stats, 0, ST_COUNT * sizeof(unsigned long long)));
+    HIPCHK(hipMemset(ws->stats, 0, ST_COUNT * ST_STRIPES * sizeof(unsigned long long)));
     *out = ws;
     return IM_OK;
 }
@@ -1883,7 +1888,7 @@ static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_
                            im_workspace *ws, hipStream_t s)
 {
     uint32_t n = g->n, W = (R + 63) / 64;
-    fill<unsigned long long>(ws->stats, ST_COUNT, 0ull, s);
+    fill<unsigned long long>(ws->stats, (uint64_t)ST_COUNT * ST_STRIPES, 0ull, s);
     fill<uint32_t>(ws->ctrs, (uint64_t)(k + 1) * PH_CTRS, 0u, s);
     fill<unsigned long long>(ws->keys, (uint64_t)(k + 1) * ws->batch.count, 0ull, s);
     fill<uint32_t>(ws->fctr, (uint64_t)(k ? k : 1) * FWD_CTRS, 0u, s);
@@ -2965,8 +2970,16 @@ extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
 {
     if (!ws || !out) return im_fail(IM_EINVAL, "null argument");
     HIPCHK(hipStreamSynchronize(ws->last_stream));
-    HIPCHK(hipMemcpy(ws->host_stats, ws->stats, ST_COUNT * sizeof(unsigned long long),
+    HIPCHK(hipMemcpy(ws->host_stats, ws->stats, ST_COUNT * ST_STRIPES * sizeof(unsigned long long),
                      hipMemcpyDeviceToHost));
+    // fold the copies into copy 0: sums, maxima for the level counters
+    unsigned long long *hs = ws->host_stats;
+    for (int c = 1; c < ST_STRIPES; c++)
+        for (int i = 0; i < ST_COUNT; i++) {
+            const unsigned long long v = hs[c * ST_COUNT + i];
+            if (i >= ST_MAXLV_BASE && i < ST_MAXLV_BASE + 9) hs[i] = std::max(hs[i], v);
+            else hs[i] += v;
+        }
     memset(out, 0, sizeof(*out));
     const unsigned long long *h = ws->host_stats;
     out->trav_init = h[ST_TRAV_INIT];

@@ -43,6 +43,22 @@ __host__ __device__ constexpr int st_tier(int pass, int tier, int field)
     return ST_TIER_BASE + pass * 12 + tier * 4 + field;
 }
 
+// The counters are kept in ST_STRIPES copies of ST_COUNT slots; the engines,
+// whose every workgroup adds its totals at the end, spread those atomics over
+// the copies by workgroup (the reader sums the copies, or takes their maximum
+// for the ST_MAXLV slots). Other kernels add to copy 0.
+constexpr int ST_STRIPES = 32;
+
+__device__ __forceinline__ void stat_add(unsigned long long *st, int idx, unsigned long long v)
+{
+    atomicAdd(&st[(blockIdx.x % ST_STRIPES) * ST_COUNT + idx], v);
+}
+
+__device__ __forceinline__ void stat_max(unsigned long long *st, int idx, unsigned long long v)
+{
+    atomicMax(&st[(blockIdx.x % ST_STRIPES) * ST_COUNT + idx], v);
+}
+
 // Per-snapshot adjacency of heavy nodes (degree >= the hub threshold), for
 // expanding them with a sparse delta: for hub index h and word w, the heads of
 // the arcs live in snapshot 64w+b are adj[off[(h*W+w)*65+b] .. off[(h*W+w)*65+b+1]).
@@ -350,7 +366,7 @@ struct LdsState {
     uint32_t s_task[T], s_src[T], s_word[T], s_cnt[T], s_next[T], s_ovf[T], s_act[T], s_new[T];
     uint32_t wpre[65];
     HubBatch<NT, (NT == 64 ? 2 : 16)> H;
-    uint32_t nf, nn, tnext, tend, ntasks, done;
+    uint32_t nf, nn, tnext, tend, ntasks, done, chunk, snext;
 };
 
 // insert v into slot s's table (if absent) and OR in `bits`; push the entry
@@ -420,7 +436,6 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
     static_assert(LIM < CS, "LIM must leave free table entries");
     constexpr int LOG_CS = __builtin_ctz(CS);
     constexpr int N = T * CS;
-    constexpr uint32_t CHUNK = 8;
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     __shared__ LdsState<NT, T, CS> L;
     const int tid = threadIdx.x;
@@ -435,6 +450,14 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
         L.nf = 0; L.nn = 0; L.tnext = 0; L.tend = 0; L.done = 0; L.H.n = 0;
         if (MODE == MODE_DEC) fill_wpre(a, L.wpre);
         L.ntasks = a.in_q ? *a.in_n : (MODE == MODE_COUNT ? a.ntasks : L.wpre[a.W]);
+        // Task assignment. When the grid has a slot for every task, each
+        // workgroup strides over the task ids (no atomics, every task starts
+        // at once, spread over all workgroups: chunk = 0). Otherwise tasks
+        // are grabbed from one counter in chunks of at least 8, so that the
+        // counter, one address for the whole grid, sees few atomics.
+        const uint32_t slots = gridDim.x * (uint32_t)T;
+        L.chunk = L.ntasks <= slots ? 0u : min(256u, max(8u, L.ntasks / slots));
+        L.snext = blockIdx.x;
     }
     __syncthreads();
 
@@ -452,10 +475,16 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
                 L.s_new[s] = NONE;
                 if (L.s_act[s] || L.done) continue;
                 if (L.tnext == L.tend) {
-                    uint32_t b = atomicAdd(a.grab, CHUNK);
+                    uint32_t b;
+                    if (L.chunk == 0) {   // striding: task blockIdx.x + i * gridDim.x
+                        b = L.snext;
+                        L.snext += gridDim.x;
+                    } else {
+                        b = atomicAdd(a.grab, L.chunk);
+                    }
                     if (b >= L.ntasks) { L.done = 1; continue; }
                     L.tnext = b;
-                    L.tend = min(b + CHUNK, L.ntasks);
+                    L.tend = min(b + max(L.chunk, 1u), L.ntasks);
                 }
                 L.s_new[s] = L.tnext++;
                 L.s_cnt[s] = 0;
@@ -678,13 +707,13 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
     st_ovf = group_sum<NT>(st_ovf, L.red);
     // workgroups that found no task add nothing (no contended atomics)
     if (tid == 0 && st_reached + st_ovf) {
-        if (MODE == MODE_DEC) atomicAdd(&a.stats[ST_DECREMENTS], (unsigned long long)st_dec);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_RELAX)], (unsigned long long)st_relax);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)st_reached);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_ARCS)], (unsigned long long)st_arcs);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_OVF)], (unsigned long long)st_ovf);
-        atomicAdd(&a.stats[a.st_trav], (unsigned long long)st_trav);
-        atomicMax(&a.stats[ST_MAXLV_BASE + a.pass * 3 + a.tier], (unsigned long long)levels);
+        if (MODE == MODE_DEC) stat_add(a.stats, ST_DECREMENTS, st_dec);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_RELAX), st_relax);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_REACHED), st_reached);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_ARCS), st_arcs);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_OVF), st_ovf);
+        stat_add(a.stats, a.st_trav, st_trav);
+        stat_max(a.stats, ST_MAXLV_BASE + a.pass * 3 + a.tier, levels);
     }
 }
 
@@ -908,11 +937,11 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     trav = group_sum<NT>(trav, L.red);
     dec = group_sum<NT>(dec, L.red);
     if (tid == 0 && reached) {
-        if (MODE == MODE_DEC) atomicAdd(&a.stats[ST_DECREMENTS], (unsigned long long)dec);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_RELAX)], (unsigned long long)relax);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_REACHED)], (unsigned long long)reached);
-        atomicAdd(&a.stats[st_tier(a.pass, a.tier, F_ARCS)], (unsigned long long)arcs);
-        atomicAdd(&a.stats[a.st_trav], (unsigned long long)trav);
-        atomicMax(&a.stats[ST_MAXLV_BASE + a.pass * 3 + a.tier], (unsigned long long)levels);
+        if (MODE == MODE_DEC) stat_add(a.stats, ST_DECREMENTS, dec);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_RELAX), relax);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_REACHED), reached);
+        stat_add(a.stats, st_tier(a.pass, a.tier, F_ARCS), arcs);
+        stat_add(a.stats, a.st_trav, trav);
+        stat_max(a.stats, ST_MAXLV_BASE + a.pass * 3 + a.tier, levels);
     }
 }
