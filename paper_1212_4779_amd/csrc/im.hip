@@ -441,32 +441,15 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
 }
 
 // Per-snapshot live lists of the nodes below the hub threshold (degree >= 2;
-// see SparseLists). One thread per (node, word) pair: a bit-sliced counter
-// (eight 64-bit planes, one 8-bit count per snapshot bit) adds up the pair's
-// mask words, which gives the 65 cumulative counts; a workgroup reserves its
-// pairs' range of adj with one atomic; then the heads are placed, each at its
-// bit's start plus the count of earlier arcs live in that bit. Pairs of
-// degree >= SP_MAXDEG (the counter's range), and pairs whose lists do not fit
-// the capacity, keep base = IM_EMPTY and are expanded through the masks.
+// see SparseLists). One thread per (node, word) pair, each with a private
+// 65-entry row of u16 counters in LDS: every live (arc, snapshot) bit adds one
+// to its snapshot's counter, an in-place prefix sum turns the row into the
+// 65 cumulative counts, which the workgroup writes out coalesced; one atomic
+// per workgroup reserves the heads, and the same row then serves as each
+// snapshot's cursor while the heads are placed. Pairs of degree >= SP_MAXDEG
+// (their counts could pass 16 bits), and pairs whose lists do not fit the
+// capacity, keep base = IM_EMPTY and are expanded through the masks.
 constexpr uint32_t SP_MAXDEG = 256;
-
-__device__ __forceinline__ void vc_add(uint64_t (&c)[8], uint64_t m)
-{
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        const uint64_t t = c[i] & m;
-        c[i] ^= m;
-        m = t;
-    }
-}
-
-__device__ __forceinline__ uint32_t vc_get(const uint64_t (&c)[8], uint32_t b)
-{
-    uint32_t v = 0;
-#pragma unroll
-    for (int i = 0; i < 8; i++) v |= (uint32_t)((c[i] >> b) & 1ull) << i;
-    return v;
-}
 
 __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const uint32_t *col,
                                                       const uint64_t *mask, uint64_t m, uint32_t n,
@@ -476,7 +459,7 @@ __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const
 {
     __shared__ uint32_t s_w[256 / 64 + 1];
     __shared__ unsigned long long s_base;
-    __shared__ __attribute__((aligned(16))) uint16_t s_cum[256 * 65];   // the chunk's counts, written out coalesced
+    __shared__ __attribute__((aligned(16))) uint16_t s_cum[256 * 65];
     const uint64_t P = (uint64_t)W * n;
     for (uint64_t p0 = (uint64_t)blockIdx.x * 256; p0 < P; p0 += (uint64_t)gridDim.x * 256) {
         const uint64_t p = p0 + threadIdx.x;
@@ -492,21 +475,22 @@ __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const
         }
         const uint64_t *mw = mask + (uint64_t)w * m;
         uint16_t *cp = s_cum + threadIdx.x * 65;
+        for (uint32_t b = 0; b < 65; b++) cp[b] = 0;
         if (elig) {
-            uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            // count into cp[b + 1], then an inclusive prefix gives cp[b] = the
+            // number of heads live in snapshots before b
             uint32_t e = e0;
             for (; e + 4 <= e1; e += 4) {   // four independent loads in flight
                 const uint64_t m0 = mw[e], m1 = mw[e + 1], m2 = mw[e + 2], m3 = mw[e + 3];
-                vc_add(c, m0); vc_add(c, m1); vc_add(c, m2); vc_add(c, m3);
+                for (uint64_t t = m0; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
+                for (uint64_t t = m1; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
+                for (uint64_t t = m2; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
+                for (uint64_t t = m3; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
             }
-            for (; e < e1; e++) vc_add(c, mw[e]);
-            for (uint32_t b = 0; b < 64; b++) {
-                cp[b] = (uint16_t)total;
-                total += vc_get(c, b);
-            }
-            cp[64] = (uint16_t)total;
-        } else {
-            for (uint32_t b = 0; b < 65; b++) cp[b] = 0;
+            for (; e < e1; e++)
+                for (uint64_t t = mw[e]; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
+            for (uint32_t b = 1; b < 65; b++) cp[b] = (uint16_t)(cp[b] + cp[b - 1]);
+            total = cp[64];
         }
         __syncthreads();
         {
@@ -528,18 +512,17 @@ __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const
         const bool fits = elig && b0 + total <= cap;
         if (p < P) base[p] = fits ? (uint32_t)b0 : IM_EMPTY;
         if (fits && total) {
-            uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            // the row now serves as each snapshot's cursor
             for (uint32_t e = e0; e < e1; e++) {
                 const uint64_t mb = mw[e];
                 const uint32_t v = col[e];
                 for (uint64_t t = mb; t; t &= t - 1) {
                     const uint32_t b = (uint32_t)__ffsll((unsigned long long)t) - 1;
-                    adj[b0 + cp[b] + vc_get(c, b)] = v;
+                    adj[b0 + cp[b]++] = v;
                 }
-                vc_add(c, mb);
             }
         }
-        __syncthreads();   // s_base is rewritten by the next chunk
+        __syncthreads();   // s_cum and s_base are rewritten by the next chunk
     }
 }
 
@@ -1797,7 +1780,8 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     uint32_t n = g->n, W = (R + 63) / 64;
     {
         PhaseTimer pt(ws, IM_PH_ARGMAX, s);
-        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n,
+        // a single graph: few workgroups, so that few atomics meet on the key
+        k_argmax<<<grid_for(n, 256, ws->batch.count == 1 ? 256 : 2048), 256, 0, s>>>(ws->gain, ws->sel, n,
                                                          ws->keys + (uint64_t)t * ws->batch.count,
                                                          ws->batch, t, ws->pk, (uint32_t)PK_ZERO);
     }
@@ -2723,7 +2707,8 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
     // argmax needs no evaluation
     {
         PhaseTimer pt(ws, IM_PH_ARGMAX, s);
-        k_argmax<<<grid_for(n, 256, 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys, ws->batch, 0,
+        // a single graph: few workgroups, so that few atomics meet on the key
+        k_argmax<<<grid_for(n, 256, ws->batch.count == 1 ? 256 : 2048), 256, 0, s>>>(ws->gain, ws->sel, n, ws->keys, ws->batch, 0,
                                                          ws->pk, (uint32_t)PK_ZERO);
     }
     if ((rc = commit_seed(g, R, 0, seeds_out, gains_out, ws, s))) return rc;
