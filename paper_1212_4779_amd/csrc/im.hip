@@ -441,15 +441,28 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
 }
 
 // Per-snapshot live lists of the nodes below the hub threshold (degree >= 2;
-// see SparseLists). One thread per (node, word) pair, each with a private
-// 65-entry row of u16 counters in LDS: every live (arc, snapshot) bit adds one
-// to its snapshot's counter, an in-place prefix sum turns the row into the
-// 65 cumulative counts, which the workgroup writes out coalesced; one atomic
-// per workgroup reserves the heads, and the same row then serves as each
-// snapshot's cursor while the heads are placed. Pairs of degree >= SP_MAXDEG
-// (their counts could pass 16 bits), and pairs whose lists do not fit the
-// capacity, keep base = IM_EMPTY and are expanded through the masks.
+// see SparseLists). A workgroup takes 256 (node, word) pairs at a time and
+// spreads the arcs of its eligible pairs evenly over its lanes (node degrees
+// are unrelated to node ids, so one row per lane would leave most lanes idle
+// behind the longest row); each arc's pair is found by a binary search over
+// the pairs' arc offsets, and consecutive lanes read consecutive mask words.
+// Every live (arc, snapshot) bit adds one to its pair's counter for that
+// snapshot (65 u16 counters per pair in LDS, updated by 32-bit atomics on the
+// half that holds them: a count stays below 2^16, so no carry crosses into
+// the neighbouring counter). Each lane then turns its pair's row into the 65
+// cumulative counts in place, the eligible rows are written out coalesced, one
+// atomic per workgroup reserves the heads, and the rows serve as each
+// snapshot's cursor while the heads are placed (so the heads of one
+// snapshot's list are in no particular order). Pairs of degree >= SP_MAXDEG,
+// and pairs whose lists do not fit the capacity, keep base = IM_EMPTY and are
+// expanded through the masks; their rows of cum are left unwritten.
 constexpr uint32_t SP_MAXDEG = 256;
+
+__device__ __forceinline__ uint32_t sp_bump(uint32_t *cnt32, uint32_t i)
+{
+    const uint32_t sh = (i & 1u) * 16u;
+    return (atomicAdd(&cnt32[i >> 1], 1u << sh) >> sh) & 0xFFFFu;
+}
 
 __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const uint32_t *col,
                                                       const uint64_t *mask, uint64_t m, uint32_t n,
@@ -457,72 +470,112 @@ __global__ __launch_bounds__(256) void k_sparse_build(const uint32_t *row, const
                                                       uint16_t *cum, uint32_t *adj,
                                                       unsigned long long *alloc, uint64_t cap)
 {
+    constexpr int U = 4;
     __shared__ uint32_t s_w[256 / 64 + 1];
     __shared__ unsigned long long s_base;
+    __shared__ uint32_t s_pre[256], s_e0[256], s_word[256], s_b0[256];
+    __shared__ uint8_t s_elig[256];
     __shared__ __attribute__((aligned(16))) uint16_t s_cum[256 * 65];
+    uint32_t *cnt32 = (uint32_t *)s_cum;
     const uint64_t P = (uint64_t)W * n;
+    const uint32_t t = threadIdx.x;
     for (uint64_t p0 = (uint64_t)blockIdx.x * 256; p0 < P; p0 += (uint64_t)gridDim.x * 256) {
-        const uint64_t p = p0 + threadIdx.x;
-        uint32_t w = 0, e0 = 0, e1 = 0, total = 0;
+        const uint64_t p = p0 + t;
+        uint32_t w = 0, e0 = 0, deg = 0;
         bool elig = false;
         if (p < P) {
             w = (uint32_t)(p / n);
             const uint32_t x = (uint32_t)(p - (uint64_t)w * n);
             e0 = row[x];
-            e1 = row[x + 1];
-            const uint32_t deg = e1 - e0;
+            deg = row[x + 1] - e0;
             elig = deg >= 2 && deg < SP_MAXDEG && (hub_deg == 0 || deg < hub_deg);
         }
-        const uint64_t *mw = mask + (uint64_t)w * m;
-        uint16_t *cp = s_cum + threadIdx.x * 65;
-        for (uint32_t b = 0; b < 65; b++) cp[b] = 0;
-        if (elig) {
-            // count into cp[b + 1], then an inclusive prefix gives cp[b] = the
-            // number of heads live in snapshots before b
-            uint32_t e = e0;
-            for (; e + 4 <= e1; e += 4) {   // four independent loads in flight
-                const uint64_t m0 = mw[e], m1 = mw[e + 1], m2 = mw[e + 2], m3 = mw[e + 3];
-                for (uint64_t t = m0; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
-                for (uint64_t t = m1; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
-                for (uint64_t t = m2; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
-                for (uint64_t t = m3; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
+        for (uint32_t j = t; j < 256 * 65 / 2; j += 256) cnt32[j] = 0u;
+        uint32_t T;
+        const uint32_t pre = block_excl_scan<256>(elig ? deg : 0u, s_w, &T);
+        s_pre[t] = pre;
+        s_e0[t] = e0;
+        s_word[t] = w;
+        s_elig[t] = elig ? 1 : 0;
+        __syncthreads();
+        // count: the pair's counter b+1 for every live bit b
+        for (uint32_t j0 = t; j0 < T; j0 += 256 * U) {
+            uint64_t b[U];
+            uint32_t q[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t j = j0 + (uint32_t)u * 256;
+                b[u] = 0ull;
+                q[u] = 0;
+                if (j < T) {
+                    q[u] = (uint32_t)upper_index<256>(s_pre, j);
+                    b[u] = mask[(uint64_t)s_word[q[u]] * m + s_e0[q[u]] + (j - s_pre[q[u]])];
+                }
             }
-            for (; e < e1; e++)
-                for (uint64_t t = mw[e]; t; t &= t - 1) cp[__ffsll((unsigned long long)t)]++;
-            for (uint32_t b = 1; b < 65; b++) cp[b] = (uint16_t)(cp[b] + cp[b - 1]);
-            total = cp[64];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                for (uint64_t v = b[u]; v; v &= v - 1)
+                    sp_bump(cnt32, q[u] * 65 + (uint32_t)__ffsll((unsigned long long)v));
         }
         __syncthreads();
-        {
-            // 256 pairs x 65 counts = 8320 aligned 32-bit words (p0 is a multiple of 256)
-            const uint64_t npair = min((uint64_t)256, P - p0);
-            const uint32_t nwords = (uint32_t)(npair * 65 + 1) / 2;
-            const uint32_t *src = (const uint32_t *)s_cum;
-            uint32_t *dst = (uint32_t *)(cum + p0 * 65);
-            for (uint32_t j = threadIdx.x; j < nwords; j += 256) {
-                if (2 * j + 1 < npair * 65) dst[j] = src[j];
-                else cum[p0 * 65 + 2 * j] = s_cum[2 * j];   // odd tail: one u16
-            }
+        // inclusive prefix over the row: cp[b] = heads live in snapshots before b
+        uint16_t *cp = s_cum + t * 65;
+        uint32_t total = 0;
+        if (elig) {
+            for (uint32_t bb = 1; bb < 65; bb++) cp[bb] = (uint16_t)(cp[bb] + cp[bb - 1]);
+            total = cp[64];
         }
         uint32_t blk;
-        const uint32_t ex = block_excl_scan<256>(elig ? total : 0u, s_w, &blk);
-        if (threadIdx.x == 0) s_base = blk ? atomicAdd(alloc, (unsigned long long)blk) : 0ull;
+        const uint32_t ex = block_excl_scan<256>(total, s_w, &blk);   // syncs: rows complete
+        {
+            // eligible rows out, as aligned 32-bit words (p0 is a multiple of 256);
+            // a word shared by two rows is written when either row is eligible
+            const uint64_t npair = min((uint64_t)256, P - p0);
+            const uint32_t nu16 = (uint32_t)(npair * 65), nwords = (nu16 + 1) / 2;
+            uint32_t *dst = (uint32_t *)(cum + p0 * 65);
+            for (uint32_t j = t; j < nwords; j += 256) {
+                const uint32_t qa = 2 * j / 65, qb = (2 * j + 1) / 65;
+                if (2 * j + 1 < nu16) {
+                    if (s_elig[qa] | s_elig[qb]) dst[j] = cnt32[j];
+                } else if (s_elig[qa]) {
+                    cum[p0 * 65 + 2 * j] = s_cum[2 * j];   // odd tail: one u16
+                }
+            }
+        }
+        if (t == 0) s_base = blk ? atomicAdd(alloc, (unsigned long long)blk) : 0ull;
         __syncthreads();
         const unsigned long long b0 = s_base + ex;
         const bool fits = elig && b0 + total <= cap;
         if (p < P) base[p] = fits ? (uint32_t)b0 : IM_EMPTY;
-        if (fits && total) {
-            // the row now serves as each snapshot's cursor
-            for (uint32_t e = e0; e < e1; e++) {
-                const uint64_t mb = mw[e];
-                const uint32_t v = col[e];
-                for (uint64_t t = mb; t; t &= t - 1) {
-                    const uint32_t b = (uint32_t)__ffsll((unsigned long long)t) - 1;
-                    adj[b0 + cp[b]++] = v;
+        s_b0[t] = fits ? (uint32_t)b0 : IM_EMPTY;
+        __syncthreads();
+        // place: the row now serves as each snapshot's cursor
+        for (uint32_t j0 = t; j0 < T; j0 += 256 * U) {
+            uint64_t b[U];
+            uint32_t q[U], e[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t j = j0 + (uint32_t)u * 256;
+                b[u] = 0ull;
+                q[u] = 0;
+                e[u] = 0;
+                if (j < T) {
+                    q[u] = (uint32_t)upper_index<256>(s_pre, j);
+                    e[u] = s_e0[q[u]] + (j - s_pre[q[u]]);
+                    if (s_b0[q[u]] != IM_EMPTY) b[u] = mask[(uint64_t)s_word[q[u]] * m + e[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (!b[u]) continue;
+                const uint32_t v = col[e[u]], hb = s_b0[q[u]];
+                for (uint64_t bits = b[u]; bits; bits &= bits - 1) {
+                    const uint32_t bit = (uint32_t)__ffsll((unsigned long long)bits) - 1;
+                    adj[hb + sp_bump(cnt32, q[u] * 65 + bit)] = v;
                 }
             }
         }
-        __syncthreads();   // s_cum and s_base are rewritten by the next chunk
+        __syncthreads();   // the LDS arrays and s_base are rewritten by the next chunk
     }
 }
 
