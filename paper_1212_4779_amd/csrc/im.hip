@@ -156,19 +156,61 @@ __global__ __launch_bounds__(TR_NT) void k_transpose(const uint32_t *row32, cons
         uint32_t base = atomicAdd(&cnt[v], L.cnt[i]);
         if (SCATTER) { L.off[i] = in_row[v] + base; L.cnt[i] = 0; }
     }
-    if (!SCATTER) return;
-    __syncthreads();
-    for (uint64_t e = e0 + tid; e < e1; e += TR_NT) {
-        uint32_t v = col[e];
-        uint32_t h = tr_slot(L, v);
-        uint32_t pos = L.off[h] + atomicAdd(&L.cnt[h], 1u);
-        uint32_t lo = 0, hi = n;  // tail: largest u with row32[u] <= e
-        while (hi - lo > 1) {
-            uint32_t mid = lo + (hi - lo) / 2;
-            if (row32[mid] <= (uint32_t)e) lo = mid; else hi = mid;
+    if constexpr (SCATTER) {
+        // tails of the slice's arcs: tl[i] = the node whose row holds arc e0+i.
+        // The nodes u_lo .. u_hi own the slice; each of them after u_lo with
+        // arcs marks the position where its row starts, and an inclusive max
+        // scan carries every mark forward over its row.
+        __shared__ uint32_t tl[TR_ARCS];
+        __shared__ uint32_t ends[2], wmax[TR_NT / 64];
+        const uint32_t len = (uint32_t)(e1 - e0);
+        for (uint32_t i = tid; i < TR_ARCS; i += TR_NT) tl[i] = 0;
+        if (tid == 0 || tid == 64) {
+            const uint32_t e = tid == 0 ? (uint32_t)e0 : (uint32_t)(e1 - 1);
+            uint32_t lo = 0, hi = n;  // largest u with row32[u] <= e
+            while (hi - lo > 1) {
+                uint32_t mid = lo + (hi - lo) / 2;
+                if (row32[mid] <= e) lo = mid; else hi = mid;
+            }
+            ends[tid / 64] = lo;
         }
-        in_col[pos] = lo;
-        in2out[pos] = (uint32_t)e;
+        __syncthreads();
+        const uint32_t u_lo = ends[0], u_hi = ends[1];
+        if (tid == 0) tl[0] = u_lo;
+        for (uint32_t u = u_lo + 1 + tid; u <= u_hi; u += TR_NT) {
+            const uint32_t r0 = row32[u];   // e0 < r0 <= e1 - 1
+            if (row32[u + 1] > r0) tl[r0 - (uint32_t)e0] = u;
+        }
+        __syncthreads();
+        constexpr uint32_t PER = TR_ARCS / TR_NT;
+        const uint32_t c0 = tid * PER;
+        uint32_t run = 0;
+        for (uint32_t i = 0; i < PER; i++) run = max(run, tl[c0 + i]);
+        // exclusive max over the lower threads' chunks
+        const int lane = tid & 63, wid = tid >> 6;
+        uint32_t x = run;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x = max(x, y);
+        }
+        if (lane == 63) wmax[wid] = x;
+        const uint32_t below = __shfl_up(x, 1, 64);
+        __syncthreads();
+        uint32_t carry = lane > 0 ? below : 0u;
+        for (int k = 0; k < wid; k++) carry = max(carry, wmax[k]);
+        for (uint32_t i = 0; i < PER; i++) {
+            carry = max(carry, tl[c0 + i]);
+            tl[c0 + i] = carry;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < len; i += TR_NT) {
+            const uint64_t e = e0 + i;
+            uint32_t v = col[e];
+            uint32_t h = tr_slot(L, v);
+            uint32_t pos = L.off[h] + atomicAdd(&L.cnt[h], 1u);
+            in_col[pos] = tl[i];
+            in2out[pos] = (uint32_t)e;
+        }
     }
 }
 
@@ -345,9 +387,10 @@ __global__ void k_hub_mark(const uint32_t *row, uint32_t n, uint32_t hub_deg, ui
 }
 
 // Count the live (arc, snapshot) pairs of hub h in word w per bit and reserve
-// their range of adj. One block per (hub, word). A hub whose lists would be
-// denser than a quarter of its masks, or would not fit, is expanded through
-// the masks instead (its slot is cleared).
+// their range of adj. Each block takes hubs blockIdx.x, blockIdx.x + gridDim.x,
+// ... in word blockIdx.y (the hub count is known only on the device). A hub
+// whose lists would be denser than a quarter of its masks, or would not fit,
+// is expanded through the masks instead (its slot is cleared).
 __global__ __launch_bounds__(HB_NT) void k_hub_count(const uint32_t *row, const uint64_t *mask,
                                                      uint64_t m, uint32_t W, const uint32_t *list,
                                                      const uint32_t *nhub, uint32_t *slot,
@@ -356,41 +399,44 @@ __global__ __launch_bounds__(HB_NT) void k_hub_count(const uint32_t *row, const 
 {
     constexpr int U = 8;
     __shared__ uint32_t cnt[64];
-    const uint32_t h = blockIdx.x, w = blockIdx.y;
-    if (h >= *nhub) return;
+    const uint32_t w = blockIdx.y, nh = *nhub;
     const int tid = threadIdx.x;
-    const uint32_t x = list[h], e0 = row[x], e1 = row[x + 1];
     const uint64_t *mw = mask + (uint64_t)w * m;
-    if (tid < 64) cnt[tid] = 0;
-    __syncthreads();
-    for (uint32_t e = e0 + tid; e < e1; e += HB_NT * U) {
-        uint64_t b[U];
+    for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+        const uint32_t x = list[h], e0 = row[x], e1 = row[x + 1];
+        if (tid < 64) cnt[tid] = 0;
+        __syncthreads();
+        for (uint32_t e = e0 + tid; e < e1; e += HB_NT * U) {
+            uint64_t b[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            uint32_t ee = e + (uint32_t)u * HB_NT;
-            b[u] = ee < e1 ? mw[ee] : 0ull;
+            for (int u = 0; u < U; u++) {
+                uint32_t ee = e + (uint32_t)u * HB_NT;
+                b[u] = ee < e1 ? mw[ee] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                while (b[u]) {
+                    atomicAdd(&cnt[__ffsll((unsigned long long)b[u]) - 1], 1u);
+                    b[u] &= b[u] - 1;
+                }
         }
-#pragma unroll
-        for (int u = 0; u < U; u++)
-            while (b[u]) {
-                atomicAdd(&cnt[__ffsll((unsigned long long)b[u]) - 1], 1u);
-                b[u] &= b[u] - 1;
+        __syncthreads();
+        if (tid < 64) {
+            // each of these lanes reads only its own counter, which it alone
+            // clears at the start of the next hub
+            uint32_t c = cnt[tid];
+            hcnt[((uint64_t)h * W + w) * 64 + tid] = c;
+            uint32_t incl = wave_incl_scan(c);
+            if (tid == 63) {
+                bool use = (uint64_t)incl * 4 <= 64ull * (e1 - e0);
+                unsigned long long base = 0;
+                if (use) {
+                    base = atomicAdd(alloc, (unsigned long long)incl);
+                    use = base + incl <= cap;
+                }
+                hbase[(uint64_t)h * W + w] = base;
+                if (!use) slot[x] = IM_EMPTY;
             }
-    }
-    __syncthreads();
-    if (tid < 64) {
-        uint32_t c = cnt[tid];
-        hcnt[((uint64_t)h * W + w) * 64 + tid] = c;
-        uint32_t incl = wave_incl_scan(c);
-        if (tid == 63) {
-            bool use = (uint64_t)incl * 4 <= 64ull * (e1 - e0);
-            unsigned long long base = 0;
-            if (use) {
-                base = atomicAdd(alloc, (unsigned long long)incl);
-                use = base + incl <= cap;
-            }
-            hbase[(uint64_t)h * W + w] = base;
-            if (!use) slot[x] = IM_EMPTY;
         }
     }
 }
@@ -404,39 +450,41 @@ __global__ __launch_bounds__(HB_NT) void k_hub_fill(const uint32_t *row, const u
 {
     constexpr int U = 8;
     __shared__ uint32_t cur[64];
-    const uint32_t h = blockIdx.x, w = blockIdx.y;
-    if (h >= *nhub) return;
-    const uint32_t x = list[h];
-    if (slot[x] == IM_EMPTY) return;
+    const uint32_t w = blockIdx.y, nh = *nhub;
     const int tid = threadIdx.x;
-    const uint32_t e0 = row[x], e1 = row[x + 1];
     const uint64_t *mw = mask + (uint64_t)w * m;
-    if (tid < 64) {
-        uint32_t c = hcnt[((uint64_t)h * W + w) * 64 + tid];
-        uint32_t incl = wave_incl_scan(c);
-        uint32_t o = (uint32_t)hbase[(uint64_t)h * W + w] + incl - c;
-        cur[tid] = o;
-        uint32_t *dst = hoff + ((uint64_t)h * W + w) * 65;
-        dst[tid] = o;
-        if (tid == 63) dst[64] = o + c;
-    }
-    __syncthreads();
-    for (uint32_t e = e0 + tid; e < e1; e += HB_NT * U) {
-        uint64_t b[U];
-        uint32_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            uint32_t ee = e + (uint32_t)u * HB_NT;
-            b[u] = ee < e1 ? mw[ee] : 0ull;
-            v[u] = ee < e1 ? col[ee] : 0u;
+    for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+        const uint32_t x = list[h];
+        if (slot[x] == IM_EMPTY) continue;   // the same for the whole block
+        const uint32_t e0 = row[x], e1 = row[x + 1];
+        if (tid < 64) {
+            uint32_t c = hcnt[((uint64_t)h * W + w) * 64 + tid];
+            uint32_t incl = wave_incl_scan(c);
+            uint32_t o = (uint32_t)hbase[(uint64_t)h * W + w] + incl - c;
+            cur[tid] = o;
+            uint32_t *dst = hoff + ((uint64_t)h * W + w) * 65;
+            dst[tid] = o;
+            if (tid == 63) dst[64] = o + c;
         }
+        __syncthreads();
+        for (uint32_t e = e0 + tid; e < e1; e += HB_NT * U) {
+            uint64_t b[U];
+            uint32_t v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            while (b[u]) {
-                uint32_t pos = atomicAdd(&cur[__ffsll((unsigned long long)b[u]) - 1], 1u);
-                hadj[pos] = v[u];
-                b[u] &= b[u] - 1;
+            for (int u = 0; u < U; u++) {
+                uint32_t ee = e + (uint32_t)u * HB_NT;
+                b[u] = ee < e1 ? mw[ee] : 0ull;
+                v[u] = ee < e1 ? col[ee] : 0u;
             }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                while (b[u]) {
+                    uint32_t pos = atomicAdd(&cur[__ffsll((unsigned long long)b[u]) - 1], 1u);
+                    hadj[pos] = v[u];
+                    b[u] &= b[u] - 1;
+                }
+        }
+        __syncthreads();   // cur is rewritten for the next hub
     }
 }
 
@@ -1699,7 +1747,7 @@ static void build_hubs(int d, const uint32_t *row, const uint32_t *col, const ui
                                                        ws->hlist[d], ws->hnum + d);
     if (m == 0 || ws->hub_deg == 0) return;
     const unsigned maxh = (unsigned)std::min<uint64_t>(m / ws->hub_deg + 1, ws->cap_hub);
-    dim3 grid(maxh, W);
+    dim3 grid(std::min(maxh, 1024u), W);
     k_hub_count<<<grid, HB_NT, 0, s>>>(row, mask, m, W, ws->hlist[d], ws->hnum + d, ws->hslot[d],
                                        ws->hcnt[d], ws->hbase[d], ws->halloc + d, ws->cap_hadj);
     k_hub_fill<<<grid, HB_NT, 0, s>>>(row, col, mask, m, W, ws->hlist[d], ws->hnum + d,
