@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void k_mask_gather(const uint32_t *in2out, uin
 // ---------------------------------------------------------------------------
 // Hub lists: per-snapshot live adjacency of heavy nodes (see HubLists)
 // ---------------------------------------------------------------------------
-constexpr int HB_NT = 256;
+constexpr int HB_NT = 1024;
 
 __global__ void k_hub_mark(const uint32_t *row, uint32_t n, uint32_t hub_deg, uint32_t *slot,
                            uint32_t *list, uint32_t *nhub)
