@@ -662,8 +662,37 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint
         }
         return;
     }
+    // a single graph: groups of four nodes (one 16-byte gain load and one
+    // 4-byte selection load each; both arrays are allocation-aligned), four
+    // groups in flight per lane, then the n % 4 tail nodes one by one
     unsigned long long best = 0;
-    for (uint32_t u = blockIdx.x * 256u + threadIdx.x; u < n; u += gridDim.x * 256u)
+    const uint32_t ng = n / 4, stride = gridDim.x * 256u;
+    const uint4 *g4 = (const uint4 *)gain;
+    const uint32_t *s4 = (const uint32_t *)sel;
+    for (uint32_t q0 = blockIdx.x * 256u + threadIdx.x; q0 < ng; q0 += 4 * stride) {
+        uint4 gv[4];
+        uint32_t sv[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t q = q0 + (uint32_t)i * stride;
+            const bool in = q >= q0 && q < ng;   // (q >= q0: no wrap-around)
+            gv[i] = in ? g4[q] : make_uint4(0u, 0u, 0u, 0u);
+            sv[i] = in ? s4[q] : 0x01010101u;    // out of range: all four taken
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t u0 = (q0 + (uint32_t)i * stride) * 4u;
+            const uint32_t gg[4] = {gv[i].x, gv[i].y, gv[i].z, gv[i].w};
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                if (!((sv[i] >> (8 * j)) & 0xFFu)) {
+                    const unsigned long long k =
+                        ((unsigned long long)gg[j] << 32) | (0xFFFFFFFFu - (u0 + (uint32_t)j));
+                    best = k > best ? k : best;
+                }
+        }
+    }
+    for (uint32_t u = 4 * ng + blockIdx.x * 256u + threadIdx.x; u < n; u += stride)
         if (!sel[u]) {
             unsigned long long k = ((unsigned long long)gain[u] << 32) | (0xFFFFFFFFu - u);
             best = k > best ? k : best;

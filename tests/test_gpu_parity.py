@@ -200,6 +200,17 @@ def test_edge_cases(im):
     s, gn, _ = im.select(_dev(im, g), 64, 300, 2)
     s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, 64, 300, 2)
     assert s.cpu().tolist() == s_ref.tolist() and gn.cpu().tolist() == g_ref.tolist()
+    # the argmax reads nodes in groups of four plus the n % 4 last ones: the
+    # best node among the last, and k = n with n % 4 = 3
+    g = _csr(11, [(10, i) for i in range(10)] + [(3, 4)], 0.6)
+    s, gn, _ = im.select(_dev(im, g), 70, 4, 5)
+    s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, 70, 4, 5)
+    assert s.cpu().tolist()[0] == 10
+    assert s.cpu().tolist() == s_ref.tolist() and gn.cpu().tolist() == g_ref.tolist()
+    g = gg.chung_lu_graph(303, 1500, 2.5, 6, True, 0.2)
+    s, gn, _ = im.select(_dev(im, g), 64, 303, 2)
+    s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, 64, 303, 2)
+    assert s.cpu().tolist() == s_ref.tolist() and gn.cpu().tolist() == g_ref.tolist()
 
 
 def test_errors(im):
