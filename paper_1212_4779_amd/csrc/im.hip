@@ -1124,28 +1124,32 @@ __global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, co
     if (threadIdx.x < 64 && cnt[threadIdx.x]) atomicAdd(&bcnt[w * 64 + threadIdx.x], cnt[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(64) void k_pack_scan(const uint32_t *bcnt, uint32_t *boff, uint32_t *gcnt)
-{
-    const uint32_t w = blockIdx.x, lane = threadIdx.x;
-    const uint32_t c = bcnt[w * 64 + lane];
-    const uint32_t incl = wave_incl_scan(c);
-    boff[w * 64 + lane] = incl - c;
-    uint32_t mx = c;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
-    if (lane == 0) gcnt[w] = mx;
-}
-
+// Place the single-bit tasks bit by bit. Every workgroup of word w takes the
+// bit offsets as the exclusive prefix of that word's 64 bit counts (counted
+// by k_pack_count); workgroup 0 of the word also stores them, with the
+// largest count, for the reverse pass.
 __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, const uint32_t *tcounts,
                                                      const uint64_t *newly, uint32_t n,
-                                                     const uint32_t *boff, uint32_t *bcur,
-                                                     uint32_t *plist)
+                                                     const uint32_t *bcnt, uint32_t *boff,
+                                                     uint32_t *gcnt, uint32_t *bcur, uint32_t *plist)
 {
     __shared__ uint32_t cnt[64], base0[64];
     const uint32_t w = blockIdx.y;
     const uint64_t off = (uint64_t)w * n;
     const uint32_t c = tcounts[w];
-    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x, k = bcnt[w * 64 + lane];
+        const uint32_t ex = wave_incl_scan(k) - k;
+        cnt[lane] = 0;
+        base0[lane] = ex;
+        if (blockIdx.x == 0) {
+            boff[w * 64 + lane] = ex;
+            uint32_t mx = k;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+            if (lane == 0) gcnt[w] = mx;
+        }
+    }
     __syncthreads();
     for (uint32_t i = blockIdx.x * PK_NT + threadIdx.x; i < c; i += gridDim.x * PK_NT) {
         const uint64_t b = newly[off + tnodes[off + i]];
@@ -1154,7 +1158,7 @@ __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, con
     __syncthreads();
     if (threadIdx.x < 64) {
         const uint32_t k = cnt[threadIdx.x];
-        base0[threadIdx.x] = k ? atomicAdd(&bcur[w * 64 + threadIdx.x], k) : 0u;
+        base0[threadIdx.x] += k ? atomicAdd(&bcur[w * 64 + threadIdx.x], k) : 0u;
         cnt[threadIdx.x] = 0;
     }
     __syncthreads();
@@ -1163,7 +1167,7 @@ __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, con
         const uint64_t b = newly[off + x];
         if (__popcll(b) != 1) continue;
         const uint32_t r = __ffsll((unsigned long long)b) - 1;
-        const uint32_t pos = boff[w * 64 + r] + base0[r] + atomicAdd(&cnt[r], 1u);
+        const uint32_t pos = base0[r] + atomicAdd(&cnt[r], 1u);
         plist[off + pos] = x;
     }
 }
@@ -1945,9 +1949,8 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
         PhaseTimer pt(ws, IM_PH_PACK, s);
         dim3 pg(grid_for(n, PK_NT, 64), W);
         k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist);
-        k_pack_scan<<<W, 64, 0, s>>>(bcnt, ws->boff, gcnt);
-        k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, ws->boff, bcur,
-                                         ws->plist);
+        k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, ws->boff,
+                                         gcnt, bcur, ws->plist);
     }
     BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W);
     a.gcnt = gcnt; a.mcnt = mcnt; a.bcnt = bcnt; a.boff = ws->boff;
