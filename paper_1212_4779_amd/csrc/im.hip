@@ -729,6 +729,11 @@ struct FwdArgs {
                                 // visit counts; zero on entry
     uint64_t *vis;              // visited (word << 32 | node), capacity W*n
     uint32_t *tnodes, *tcounts;
+    // reverse-task packing counts of the newly covered (word, node) pairs, or
+    // bcnt = nullptr for none: per (word, bit) the pairs covered in that one
+    // snapshot of the word ([W][64], zero on entry); pairs covered in several
+    // snapshots are listed in mlist[w][0 .. mcnt[w])
+    uint32_t *bcnt, *mcnt, *mlist;
     const unsigned long long *key;   // keys of this round, one per instance
     uint32_t t;
     Batch b;
@@ -752,6 +757,7 @@ struct FwdLds {
     uint32_t bcast;
     uint32_t p0[256];   // level 0: prefix of the seed's per-(word, bit) list lengths
     uint32_t o0[256];   // level 0: start of each (word, bit) list
+    uint32_t pk[64 * 64];   // this workgroup's packing counts per (word, bit)
 };
 
 __device__ __forceinline__ uint32_t coherent_load(uint32_t *p) { return atomicAdd(p, 0u); }
@@ -996,13 +1002,17 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     // (workgroup, word) and chunk
     uint64_t relax = 0, trav = 0;
     const uint32_t nv = group_load(&a.cnt[3], &L.bcast);
-    uint32_t *wcnt = L.scan;  // reused: per-word counts of this chunk (W <= 64)
-    uint32_t *wbase = L.rs;
+    // reused (W <= 64): per-word visit and multi-bit counts of this chunk, and
+    // their global bases
+    uint32_t *wcnt = L.scan, *wbase = L.rs, *wmc = L.wd, *wmb = L.aux;
+    const bool pack = a.bcnt != nullptr;
+    for (uint32_t j = tid; j < a.W * 64; j += FWD_NT) L.pk[j] = 0;
     for (uint32_t base = blockIdx.x * FWD_NT; base < nv; base += gridDim.x * FWD_NT) {
-        if (tid < 64) wcnt[tid] = 0;
+        if (tid < 64) { wcnt[tid] = 0; wmc[tid] = 0; }
         __syncthreads();
         const uint32_t i = base + tid;
-        uint32_t w = 0, x = 0, r = 0;
+        uint32_t w = 0, x = 0, r = 0, rm = 0;
+        bool multi = false;
         if (i < nv) {
             uint64_t e = a.vis[i];
             w = (uint32_t)(e >> 32);
@@ -1014,13 +1024,27 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
             relax += dg;
             trav += (uint64_t)__popcll(b) * dg;
             r = atomicAdd(&wcnt[w], 1u);
+            if (pack) {
+                multi = __popcll(b) != 1;
+                if (multi) rm = atomicAdd(&wmc[w], 1u);
+                else atomicAdd(&L.pk[w * 64 + (uint32_t)__ffsll((unsigned long long)b) - 1], 1u);
+            }
         }
         __syncthreads();
-        if (tid < 64 && tid < (int)a.W && wcnt[tid]) wbase[tid] = atomicAdd(&a.cnt[4 + tid], wcnt[tid]);
+        if (tid < 64 && tid < (int)a.W) {
+            if (wcnt[tid]) wbase[tid] = atomicAdd(&a.cnt[4 + tid], wcnt[tid]);
+            if (wmc[tid]) wmb[tid] = atomicAdd(&a.mcnt[tid], wmc[tid]);
+        }
         __syncthreads();
-        if (i < nv) a.tnodes[(uint64_t)w * a.n + wbase[w] + r] = x;
+        if (i < nv) {
+            a.tnodes[(uint64_t)w * a.n + wbase[w] + r] = x;
+            if (multi) a.mlist[(uint64_t)w * a.n + wmb[w] + rm] = x;
+        }
         __syncthreads();
     }
+    if (pack)
+        for (uint32_t j = tid; j < a.W * 64; j += FWD_NT)
+            if (L.pk[j]) atomicAdd(&a.bcnt[j], L.pk[j]);
     grid.sync();
     if (gtid < a.W) {
         const uint32_t c = coherent_load(&a.cnt[4 + gtid]);
@@ -1066,14 +1090,33 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
                                    a.bq0 + off, a.bq1 + off, a.tnodes + off, arcs);
     const uint32_t nvis = L.nvis;
     uint64_t relax = 0, trav = 0;
-    for (uint32_t i = tid; i < nvis; i += FWB_NT) {
-        uint32_t x = a.tnodes[off + i];
-        uint64_t b = a.newly[off + x];
-        a.covered[off + x] |= b;
-        uint32_t dg = a.row[x + 1] - a.row[x];
-        relax += dg;
-        trav += (uint64_t)__popcll(b) * dg;
+    __shared__ uint32_t pk[64];   // packing counts per bit of this word
+    const bool pack = a.bcnt != nullptr;
+    if (tid < 64) pk[tid] = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nvis; b0 += FWB_NT) {   // whole wavefronts per step
+        const uint32_t i = b0 + tid;
+        uint32_t x = 0;
+        bool multi = false;
+        if (i < nvis) {
+            x = a.tnodes[off + i];
+            uint64_t b = a.newly[off + x];
+            a.covered[off + x] |= b;
+            uint32_t dg = a.row[x + 1] - a.row[x];
+            relax += dg;
+            trav += (uint64_t)__popcll(b) * dg;
+            if (pack) {
+                multi = __popcll(b) != 1;
+                if (!multi) atomicAdd(&pk[__ffsll((unsigned long long)b) - 1], 1u);
+            }
+        }
+        if (pack) {
+            const uint32_t p = wave_append(multi, &a.mcnt[w]);
+            if (multi) a.mlist[off + p] = x;
+        }
     }
+    __syncthreads();
+    if (pack && tid < 64 && pk[tid]) atomicAdd(&a.bcnt[w * 64 + tid], pk[tid]);
     relax = group_sum<FWB_NT>(relax, L.red);
     trav = group_sum<FWB_NT>(trav, L.red);
     if (tid == 0) {
@@ -1097,37 +1140,10 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
 constexpr int PK_NT = 256;
 constexpr int PK_ZERO = 64 * 64 * 2 + 128;  // bcnt, bcur [W][64]; gcnt, mcnt [64]
 
-__global__ __launch_bounds__(PK_NT) void k_pack_count(const uint32_t *tnodes, const uint32_t *tcounts,
-                                                      const uint64_t *newly, uint32_t n,
-                                                      uint32_t *bcnt, uint32_t *mcnt, uint32_t *mlist)
-{
-    __shared__ uint32_t cnt[64];
-    const uint32_t w = blockIdx.y;
-    const uint64_t off = (uint64_t)w * n;
-    const uint32_t c = tcounts[w];
-    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t base = blockIdx.x * PK_NT; base < c; base += gridDim.x * PK_NT) {
-        const uint32_t i = base + threadIdx.x;
-        bool multi = false;
-        uint32_t x = 0;
-        if (i < c) {
-            x = tnodes[off + i];
-            const uint64_t b = newly[off + x];
-            if (__popcll(b) == 1) atomicAdd(&cnt[__ffsll((unsigned long long)b) - 1], 1u);
-            else multi = true;
-        }
-        const uint32_t p = wave_append(multi, &mcnt[w]);
-        if (multi) mlist[off + p] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < 64 && cnt[threadIdx.x]) atomicAdd(&bcnt[w * 64 + threadIdx.x], cnt[threadIdx.x]);
-}
-
 // Place the single-bit tasks bit by bit. Every workgroup of word w takes the
 // bit offsets as the exclusive prefix of that word's 64 bit counts (counted
-// by k_pack_count); workgroup 0 of the word also stores them, with the
-// largest count, for the reverse pass.
+// by the forward search as it finished); workgroup 0 of the word also stores
+// them, with the largest count, for the reverse pass.
 __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, const uint32_t *tcounts,
                                                      const uint64_t *newly, uint32_t n,
                                                      const uint32_t *bcnt, uint32_t *boff,
@@ -1929,6 +1945,9 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
     f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
     f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
+    uint32_t *bcnt = ws->pk, *bcur = ws->pk + 64 * 64, *gcnt = ws->pk + 2 * 64 * 64,
+             *mcnt = gcnt + 64;
+    f.bcnt = bcnt; f.mcnt = mcnt; f.mlist = ws->mlist;
     f.key = ws->keys + (uint64_t)t * ws->batch.count; f.t = t; f.b = ws->batch;
     f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
     f.stats = ws->stats;
@@ -1943,12 +1962,11 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
             return im_fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
     }
 
-    uint32_t *bcnt = ws->pk, *bcur = ws->pk + 64 * 64, *gcnt = ws->pk + 2 * 64 * 64,
-             *mcnt = gcnt + 64;
     {
+        // the forward search counted the single-bit sources per bit and
+        // listed the others
         PhaseTimer pt(ws, IM_PH_PACK, s);
         dim3 pg(grid_for(n, PK_NT, 64), W);
-        k_pack_count<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, mcnt, ws->mlist);
         k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, ws->boff,
                                          gcnt, bcur, ws->plist);
     }
@@ -2788,6 +2806,7 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
     f.fq0 = ws->fqa; f.fq1 = ws->fqb; f.cnt = ws->fctr + (uint64_t)t * FWD_CTRS;
     f.bq0 = ws->bqa; f.bq1 = ws->bqb; f.coop_gain = ws->coop_gain; f.vis = ws->fvis;
     f.tnodes = ws->tnodes; f.tcounts = ws->tcounts;
+    f.bcnt = nullptr; f.mcnt = nullptr; f.mlist = nullptr;
     f.key = ws->keys + t; f.t = t; f.b = ws->batch;
     f.seeds_out = seeds_out; f.gains_out = gains_out; f.sel = ws->sel;
     f.stats = ws->stats;
