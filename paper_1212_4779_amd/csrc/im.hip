@@ -1953,7 +1953,9 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     f.stats = ws->stats;
     {
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
-        if (ws->batch.count == 1) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
+        // (with a zero threshold every round is cooperative: the one-workgroup
+        // kernel would return at once)
+        if (ws->batch.count == 1 && ws->coop_gain > 0) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
         void *args[] = {&f};
         const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * W);
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
@@ -2812,7 +2814,7 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
     f.stats = ws->stats;
     {
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
-        k_forward_block<<<W, FWB_NT, 0, s>>>(f);
+        if (ws->coop_gain > 0) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
         void *args[] = {&f};
         const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * W);
         hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
