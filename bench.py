@@ -433,7 +433,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(snapshot words would shard over GPUs with one gain reduction per round; not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch512":
