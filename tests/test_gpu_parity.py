@@ -363,3 +363,28 @@ def test_batch_rejects_bad_instance(im):
     assert e.value.code == N.IM_EINVAL
     with pytest.raises(N.ImError):
         im.select_batch([(good, 64, 3, 1), (good, 0, 1, 1)])
+
+
+@pytest.mark.parametrize("R", [4096, 4033])
+def test_maximum_snapshot_count(im, R):
+    # R = IM_R_MAX (64 snapshot words) and a ragged last word: every round's
+    # gain vector, through the cooperative and the one-workgroup forward search
+    g = gg.chung_lu_graph(300, 1500, 2.5, 17, True, 0.1)
+    s_ref, g_ref, tr_ref, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, 6, 3, trace=True)
+    d = _dev(im, g)
+    for gain in (0, 1 << 62):
+        ws = im.Workspace()
+        ws.set_coop_gain(gain)
+        s, gn, tr = im.select(d, R, 6, 3, ws=ws, trace=True)
+        assert s.cpu().tolist() == s_ref.tolist() and gn.cpu().tolist() == g_ref.tolist(), gain
+        assert np.array_equal(tr.cpu().numpy(), tr_ref.astype(np.int64)), gain
+
+
+def test_maximum_snapshot_count_weighted_cascade(im):
+    # a supercritical weighted-cascade graph at R = IM_R_MAX: large reach sets
+    # in all 64 words (tier 2 and hub lists)
+    g = gg.chung_lu_graph(2000, 12000, 2.3, 18, True, None)
+    s_ref, g_ref, tr_ref, _ = oracle.select_du(g.row_ptr, g.col, g.prob, 4096, 4, 5, trace=True)
+    s, gn, tr = im.select(_dev(im, g), 4096, 4, 5, trace=True)
+    assert s.cpu().tolist() == s_ref.tolist() and gn.cpu().tolist() == g_ref.tolist()
+    assert np.array_equal(tr.cpu().numpy(), tr_ref.astype(np.int64))
