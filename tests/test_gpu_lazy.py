@@ -140,6 +140,8 @@ def _small_cases():
     out.append(("wc_R1", gg.chung_lu_graph(4000, 40000, 2.1, 9, True, None), 1, 15, 3))
     # k = n: the late rounds have only zero gains (lowest id first)
     out.append(("k_eq_n", gg.chung_lu_graph(60, 200, 2.5, 3, True, 0.2), 65, 60, 2))
+    # the maximum snapshot count (64 words)
+    out.append(("max_R", gg.chung_lu_graph(300, 1500, 2.5, 17, True, 0.1), 4096, 6, 3))
     return out
 
 

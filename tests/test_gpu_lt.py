@@ -71,6 +71,7 @@ def _cases():
          130, 8, 4),
         ("in_star_R1", _star_in(3000), 1, 5, 2),
         ("in_star_R256", _star_in(600), 256, 5, 9),
+        ("max_R", _random_weights(gg.chung_lu_graph(300, 1500, 2.5, 14, True, None), rng), 4096, 5, 7),
     ]
 
 

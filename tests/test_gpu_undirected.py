@@ -75,6 +75,7 @@ def _cases():
         ("mixed_p_R1", _sym(500, [(i, (i * 7 + 1) % 500) for i in range(499) if (i * 7 + 1) % 500 != i],
                             rng.uniform(0, 1, 499).astype(np.float32), loops=(3, 77)), 1, 30, 2),
         ("p1_two_paths", _sym(12, [(0, 1), (1, 2), (5, 6), (6, 7), (7, 8)], 1.0), 70, 12, 1),
+        ("max_R", gg.chung_lu_graph(400, 1600, 2.3, 33, False, 0.1), 4096, 6, 7),
     ]
 
 
