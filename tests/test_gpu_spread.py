@@ -46,6 +46,8 @@ def _cases():
         # more than 256 words: the evaluator runs several chunks of words
         ("small_uic_R20000", gg.chung_lu_graph(300, 1500, 2.5, 3, True, 0.08), 20000, 6,
          [1, 7, 7, 250, 0]),
+        # the evaluator's maximum R = 2^20 (16,384 words)
+        ("tiny_R2p20", gg.chung_lu_graph(60, 240, 2.5, 19, True, 0.15), 1 << 20, 3, [5, 0, 5, 17]),
     ]
 
 
