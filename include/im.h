@@ -87,8 +87,9 @@ int im_workspace_destroy(im_workspace *ws);
  *     middle engine tier: 0 (default) 4 x 256, 1: 2 x 512, 2: 1 x 1024; a
  *     task reaching more nodes than three quarters of its table moves on to
  *     the last tier.
- *   IM_OPT_TIER2_LANES: lanes per task of the last tier, 256 (default) or
- *     1024.
+ *   IM_OPT_TIER2_LANES: lanes per task of the last tier, 64, 256 (default)
+ *     or 1024 (64: more tasks at once, for long searches with small
+ *     frontiers).
  *   IM_OPT_SPARSE_LISTS: 1 (default) builds per-snapshot live lists of the
  *     nodes below the hub threshold as well, so that a node reached in at
  *     most two of a word's snapshots reads only its arcs live there; 0 reads

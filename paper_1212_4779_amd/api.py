@@ -102,7 +102,7 @@ class Workspace:
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER1_SHAPE, int(shape)))
 
     def set_tier2_lanes(self, lanes):
-        """Lanes per task of the last engine tier (256 or 1024). No result changes."""
+        """Lanes per task of the last engine tier (64, 256 or 1024). No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_TIER2_LANES, int(lanes)))
 
     def set_sparse_lists(self, on):

@@ -1221,6 +1221,7 @@ constexpr int T1_NT = 256, T1_T = 4, T1_CS = 256, T1_LIM = 192, T1_U = 4;
 // tier 2: dense global arrays
 constexpr int T2_NT = 256, T2_U = 8;
 constexpr int T2W_NT = 1024;   // the wide variant: more lanes per task
+constexpr int T2S_NT = 64;     // the narrow variant: more tasks at once (long, thin searches)
 // per-phase device counters: grab0, n1, grab1, n2, grab2
 constexpr int PH_CTRS = 8;
 // per-round forward counters: 3 frontier counts + one visit count per word
@@ -1236,7 +1237,7 @@ struct im_workspace {
     uint32_t max_slots = 256, slots_n = 0;  // tier-2: slot limit, length of each slot in use
     uint64_t slots_entries = 0;             // allocated slot entries
     int tier1_shape = 0;     // tier-1 tasks x table entries: 0: 4 x 256, 1: 2 x 512, 2: 1 x 1024
-    int tier2_wide = 0;      // 1024 lanes per tier-2 task instead of 256
+    uint32_t tier2_lanes = T2_NT;   // lanes per tier-2 task: 64, 256 or 1024
     uint64_t cap_m = 0;
     // graph-derived
     uint32_t *row32 = nullptr, *in_row = nullptr, *in_col = nullptr, *in2out = nullptr;
@@ -1901,8 +1902,10 @@ static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipSt
     a.out_q = nullptr; a.out_n = nullptr; a.grab = ctr + 4; a.tier = 2;
     {
         PhaseTimer pt(ws, ph0 + 2, s);
-        if (ws->tier2_wide)
+        if (ws->tier2_lanes == (uint32_t)T2W_NT)
             k_block_bfs<MODE, T2W_NT, T2_U, PRUNE><<<ws->slots, T2W_NT, 0, s>>>(a);
+        else if (ws->tier2_lanes == (uint32_t)T2S_NT)
+            k_block_bfs<MODE, T2S_NT, T2_U, PRUNE><<<ws->slots, T2S_NT, 0, s>>>(a);
         else
             k_block_bfs<MODE, T2_NT, T2_U, PRUNE><<<ws->slots, T2_NT, 0, s>>>(a);
     }
@@ -3351,8 +3354,9 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         ws->tier1_shape = (int)value;
         return IM_OK;
     case IM_OPT_TIER2_LANES:
-        if (value != 256 && value != 1024) return im_fail(IM_EINVAL, "tier-2 lanes must be 256 or 1024");
-        ws->tier2_wide = value == 1024;
+        if (value != T2S_NT && value != T2_NT && value != T2W_NT)
+            return im_fail(IM_EINVAL, "tier-2 lanes must be 64, 256 or 1024");
+        ws->tier2_lanes = (uint32_t)value;
         return IM_OK;
     case IM_OPT_SPARSE_LISTS:
         if (value != 0 && value != 1) return im_fail(IM_EINVAL, "sparse lists must be 0 or 1");
@@ -3560,7 +3564,7 @@ extern "C" int im_plan_create_batch(const im_instance *inst, uint32_t count, uin
         // copy the caller's engine schedule (e.g. set by im_autotune_batch)
         p->ws->hub_deg = tuned->hub_deg;
         p->ws->tier1_shape = tuned->tier1_shape;
-        p->ws->tier2_wide = tuned->tier2_wide;
+        p->ws->tier2_lanes = tuned->tier2_lanes;
         p->ws->max_slots = tuned->max_slots;
         p->ws->coop_gain = tuned->coop_gain;
         p->ws->sparse = tuned->sparse;
@@ -3621,7 +3625,8 @@ struct Schedule {
 static const Schedule kSchedules[] = {
     {256, 0, 256, 256, 1},  {256, 0, 1024, 256, 1}, {256, 0, 256, 2048, 1},
     {256, 0, 256, 1024, 1}, {256, 0, 1024, 1024, 1}, {256, 0, 1024, 256, 0},
-    {256, 0, 256, 2048, 0}, {256, 1, 1024, 256, 1},
+    {256, 0, 256, 2048, 0}, {256, 1, 1024, 256, 1}, {256, 0, 64, 8192, 1},
+    {256, 0, 64, 8192, 0},
 };
 constexpr int N_SCHEDULES = sizeof(kSchedules) / sizeof(kSchedules[0]);
 constexpr uint32_t TUNE_ROUNDS = 4;   // greedy rounds in a trial
@@ -3630,7 +3635,7 @@ static void apply_schedule(im_workspace *ws, const Schedule &c)
 {
     ws->hub_deg = (uint32_t)c.hub_degree;
     ws->tier1_shape = c.tier1_shape;
-    ws->tier2_wide = c.tier2_lanes == 1024;
+    ws->tier2_lanes = (uint32_t)c.tier2_lanes;
     ws->max_slots = (uint32_t)c.max_slots;
     ws->coop_gain = c.coop_forward ? 0ull : ~0ull;
 }

@@ -16,6 +16,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 SCHEDULES = [  # (hub degree, tier-1 shape, tier-2 lanes, tier-2 slots)
     (256, 0, 256, 256), (256, 1, 1024, 256), (256, 2, 256, 2048),
     (1024, 0, 256, 8), (0, 1, 1024, 8), (16, 2, 1024, 64),
+    (256, 0, 64, 8192), (16, 1, 64, 8),
 ]
 
 
@@ -66,7 +67,7 @@ def test_autotune_choice_and_cache(im):
     ws = im.Workspace()
     t = im.autotune(d, w["R"], w["seed"], ws=ws)
     assert t["tried"] >= 2 and t["ms"] > 0
-    assert t["tier1_shape"] in (0, 1, 2) and t["tier2_lanes"] in (256, 1024)
+    assert t["tier1_shape"] in (0, 1, 2) and t["tier2_lanes"] in (64, 256, 1024)
     seeds, gains, _ = im.select(d, w["R"], w["k"], w["seed"], ws=ws)
     assert seeds.cpu().tolist() == gold["seeds"]
     assert gains.cpu().tolist() == gold["gains"]
