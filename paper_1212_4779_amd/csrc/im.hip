@@ -1285,7 +1285,7 @@ struct im_workspace {
     unsigned long long *sp_alloc = nullptr;  // [2]
     unsigned long long *halloc = nullptr;  // [2] allocation counters
     // block engine slots
-    uint64_t *b_reach = nullptr, *b_pend = nullptr;
+    uint64_t *b_reach = nullptr;   // tier-2 slots: (reach, pend) per node, interleaved
     uint32_t *b_qa = nullptr, *b_qb = nullptr, *b_vis = nullptr;
     // lazy evaluation (A9)
     uint32_t cap_celf = 0;
@@ -1426,7 +1426,7 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     dfree(ws->fpend); dfree(ws->fqa); dfree(ws->fqb); dfree(ws->fvis); dfree(ws->bqa); dfree(ws->bqb); dfree(ws->fctr);
     dfree(ws->pk); dfree(ws->boff); dfree(ws->plist); dfree(ws->mlist);
     dfree(ws->tnodes); dfree(ws->tcounts); dfree(ws->keys); dfree(ws->ovf_q); dfree(ws->ovf_q2); dfree(ws->ctrs);
-    dfree(ws->b_reach); dfree(ws->b_pend);
+    dfree(ws->b_reach);
     dfree(ws->b_qa); dfree(ws->b_qb); dfree(ws->b_vis);
     for (int d = 0; d < 2; d++) {
         dfree(ws->hslot[d]); dfree(ws->hlist[d]); dfree(ws->hcnt[d]); dfree(ws->hoff[d]);
@@ -1478,12 +1478,11 @@ static int reserve_slots(im_workspace *ws, uint32_t slot_len)
     const uint32_t slots = slots_for(slot_len, ws->max_slots);
     const uint64_t sn = (uint64_t)slots * slot_len;
     if (sn > ws->slots_entries) {
-        if ((rc = dalloc(&ws->b_reach, sn)) || (rc = dalloc(&ws->b_pend, sn)) ||
+        if ((rc = dalloc(&ws->b_reach, 2 * sn)) ||
             (rc = dalloc(&ws->b_qa, sn)) || (rc = dalloc(&ws->b_qb, sn)) ||
             (rc = dalloc(&ws->b_vis, sn)))
             return rc;
-        HIPCHK(hipMemset(ws->b_reach, 0, sn * sizeof(uint64_t)));
-        HIPCHK(hipMemset(ws->b_pend, 0, sn * sizeof(uint64_t)));
+        HIPCHK(hipMemset(ws->b_reach, 0, 2 * sn * sizeof(uint64_t)));
         ws->slots_entries = sn;
     }
     ws->slots = slots;
@@ -1846,7 +1845,7 @@ static BfsArgs bfs_args(im_workspace *ws, const uint32_t *row, const uint32_t *c
     a.node_inst = ws->batch.node_inst; a.inst_R = ws->batch.R; a.inst_off = ws->batch.node_off;
     a.slot_n = ws->slots_n;
     a.gain = ws->gain;
-    a.b_reach = ws->b_reach; a.b_pend = ws->b_pend;
+    a.b_reach = ws->b_reach;
     a.b_qa = ws->b_qa; a.b_qb = ws->b_qb; a.b_vis = ws->b_vis;
     a.stats = ws->stats;
     return a;

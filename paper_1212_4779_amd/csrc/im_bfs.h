@@ -175,7 +175,7 @@ struct BfsArgs {
     uint32_t *out_n;
     uint32_t *grab;           // task counter of this launch (zero before launch)
     // global-engine slots
-    uint64_t *b_reach, *b_pend;            // [slots][slot_n], indexed by node - base
+    uint64_t *b_reach;                     // [slots][slot_n][2]: (reach, pend) of node - base
     uint32_t *b_qa, *b_qb, *b_vis;         // [slots][slot_n], node ids
     unsigned long long *stats;
     int pass, tier;
@@ -735,16 +735,20 @@ struct BlockLds {
     HubBatch<NT, 16> H;
 };
 
-// reach and pend are indexed by v - base (the task's instance's first node)
+// reach and pend are indexed by (v - base) * S (base: the task's instance's
+// first node); S = 2 with pend = reach + 1 keeps a node's two words in one
+// 16-byte record, so a relaxation touches one cache line
+template <int S = 1>
 __device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, uint32_t base,
                                              uint32_t *vis, uint32_t *nxt, uint32_t *nvis,
                                              uint32_t *nn, uint32_t v, uint64_t bits)
 {
-    uint64_t old = atomicOr((unsigned long long *)&reach[v - base], (unsigned long long)bits);
+    const uint64_t i = (uint64_t)(v - base) * S;
+    uint64_t old = atomicOr((unsigned long long *)&reach[i], (unsigned long long)bits);
     uint64_t nb = bits & ~old;
     if (!nb) return;
     if (old == 0) vis[atomicAdd(nvis, 1u)] = v;
-    uint64_t op = atomicOr((unsigned long long *)&pend[v - base], (unsigned long long)nb);
+    uint64_t op = atomicOr((unsigned long long *)&pend[i], (unsigned long long)nb);
     if (op == 0) nxt[atomicAdd(nn, 1u)] = v;
 }
 
@@ -752,7 +756,7 @@ __device__ __forceinline__ void global_relax(uint64_t *reach, uint64_t *pend, ui
 // with reach != 0. Each thread passes its own seed (src, start); start = 0
 // means none. Every node the task can reach is >= base, and reach / pend
 // hold the nodes from base on. All threads of the workgroup must call it.
-template <int NT, int U, bool PRUNE, bool SPARSE = true>
+template <int NT, int U, bool PRUNE, bool SPARSE = true, int S = 1>
 __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                               const uint32_t *row, const uint32_t *col, const uint64_t *mask,
                               const HubLists &hub, const SparseLists &sp, uint32_t n,
@@ -766,7 +770,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
     if (tid == 0) { L.nf = 0; L.nn = 0; L.nvis = 0; L.H.n = 0; L.levels = 0; L.entries = 0; }
     __syncthreads();
     // seeds: every lane with start bits (lanes 0..63 for multi-source tasks)
-    if (start) global_relax(reach, pend, base, vis, qa, &L.nvis, &L.nf, src, start);
+    if (start) global_relax<S>(reach, pend, base, vis, qa, &L.nvis, &L.nf, src, start);
     __syncthreads();
     uint32_t *cur = qa, *nxt = qb;
     for (;;) {
@@ -782,7 +786,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 rs = row[x];
                 deg = row[x + 1] - rs;
                 // bits gained since the last expansion (later ones re-queue x)
-                d = atomicExch((unsigned long long *)&pend[x - base], 0ull);
+                d = atomicExch((unsigned long long *)&pend[(uint64_t)(x - base) * S], 0ull);
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, 0u, d);
                     deg = 0; d = 0;
@@ -839,7 +843,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (bb[u]) global_relax(reach, pend, base, vis, nxt, &L.nvis, &L.nn, vv[u], bb[u]);
+                    if (bb[u]) global_relax<S>(reach, pend, base, vis, nxt, &L.nvis, &L.nn, vv[u], bb[u]);
             }
             __syncthreads();
             // hub expansions of this tile: only the arcs live in the delta's snapshots
@@ -848,7 +852,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 auto relax = [&](uint32_t, uint32_t v, uint64_t bits) {
                     if (!bits) return;
                     if (PRUNE) bits &= ~prune[v];
-                    if (bits) global_relax(reach, pend, base, vis, nxt, &L.nvis, &L.nn, v, bits);
+                    if (bits) global_relax<S>(reach, pend, base, vis, nxt, &L.nvis, &L.nn, v, bits);
                 };
                 expand_hubs<NT, 16, U>(L.H, nhub, hub, W, word_of, relax, [] {}, arcs);
             }
@@ -866,8 +870,9 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     __shared__ uint32_t wpre[65];
     const int tid = threadIdx.x;
     const uint64_t slot = blockIdx.x;
-    uint64_t *reach = a.b_reach + slot * a.slot_n;
-    uint64_t *pend = a.b_pend + slot * a.slot_n;
+    // the slot's (reach, pend) records, interleaved
+    uint64_t *reach = a.b_reach + slot * a.slot_n * 2;
+    uint64_t *pend = reach + 1;
     uint32_t *qa = a.b_qa + slot * a.slot_n;
     uint32_t *qb = a.b_qb + slot * a.slot_n;
     uint32_t *vis = a.b_vis + slot * a.slot_n;
@@ -909,21 +914,21 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
                 src = L.gsrc[tid]; bits = L.gbits[tid];
             }
             const uint32_t base = split ? a.inst_off[a.node_inst[src0]] : 0u;
-                block_bfs_run<NT, U, PRUNE>(L, src, bits, a.row, a.col, mask, a.hub, a.sp, a.n, a.W, w, prune,
+                block_bfs_run<NT, U, PRUNE, true, 2>(L, src, bits, a.row, a.col, mask, a.hub, a.sp, a.n, a.W, w, prune,
                                         reach, pend, base, qa, qb, vis, arcs);
             const uint32_t nvis = L.nvis;
             levels += L.levels;
             uint64_t cnt = 0;
             for (uint32_t i = tid; i < nvis; i += NT) {
                 uint32_t x = vis[i];
-                uint32_t pc = (uint32_t)__popcll(reach[x - base]);
+                uint32_t pc = (uint32_t)__popcll(reach[(uint64_t)(x - base) * 2]);
                 uint32_t dg = a.row[x + 1] - a.row[x];
                 relax += dg;
                 reached += 1;
                 trav += (uint64_t)pc * dg;
                 if (MODE == MODE_COUNT) cnt += pc;
                 else { atomicSub(&a.gain[x], pc); dec += pc; }
-                reach[x - base] = 0;
+                reach[(uint64_t)(x - base) * 2] = 0;   // pend is zero at the fixpoint
             }
             if (MODE == MODE_COUNT) {
                 cnt = group_sum<NT>(cnt, L.red);
