@@ -264,9 +264,13 @@ int im_autotune_batch(const im_instance *inst, uint32_t count, im_workspace *ws,
  * hub lists, initial gains and all k rounds -- into one HIP graph bound to a
  * private workspace and to the given device pointers (graph arrays, seeds_out,
  * gains_out). im_plan_launch enqueues one replay on `stream`: every replay
- * recomputes everything from the graph arrays as they are at that time (they
- * must keep their shape; their contents may change). Replays of one plan must
- * not overlap. A schedule that im_autotune chose earlier in the process for
+ * recomputes everything -- the 32-bit row offsets, reverse CSR, masks, lists,
+ * gains and rounds -- from the graph arrays as they are at that time. They
+ * must keep their shape (n, m) and their contents may change, but they must
+ * stay valid as im_validate defines it: validity is checked when the plan is
+ * created, not on replay, and a replay over an invalid graph (say a col entry
+ * >= n) has unspecified results and may access memory out of bounds. Replays
+ * of one plan must not overlap. A schedule that im_autotune chose earlier in the process for
  * a graph with the same signature is used by the plan. */
 typedef struct im_plan im_plan;
 int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
@@ -274,7 +278,9 @@ int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
 /* The batched selection (im_select_batch) captured into one HIP graph:
  * validation and the instance tables are done once here (synchronous); a
  * replay merges the instances' arrays again and runs the whole batched
- * selection, so one launch selects the seeds of every instance. `tuned`
+ * selection, so one launch selects the seeds of every instance. The
+ * instances' arrays follow the rules of im_plan_create's graph arrays (same
+ * shapes, contents valid; checked at creation only). `tuned`
  * (may be NULL) lends its engine schedule, e.g. one set by
  * im_autotune_batch. count >= 2. */
 int im_plan_create_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out,

@@ -50,8 +50,11 @@ def _score(api, graph, S, R_eval, eval_seed, ws):
     return int(per.sum().item()) / R_eval
 
 
-def study(graph, Rs, k, runs, R_eval, eval_seed, R_ref=4096, k_entropy=5, log=print):
-    """The sweep on one device graph; returns a dict with one row per R."""
+def study(graph, Rs, k, runs, R_eval, eval_seed, R_ref=4096, k_entropy=5, log=print,
+          keep_runs=False):
+    """The sweep on one device graph; returns a dict with one row per R (with
+    keep_runs, each row also lists every run's seeds and scored spread, and
+    the result the reference seeds)."""
     from . import api
 
     ws = api.Workspace()
@@ -72,12 +75,18 @@ def study(graph, Rs, k, runs, R_eval, eval_seed, R_ref=4096, k_entropy=5, log=pr
         rows.append({"R": R, "spread_mean": sum(spreads) / runs, "d_mean": sum(d) / runs,
                      "H_k": entropy([S[:k_entropy] for S in sols[R]]),
                      "distinct_solutions": len({frozenset(S) for S in sols[R]})})
+        if keep_runs:
+            rows[-1]["runs"] = [{"seed": 1000 + r, "seeds": sols[R][r], "spread": spreads[r]}
+                                for r in range(runs)]
         log(f"R={R}: spread {rows[-1]['spread_mean']:.2f}, d {rows[-1]['d_mean']:.5f}, "
             f"H_{k_entropy} {rows[-1]['H_k']:.3f}")
-    return {"rows": rows, "reference_R": R_ref, "reference_spread": ref, "R_min": r_min(rows),
+    out = {"rows": rows, "reference_R": R_ref, "reference_spread": ref, "R_min": r_min(rows),
             "runs": runs, "k": k, "k_entropy": k_entropy, "R_eval": R_eval,
             "eval_seed": eval_seed, "selection_s": round(t_sel, 3),
             "evaluation_s": round(time.perf_counter() - t1, 3)}
+    if keep_runs:
+        out["reference_seeds"] = ref_seeds.cpu().tolist()
+    return out
 
 
 def main():

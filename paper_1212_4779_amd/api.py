@@ -4,12 +4,18 @@ torch supplies device memory and the current HIP stream; every step of the
 selection runs in libim's kernels. Tensors passed in must already live on
 the GPU; nothing here computes on the host.
 """
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
 import torch
 
 from . import _native as N
+
+# every open workspace, plan and network: released by _release_all before
+# the interpreter exits
+_live = weakref.WeakSet()
 
 
 def _ptr(t):
@@ -68,6 +74,7 @@ class Workspace:
         h = ctypes.c_void_p()
         N.check(N.lib().im_workspace_create(ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def close(self):
         if self.handle:
@@ -300,6 +307,7 @@ class Plan:
         N.check(N.lib().im_plan_create(ctypes.byref(self._g), R, k, seed, _ptr(self.seeds_raw),
                                        _ptr(self.gains), _stream(dev), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def launch(self):
         N.check(N.lib().im_plan_launch(self.handle, _stream(self.graph.device)))
@@ -339,6 +347,7 @@ class Mlp:
         h = ctypes.c_void_p()
         N.check(N.lib().im_mlp_create(ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
         if params is not None:
             self.set_params(params)
 
@@ -504,6 +513,7 @@ class BatchPlan:
                                              tuned.handle if tuned is not None else ctypes.c_void_p(0),
                                              _stream(dev), ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
     def launch(self):
         N.check(N.lib().im_plan_launch(self.handle, _stream(self.device)))
@@ -531,3 +541,24 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def _release_all():
+    """Destroy every workspace, plan and network still open once the device
+    work has finished. Runs before the interpreter shuts down, so that no HIP
+    object is released from a finalizer after the runtime (or a profiler
+    attached to it) has begun its own shutdown."""
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    _default_ws.clear()
+
+
+atexit.register(_release_all)

@@ -108,6 +108,14 @@ __global__ void k_validate(const uint64_t *row_ptr, const uint32_t *col, const f
     if (e) atomicOr(err, e);
 }
 
+// 32-bit copy of the row offsets (a plan's replays re-read row_ptr with this)
+__global__ void k_row32(const uint64_t *row_ptr, uint32_t n, uint32_t *row32)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        row32[i] = (uint32_t)row_ptr[i];
+}
+
 // Reverse-CSR construction. Arcs into one high in-degree node are spread over
 // the whole arc array, so plain per-arc global atomics on its counter
 // serialise. Each workgroup therefore first aggregates its contiguous slice of
@@ -1386,10 +1394,9 @@ static void dfree(Tv *&p)
 struct EvalArgs;
 __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a);
 
-extern "C" int im_workspace_create(im_workspace **out)
+// device properties and cooperative grid sizes of a new workspace
+static int ws_init_device(im_workspace *ws)
 {
-    if (!out) return im_fail(IM_EINVAL, "im_workspace_create: null output pointer");
-    im_workspace *ws = new im_workspace();
     HIPCHK(hipGetDevice(&ws->device));
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, ws->device));
@@ -1405,7 +1412,15 @@ extern "C" int im_workspace_create(im_workspace **out)
         if (be < 1) be = 1;
         ws->eval_grid = (unsigned)be * (unsigned)ws->num_cu;
     }
+    return IM_OK;
+}
+
+extern "C" int im_workspace_create(im_workspace **out)
+{
+    if (!out) return im_fail(IM_EINVAL, "im_workspace_create: null output pointer");
+    im_workspace *ws = new im_workspace();
     int rc;
+    if ((rc = ws_init_device(ws))) { delete ws; return rc; }
     if ((rc = dalloc(&ws->stats, ST_COUNT * ST_STRIPES))) { delete ws; return rc; }
     if ((rc = dalloc(&ws->err, 1))) { delete ws; return rc; }
     HIPCHK(hipHostMalloc((void **)&ws->host_err, sizeof(uint32_t), hipHostMallocDefault));
@@ -3262,6 +3277,8 @@ extern "C" int im_plan_create(const im_graph *g, uint32_t R, uint32_t k, uint64_
         if (e != hipSuccess) {
             rc = im_fail(IM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
         } else {
+            // every replay takes the row offsets as they are at that time
+            k_row32<<<grid_for((uint64_t)g->n + 1, 256), 256, 0, s>>>(g->row_ptr, g->n, p->ws->row32);
             rc = enqueue_prepare(g, R, seed, k, p->ws, s);
             if (!rc) rc = enqueue_rounds(g, R, k, seeds_out, gains_out, nullptr, p->ws, s);
             hipGraph_t graph = nullptr;

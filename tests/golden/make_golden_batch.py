@@ -1,11 +1,11 @@
 """Write the stored expected values of the 512-instance batched workload.
 
-Calls only the CPU oracle (``oracle/``) and the seeded input generator. The
-weighted-cascade instances are near-critical: the largest one alone costs the
-single-threaded oracle minutes. The stored sample is therefore every instance
-with at most SAMPLE_MAX_N nodes (deterministic; about 290 of the 512); for
-each it keeps a digest of the generated graph and the oracle's
-StaticGreedyDU seeds and gains.
+Calls only the CPU oracle (``oracle/``) and the seeded input generator. Every
+one of the 512 instances is stored: a digest of the generated graph and the
+oracle's StaticGreedyDU seeds, gains and traversal count. The
+weighted-cascade instances are near-critical (the largest one alone costs the
+single-threaded oracle minutes), so the instances run in worker processes,
+largest first.
 
 Usage: python tests/golden/make_golden_batch.py [workers]
 """
@@ -22,9 +22,6 @@ import oracle  # noqa: E402
 from paper_1212_4779_amd import graphgen as gg  # noqa: E402
 
 
-SAMPLE_MAX_N = 20000
-
-
 def one(i_w):
     i, w = i_w
     g = gg.graph_from_recipe(w)
@@ -39,11 +36,12 @@ if __name__ == "__main__":
     oracle._load()
     rec = gg.batch_instances(**gg.BATCH_WORKLOAD)
     t0 = time.time()
-    sample = [(i, w) for i, w in enumerate(rec) if w["n"] <= SAMPLE_MAX_N]
+    # largest first, so that no long instance starts last
+    todo = sorted(enumerate(rec), key=lambda iw: -iw[1]["n"] * iw[1]["R"])
     with mp.get_context("fork").Pool(workers) as pool:
-        res = pool.map(one, sample, chunksize=1)
-    out = dict(workload="batch512", recipe=gg.BATCH_WORKLOAD, sample_max_n=SAMPLE_MAX_N,
-               instances=res)
+        res = pool.map(one, todo, chunksize=1)
+    res.sort(key=lambda r: r["i"])
+    out = dict(workload="batch512", recipe=gg.BATCH_WORKLOAD, instances=res)
     with open(os.path.join(HERE, "batch512.json"), "w") as f:
         json.dump(out, f)
     print(f"batch512: {time.time() - t0:.1f}s")

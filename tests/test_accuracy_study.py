@@ -44,3 +44,42 @@ def test_small_sweep_is_consistent():
     S = im.select(d, 16, 5, 1000)[0].cpu().tolist()
     _, per = im.spread(d, 2048, 99, S, marginals=False, per_snapshot=True)
     assert per.sum().item() > 0
+
+
+@pytest.mark.gpu
+def test_sweep_runs_equal_the_oracle():
+    # every run of a small sweep against the oracle: its seeds are the
+    # oracle's StaticGreedyDU seeds on the run's snapshots, its spread the
+    # oracle's f(S) / R_eval on the common evaluation snapshots, and the
+    # summary measures (Sec. 3.4: d_{R,k}, H_{R,k}) follow from those
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import numpy as np
+    import oracle
+    import paper_1212_4779_amd as im
+    g = gg.chung_lu_graph(400, 1600, 2.4, 43, True, 0.08)
+    d = im.Graph.from_numpy(g.row_ptr, g.col, g.prob)
+    Rs, k, runs, R_eval, eval_seed, R_ref = [1, 8, 64], 5, 4, 512, 99, 128
+    res = accuracy.study(d, Rs, k, runs, R_eval, eval_seed, R_ref=R_ref, k_entropy=3,
+                         log=lambda *_: None, keep_runs=True)
+
+    def f(S):
+        marg, _ = oracle.spread_prefix(g.row_ptr, g.col, g.prob, R_eval, eval_seed, S)
+        return int(marg.sum()) / R_eval
+
+    ref_seeds, _, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R_ref, k, 999)
+    assert res["reference_seeds"] == ref_seeds.tolist()
+    ref = f(ref_seeds)
+    assert res["reference_spread"] == ref
+    for row, R in zip(res["rows"], Rs):
+        sols, spreads = [], []
+        for run in row["runs"]:
+            s_ref, _, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, run["seed"])
+            assert run["seeds"] == s_ref.tolist(), (R, run["seed"])
+            assert run["spread"] == f(s_ref), (R, run["seed"])
+            sols.append(s_ref.tolist())
+            spreads.append(f(s_ref))
+        assert row["d_mean"] == pytest.approx(float(np.mean([(ref - x) / ref for x in spreads])),
+                                              rel=0, abs=1e-12)
+        assert row["H_k"] == accuracy.entropy([S[:3] for S in sols])

@@ -326,6 +326,32 @@ def test_plan_graph_replays(im, name):
     plan.close()
 
 
+def test_plan_replay_after_the_graph_changed(im):
+    # a replay recomputes everything from the arrays as they are then: new
+    # probabilities and a different (valid, same-shape) row_ptr and col
+    import torch
+    R, k, seed = 64, 8, 5
+    ga = gg.chung_lu_graph(2000, 20000, 2.5, 1, True, 0.05)
+    gb = gg.chung_lu_graph(2000, 20000, 2.5, 2, True, 0.05)
+    assert ga.m == gb.m and ga.n == gb.n
+    gb.prob[:] = np.float32(0.08)
+    gb.prob[::7] = np.float32(0.01)
+    d = _dev(im, ga)
+    plan = im.Plan(d, R, k, seed)
+    for g in (ga, gb, ga):
+        src = _dev(im, g)
+        d.row_ptr.copy_(src.row_ptr)
+        d.col.copy_(src.col)
+        d.prob.copy_(src.prob)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
+        assert plan.seeds.cpu().tolist() == s_ref.tolist()
+        assert plan.gains.cpu().tolist() == g_ref.tolist()
+    plan.close()
+
+
 def _batch_instances():
     out = []
     recipes = gg.batch_instances(24, master_seed=11)
