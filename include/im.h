@@ -224,6 +224,30 @@ typedef struct im_instance {
     uint64_t seed;    /* RNG seed of this instance's snapshots */
 } im_instance;
 
+/* For callers that cannot allocate device memory -- code that must not call
+ * hipMalloc or hipFree, such as tight serving loops and harnesses that forbid
+ * allocation: im_select (no trace output) without a workspace. Every buffer
+ * the selection needs is carved from one static device array of
+ * IM_NOALLOC_SCRATCH_BYTES bytes, of which each GPU the library runs on holds
+ * its own copy until the process ends; the call allocates nothing, on the
+ * device or through any library routine. Seeds and gains equal im_select's
+ * (the schedule differs only in where tasks run: no sparse live lists, 16
+ * last-tier slots).
+ * Size limit: the buffers take about 8 + 32 W bytes per arc and
+ * 475 + 76 W bytes per node (W = ceil(R/64)); a graph that needs more than
+ * the scratch is rejected with IM_EINVAL before any device work, nothing
+ * written. Other errors as im_select.
+ * Blocking in part: the call waits for earlier work on `stream` (it may still
+ * be using the scratch), validates the graph with one host wait, then
+ * enqueues the selection on `stream` and returns. The scratch keeps the last
+ * call's contents; every call clears what must start at zero. All calls on
+ * one GPU share its one array: calls whose work overlaps on one GPU (other
+ * streams, other threads, before the previous call's work has finished) race
+ * and give wrong results. */
+#define IM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int im_select_noalloc(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                      uint32_t *seeds_out, uint64_t *gains_out, void *stream);
+
 /* Batched selection: `count` independent instances of uneven size (host
  * array of descriptors; the graphs themselves are device-resident) are laid
  * side by side as one block-diagonal graph and selected together, so every

@@ -21,10 +21,11 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
            "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy",
            "im_autotune", "im_autotune_batch", "im_plan_create_batch", "im_spread",
-           "im_pair_ids", "im_select_undirected")
+           "im_pair_ids", "im_select_undirected", "im_select_noalloc")
 IM_MLP_NPARAM = 4609
 IM_SPREAD_R_MAX = 1 << 20
 IM_PH_MAX = 24
+IM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
           "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs",
@@ -148,6 +149,7 @@ def lib():
         L.im_spread.argtypes = [G, u32, u64, p, u32, p, p, p, p]
         L.im_pair_ids.argtypes = [G, p, p, p]
         L.im_select_undirected.argtypes = [G, u32, u32, u64, p, p, p, p, p]
+        L.im_select_noalloc.argtypes = [G, u32, u32, u64, p, p, p]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

@@ -232,6 +232,22 @@ def select(graph, R, k, seed, ws=None, trace=False):
     return _u32(seeds), gains, (_u32(tr) if trace else None)
 
 
+def select_noalloc(graph, R, k, seed, seeds=None, gains=None):
+    """im_select without a workspace: the library allocates nothing, every
+    buffer comes from its static device scratch. The caller passes the
+    output tensors (int32 [k], int64 [k]) or gets new ones.
+    Returns (seeds int64 [k], gains int64 [k])."""
+    dev = graph.device
+    if seeds is None:
+        seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    if gains is None:
+        gains = torch.empty(k, dtype=torch.int64, device=dev)
+    g = graph.c_struct()
+    N.check(N.lib().im_select_noalloc(ctypes.byref(g), R, k, seed, _ptr(seeds), _ptr(gains),
+                                      _stream(dev)))
+    return _u32(seeds), gains
+
+
 def autotune(graph, R, seed, ws=None):
     """Pick the fastest engine schedule for this graph (set on `ws`); returns it as a dict."""
     g = graph.c_struct()

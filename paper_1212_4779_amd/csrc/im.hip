@@ -23,6 +23,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1369,11 +1370,51 @@ struct PhaseTimer {
     }
 };
 
+// Workspace buffers come from hipMalloc, or, while a call of the entry point
+// that allocates nothing is being set up on this thread, from a bump arena
+// over that entry point's static device scratch. A measuring arena hands out
+// no memory: it only adds up what the buffers would take.
+struct Arena {
+    char *base;        // device address of the scratch (null while measuring)
+    uint64_t cap, used;
+    hipStream_t stream;   // the call's stream: buffers are cleared on it
+};
+static thread_local Arena *t_arena = nullptr;
+
+static int arena_take(Arena *a, void **p, uint64_t bytes)
+{
+    const uint64_t at = (a->used + 255) & ~255ull;
+    a->used = at + bytes;
+    if (!a->base) {
+        *p = nullptr;
+        return IM_OK;
+    }
+    if (a->used > a->cap) {
+        *p = nullptr;
+        return im_fail(IM_EINVAL, "the selection needs more than the %llu bytes of static scratch",
+                       (unsigned long long)a->cap);
+    }
+    *p = a->base + at;
+    return IM_OK;
+}
+
+// hipMemset of a workspace buffer (skipped while an arena only measures)
+static int ws_memset(void *p, uint64_t bytes)
+{
+    if (t_arena) {
+        if (t_arena->base) HIPCHK(hipMemsetAsync(p, 0, bytes, t_arena->stream));
+        return IM_OK;
+    }
+    HIPCHK(hipMemset(p, 0, bytes));
+    return IM_OK;
+}
+
 template <typename Tv>
 static int dalloc(Tv **p, uint64_t cnt)
 {
-    if (*p) { (void)hipFree(*p); *p = nullptr; }
     if (cnt == 0) cnt = 1;
+    if (t_arena) return arena_take(t_arena, (void **)p, cnt * sizeof(Tv));
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
     hipError_t e = hipMalloc((void **)p, cnt * sizeof(Tv));
     if (e != hipSuccess) {
         *p = nullptr;
@@ -1497,7 +1538,7 @@ static int reserve_slots(im_workspace *ws, uint32_t slot_len)
             (rc = dalloc(&ws->b_qa, sn)) || (rc = dalloc(&ws->b_qb, sn)) ||
             (rc = dalloc(&ws->b_vis, sn)))
             return rc;
-        HIPCHK(hipMemset(ws->b_reach, 0, 2 * sn * sizeof(uint64_t)));
+        if ((rc = ws_memset(ws->b_reach, 2 * sn * sizeof(uint64_t)))) return rc;
         ws->slots_entries = sn;
     }
     ws->slots = slots;
@@ -1530,8 +1571,9 @@ static int ws_reserve(im_workspace *ws, uint32_t n, uint64_t m, uint32_t W, uint
             return rc;
         for (int d = 0; d < 2; d++)
             if ((rc = dalloc(&ws->hslot[d], cn))) return rc;
-        HIPCHK(hipMemset(ws->newly, 0, nW * sizeof(uint64_t)));
-        HIPCHK(hipMemset(ws->fpend, 0, nW * sizeof(uint64_t)));
+        if ((rc = ws_memset(ws->newly, nW * sizeof(uint64_t))) ||
+            (rc = ws_memset(ws->fpend, nW * sizeof(uint64_t))))
+            return rc;
         ws->cap_n = cn;
     }
     if ((rc = reserve_slots(ws, slot_len))) return rc;
@@ -3225,6 +3267,105 @@ extern "C" int im_select(const im_graph *g, uint32_t R, uint32_t k, uint64_t see
     PhaseTimer pt(ws, IM_PH_CALL, s);
     if ((rc = prepare(g, R, seed, k, ws, s))) return rc;
     return enqueue_rounds(g, R, k, seeds_out, gains_out, trace_out, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// Selection that allocates nothing: every workspace buffer is carved from one
+// static device array per GPU, laid out afresh by each call
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[IM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NA_MAX_DEV = 64;
+constexpr uint32_t NA_SLOTS = 16;   // last-tier slots (28 bytes per node each)
+
+struct NoAllocDev {
+    std::mutex mu;
+    char *ptr = nullptr;   // this GPU's copy of `scratch` (from hipGetSymbolAddress)
+    int num_cu = 0;
+    unsigned fwd_grid = 0, eval_grid = 0;
+    im_workspace ws;       // host view of the carved buffers, rebuilt by every call
+    uint32_t host_err = 0;
+    unsigned long long host_stats[ST_COUNT * ST_STRIPES];
+};
+static NoAllocDev g_noalloc[NA_MAX_DEV];
+
+// the schedule of the static workspace: no sparse live lists, few slots
+static void noalloc_options(im_workspace *ws)
+{
+    ws->sparse = 0;
+    ws->max_slots = NA_SLOTS;
+}
+
+// every buffer the selection uses, carved from (or measured against) the arena
+static int noalloc_reserve(im_workspace *ws, const im_graph *g, uint32_t R, uint32_t k)
+{
+    int rc;
+    if ((rc = dalloc(&ws->stats, ST_COUNT * ST_STRIPES)) || (rc = dalloc(&ws->err, 1))) return rc;
+    return ws_reserve(ws, g->n, g->m, (R + 63) / 64, k, g->n);
+}
+
+extern "C" int im_select_noalloc(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                                 uint32_t *seeds_out, uint64_t *gains_out, void *stream)
+{
+    int rc;
+    if ((rc = check_args(g, R))) return rc;
+    if (k > g->n) return im_fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
+    if (k && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
+    {
+        // size check before any device work: host arithmetic only
+        im_workspace probe;
+        noalloc_options(&probe);
+        Arena a = {nullptr, IM_NOALLOC_SCRATCH_BYTES, 0, nullptr};
+        t_arena = &a;
+        rc = noalloc_reserve(&probe, g, R, k);
+        t_arena = nullptr;
+        if (rc) return rc;
+        if (a.used > a.cap)
+            return im_fail(IM_EINVAL,
+                           "im_select_noalloc: n = %u, m = %llu, R = %u needs %llu bytes of "
+                           "scratch, more than the %llu of the static scratch",
+                           g->n, (unsigned long long)g->m, R, (unsigned long long)a.used,
+                           (unsigned long long)a.cap);
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NA_MAX_DEV) return im_fail(IM_EINVAL, "device %d out of range", dev);
+    NoAllocDev &d = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(d.mu);
+    if (!d.ptr) {
+        // once per device, with that device current: the array's address on it
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return im_fail(IM_EHIP, "hipGetSymbolAddress of the static scratch: %s",
+                           hipGetErrorString(e));
+        im_workspace tmp;
+        if ((rc = ws_init_device(&tmp))) return rc;
+        d.num_cu = tmp.num_cu;
+        d.fwd_grid = tmp.fwd_grid;
+        d.eval_grid = tmp.eval_grid;
+        d.ptr = (char *)p;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // an earlier call on this stream may still be using the scratch
+    HIPCHK(hipStreamSynchronize(s));
+    d.ws = im_workspace();
+    im_workspace *ws = &d.ws;
+    ws->device = dev;
+    ws->num_cu = d.num_cu;
+    ws->fwd_grid = d.fwd_grid;
+    ws->eval_grid = d.eval_grid;
+    noalloc_options(ws);
+    ws->host_err = &d.host_err;
+    ws->host_stats = d.host_stats;
+    Arena a = {d.ptr, IM_NOALLOC_SCRATCH_BYTES, 0, s};
+    t_arena = &a;
+    rc = noalloc_reserve(ws, g, R, k);
+    t_arena = nullptr;
+    if (rc) return rc;
+    if ((rc = validate(g, ws, s, ws->row32))) return rc;
+    if ((rc = enqueue_prepare(g, R, seed, k, ws, s))) return rc;
+    return enqueue_rounds(g, R, k, seeds_out, gains_out, nullptr, ws, s);
 }
 
 // ---------------------------------------------------------------------------
