@@ -76,10 +76,15 @@ int im_workspace_destroy(im_workspace *ws);
  *     least this value run the forward search on a cooperative grid
  *     (IM_OPT_FWD_GROUPS workgroups per snapshot word); smaller rounds use
  *     one workgroup per word. Default 0 (always the cooperative grid).
- *   IM_OPT_LAZY_ENGINE: exact evaluations of the lazy path run as one
- *     cooperative grid per batch, all (candidate, word) searches together
- *     (1, default, when their state fits 8 GB), or through the three
- *     per-task engine tiers (0).
+ *   IM_OPT_LAZY_ENGINE: exact evaluations of the lazy path run on the last
+ *     engine tier alone, one workgroup per (candidate, word) search (2,
+ *     default: candidates are the nodes with the largest bounds, whose
+ *     searches the smaller tiers would only hand on; when a batch's searches
+ *     fit the tier's slots their fixpoints stay there, and the round's seed,
+ *     if evaluated in the round's last batch, is committed from them instead
+ *     of a new forward search), through the three per-task engine tiers (0),
+ *     or as one cooperative grid per batch, all (candidate, word) searches
+ *     together (1, when their state fits 8 GB).
  *   IM_OPT_MAX_SLOTS: workgroups of the last engine tier, each with dense
  *     per-node state (28 bytes per node of the largest instance; at most
  *     48 GB in total). 8..65536, default 256.

@@ -96,8 +96,9 @@ class Workspace:
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_COOP_GAIN, int(gain)))
 
     def set_lazy_engine(self, engine):
-        """Exact evaluations of the lazy path: 1 one cooperative grid per batch
-        (default), 0 the three per-task engine tiers. No result changes."""
+        """Exact evaluations of the lazy path: 2 the last tier alone, one
+        workgroup per candidate and word (default), 0 the three per-task engine
+        tiers, 1 one cooperative grid per batch. No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LAZY_ENGINE, int(engine)))
 
     def set_max_slots(self, slots):

@@ -724,6 +724,7 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint
 // tnodes[w] lists the nodes with N[w][x] != 0 (the reverse tasks).
 // ---------------------------------------------------------------------------
 struct FwdArgs {
+    const uint32_t *skip;       // non-zero *skip: the round was committed already (lazy path)
     const uint32_t *row, *col;
     const uint64_t *mask;
     HubLists hub;
@@ -823,6 +824,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
     const bool single = a.b.count == 1;
     const unsigned long long key0 = a.key[0];
+    if (a.skip && *a.skip) return;    // uniform over the grid: before any grid barrier
     if (single && key0 == 0) return;  // no unselected node (cannot happen for k <= n)
     if (single && (key0 >> 32) < a.coop_gain) return;  // a small round: k_forward_block runs it
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key0 & 0xFFFFFFFFull);
@@ -1077,6 +1079,7 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
     __shared__ BlockLds<FWB_NT> L;
     const int tid = threadIdx.x;
     const unsigned long long key = a.key[0];
+    if (a.skip && *a.skip) return;
     if (key == 0) return;
     if ((key >> 32) >= a.coop_gain) return;  // the cooperative kernel runs this round
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
@@ -1299,12 +1302,15 @@ struct im_workspace {
     // lazy evaluation (A9)
     uint32_t cap_celf = 0;
     uint64_t cap_sort = 0;
+    uint32_t *c_kept = nullptr;  // [2][cap_kept]: visit count and source of each kept search
+    uint32_t cap_kept = 0;
     uint32_t *c_bound = nullptr, *c_fresh = nullptr, *c_ev = nullptr, *c_ordB = nullptr,
              *c_ordS = nullptr, *c_E = nullptr, *c_cand = nullptr, *c_ctl = nullptr;
     uint8_t *c_moved = nullptr;
     float *c_score = nullptr, *c_feat = nullptr;
     unsigned long long *c_sort = nullptr;
-    int lazy_engine = 1;     // 1: cooperative batched evaluation, 0: the three tiers
+    int lazy_engine = 2;     // 2: the last tier only (one workgroup per task), 0: the
+                             // three tiers, 1: cooperative batched evaluation
     int learned_policy = 2;  // 1: score order among can-win nodes, 2: predicted-gain batches
     unsigned eval_grid = 0;
     uint64_t cap_eval = 0;
@@ -1496,7 +1502,7 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     if (ws->b_host) (void)hipHostFree(ws->b_host);
     dfree(ws->c_bound); dfree(ws->c_fresh); dfree(ws->c_ev); dfree(ws->c_ordB); dfree(ws->c_ordS);
     dfree(ws->c_E); dfree(ws->c_cand); dfree(ws->c_ctl); dfree(ws->c_moved); dfree(ws->c_score);
-    dfree(ws->c_feat); dfree(ws->c_sort);
+    dfree(ws->c_feat); dfree(ws->c_sort); dfree(ws->c_kept);
     dfree(ws->e_reach); dfree(ws->e_pend); dfree(ws->e_fq0); dfree(ws->e_fq1); dfree(ws->e_vis);
     dfree(ws->e_cnt);
     und_state_free(ws->und);
@@ -1967,6 +1973,26 @@ static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipSt
     }
 }
 
+// Every task of `a` on the last tier alone, one workgroup per task: for
+// tasks known to be large (the lazy path's candidates are the nodes with the
+// largest bounds), which the smaller tiers would only hand on.
+// KEEP: one task per slot (ntasks <= slots), the fixpoints stay in the slots.
+template <int MODE, bool PRUNE, bool KEEP = false>
+static void run_last_tier(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph, hipStream_t s)
+{
+    a.in_q = nullptr; a.in_n = nullptr;
+    a.out_q = nullptr; a.out_n = nullptr; a.grab = ctr + 4; a.tier = 2;
+    if (KEEP) { a.kept_nvis = ws->c_kept; a.kept_src = ws->c_kept + ws->cap_kept; }
+    PhaseTimer pt(ws, ph, s);
+    const unsigned grid = std::max<unsigned>(1u, std::min<unsigned>(ws->slots, a.ntasks));
+    if (ws->tier2_lanes == (uint32_t)T2W_NT)
+        k_block_bfs<MODE, T2W_NT, T2_U, PRUNE, KEEP><<<grid, T2W_NT, 0, s>>>(a);
+    else if (ws->tier2_lanes == (uint32_t)T2S_NT)
+        k_block_bfs<MODE, T2S_NT, T2_U, PRUNE, KEEP><<<grid, T2S_NT, 0, s>>>(a);
+    else
+        k_block_bfs<MODE, T2_NT, T2_U, PRUNE, KEEP><<<grid, T2_NT, 0, s>>>(a);
+}
+
 // A3: initial gains (gain must be zero on entry)
 static void initial_gains(const im_graph *g, uint32_t R, im_workspace *ws, uint32_t *ctr,
                           hipStream_t s)
@@ -1996,6 +2022,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     }
 
     FwdArgs f;
+    f.skip = nullptr;
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
     f.hub = hub_lists(ws, 0);
     f.sp = sparse_lists(ws, 0);
@@ -2158,7 +2185,8 @@ constexpr uint32_t CELF_CAPW = 2048;   // can-win nodes gathered for a learned p
 constexpr int SORT_TILE = 4096;        // keys sorted per workgroup in LDS
 // control words: candidate count, |E|, walk heads of ordB / ordS, then the
 // evaluation's tier counters
-enum { CC_NCAND = 0, CC_NE = 1, CC_HEADB = 2, CC_HEADS = 3, CC_EVCTR = 8, CC_COUNT = 8 + PH_CTRS };
+enum { CC_NCAND = 0, CC_NE = 1, CC_HEADB = 2, CC_HEADS = 3, CC_KEPT = 4, CC_EVCTR = 8,
+       CC_COUNT = 8 + PH_CTRS };
 
 __device__ __forceinline__ unsigned long long node_key(uint32_t primary, uint32_t u)
 {
@@ -2180,6 +2208,39 @@ __device__ __forceinline__ uint32_t score_bits(float f)
 // static inputs of the network (see im_mlp.h), from the out-CSR and the
 // reverse CSR's row offsets; one wavefront per node, so that a hub's arcs
 // are summed by 64 lanes (fixed lane order: deterministic)
+// Nodes of out-degree <= FEAT_SMALL: one thread each, arcs summed in arc order.
+constexpr uint32_t FEAT_SMALL = 64;
+
+__device__ __forceinline__ void feat_store(float *feat, uint32_t u, uint32_t indeg, uint32_t deg,
+                                           float ps, uint64_t two)
+{
+    float *f = feat + (uint64_t)u * 4;   // caller memory: 4-byte alignment only
+    f[0] = log1pf((float)indeg);
+    f[1] = log1pf((float)deg);
+    f[2] = log1pf(ps);
+    f[3] = log1pf((float)two);
+}
+
+__global__ __launch_bounds__(256) void k_features_small(const uint32_t *row, const uint32_t *col,
+                                                        const float *prob, const uint32_t *in_row,
+                                                        uint32_t n, float *feat)
+{
+    for (uint32_t u = blockIdx.x * 256u + threadIdx.x; u < n; u += gridDim.x * 256u) {
+        const uint32_t rs = row[u], re = row[u + 1];
+        if (re - rs > FEAT_SMALL) continue;
+        float ps = 0.0f;
+        uint64_t two = 0;
+#pragma unroll 4
+        for (uint32_t e = rs; e < re; e++) {
+            ps += prob[e];
+            const uint32_t v = col[e];
+            two += row[v + 1] - row[v];
+        }
+        feat_store(feat, u, in_row[u + 1] - in_row[u], re - rs, ps, two);
+    }
+}
+
+// the other nodes: one wavefront each (fixed lane order: deterministic)
 __global__ __launch_bounds__(256) void k_features(const uint32_t *row, const uint32_t *col,
                                                   const float *prob, const uint32_t *in_row,
                                                   uint32_t n, float *feat)
@@ -2187,7 +2248,14 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t *row, const uin
     const int lane = threadIdx.x & 63;
     const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * 256u) >> 6;
-    for (uint32_t u = wave; u < n; u += nwaves) {
+    for (uint32_t b0 = wave * 64; b0 < n; b0 += nwaves * 64) {
+      // 64 nodes' degrees in one load, then each large one by the whole wavefront
+      const uint32_t ul = b0 + (uint32_t)lane;
+      const uint32_t dl = ul < n ? row[ul + 1] - row[ul] : 0u;
+      uint64_t big = __ballot(dl > FEAT_SMALL);
+      while (big) {
+        const uint32_t u = b0 + (uint32_t)(__ffsll((unsigned long long)big) - 1);
+        big &= big - 1;
         const uint32_t rs = row[u], re = row[u + 1];
         float ps = 0.0f;
         uint64_t two = 0;
@@ -2199,13 +2267,17 @@ __global__ __launch_bounds__(256) void k_features(const uint32_t *row, const uin
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) ps += __shfl_xor(ps, d, 64);
         two = wave_sum_u64(two);
-        if (lane == 0) {
-            feat[(uint64_t)u * 4 + 0] = log1pf((float)(in_row[u + 1] - in_row[u]));
-            feat[(uint64_t)u * 4 + 1] = log1pf((float)(re - rs));
-            feat[(uint64_t)u * 4 + 2] = log1pf(ps);
-            feat[(uint64_t)u * 4 + 3] = log1pf((float)two);
-        }
+        if (lane == 0) feat_store(feat, u, in_row[u + 1] - in_row[u], re - rs, ps, two);
+      }
     }
+}
+
+static void launch_features(const uint32_t *row, const uint32_t *col, const float *prob,
+                            const uint32_t *in_row, uint32_t n, float *feat, hipStream_t s)
+{
+    if (n == 0) return;
+    k_features_small<<<grid_for(n, 256, 8192), 256, 0, s>>>(row, col, prob, in_row, n, feat);
+    k_features<<<grid_for(n, 256, 8192), 256, 0, s>>>(row, col, prob, in_row, n, feat);
 }
 
 // score[u] = network(feat[u], ln(1 + bound[u] / R)) for u in list[0..cnt)
@@ -2543,12 +2615,17 @@ __global__ __launch_bounds__(256) void k_celf_update(const uint32_t *cand, uint3
             const uint32_t q = atomicAdd(&ctl[CC_NE], 1u);
             if (q < CELF_CAPE) E[q] = c;
         }
-        if (wb) {
+    }
+    if (wb) {
+        // new scores: one wavefront per candidate (its input has the new gain)
+        for (uint32_t i = threadIdx.x >> 6; i < ncand; i += 4) {
+            const uint32_t c = cand[i];
             float x[MLP_IN];
 #pragma unroll
             for (int q = 0; q < 4; q++) x[q] = feat[(uint64_t)c * 4 + q];
-            x[4] = log1pf((float)g * invR);
-            score[c] = mlp_eval(sw, x);
+            x[4] = log1pf((float)ev[c] * invR);
+            const float y = mlp_eval_wave(sw, x);
+            if ((threadIdx.x & 63) == 0) score[c] = y;
         }
     }
 }
@@ -2768,6 +2845,10 @@ static int reserve_celf(im_workspace *ws, uint32_t n)
         if ((rc = dalloc(&ws->c_sort, len))) return rc;
         ws->cap_sort = len;
     }
+    if (ws->slots > ws->cap_kept || !ws->c_kept) {
+        if ((rc = dalloc(&ws->c_kept, 2ull * ws->slots))) return rc;
+        ws->cap_kept = ws->slots;
+    }
     return IM_OK;
 }
 
@@ -2855,10 +2936,12 @@ static void rebuild_orders(im_workspace *ws, uint32_t n, bool learned, hipStream
 // A5 without A6: commit the round's argmax key keys[t] (forward search,
 // covered |= newly covered) and clear the newly-covered words
 static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seeds_out,
-                       uint64_t *gains_out, im_workspace *ws, hipStream_t s)
+                       uint64_t *gains_out, im_workspace *ws, hipStream_t s,
+                       const uint32_t *skip = nullptr)
 {
     const uint32_t n = g->n, W = (R + 63) / 64;
     FwdArgs f;
+    f.skip = skip;
     f.row = ws->row32; f.col = g->col; f.mask = ws->mask_out; f.m = g->m;
     f.hub = hub_lists(ws, 0);
     f.sp = sparse_lists(ws, 0);
@@ -2888,6 +2971,89 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
     return IM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Committing from a kept evaluation. With the last-tier engine, a batch whose
+// (candidate, word) searches fit the slots runs one search per slot and keeps
+// its fixpoint there. Every search was pruned at covered, so the reach bits
+// of the round's seed v* are exactly its newly covered bits: when v* was in
+// the round's last batch, covered |= those bits replaces the forward search
+// from v* (which then returns at once).
+// ---------------------------------------------------------------------------
+struct KeptArgs {
+    const unsigned long long *key;   // the round's best key
+    uint32_t t, ncand, n, W, slot_n;
+    const uint32_t *nvis, *src;      // per kept search (task = slot)
+    const uint64_t *reach;           // slots' (reach, pend) records
+    const uint32_t *vis;             // slots' visit lists
+    const uint32_t *row;
+    uint64_t *covered;
+    uint32_t *seeds_out, *tcounts, *flag;
+    uint64_t *gains_out;
+    uint8_t *sel;
+    unsigned long long *stats;
+};
+
+// KC_G workgroups per word (grid KC_G x W)
+constexpr uint32_t KC_G = 64;
+
+__global__ __launch_bounds__(256) void k_kept_commit(KeptArgs a)
+{
+    __shared__ uint32_t found;
+    __shared__ unsigned long long red[4];
+    const uint32_t w = blockIdx.y, part = blockIdx.x, tid = threadIdx.x;
+    const unsigned long long key = *a.key;
+    if (key == 0) return;
+    const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+    if (tid == 0) found = 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t j = tid; j < a.ncand; j += 256)
+        if (a.src[j] == v) found = j;   // candidates are distinct: one writer
+    __syncthreads();
+    const uint32_t j = found;
+    if (j == 0xFFFFFFFFu) return;   // evaluated in an earlier batch: the forward search commits
+    const uint32_t task = w * a.ncand + j;
+    const uint32_t nv = a.nvis[task];
+    const uint32_t *vis = a.vis + (uint64_t)task * a.slot_n;
+    const uint64_t *reach = a.reach + (uint64_t)task * a.slot_n * 2;
+    uint64_t relax = 0, trav = 0;
+    for (uint32_t i = part * 256 + tid; i < nv; i += KC_G * 256) {
+        const uint32_t x = vis[i];
+        const uint64_t b = reach[(uint64_t)x * 2];
+        a.covered[(uint64_t)w * a.n + x] |= b;
+        const uint32_t dg = a.row[x + 1] - a.row[x];
+        relax += dg;
+        trav += (uint64_t)__popcll(b) * dg;
+    }
+    relax = group_sum<256>(relax, red);
+    trav = group_sum<256>(trav, red);
+    if (tid == 0 && relax) {
+        atomicAdd(&a.stats[ST_RELAX_FWD], (unsigned long long)relax);
+        atomicAdd(&a.stats[ST_TRAV_FWD], (unsigned long long)trav);
+    }
+    if (tid == 0 && part == 0) {
+        a.tcounts[w] = 0;
+        atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)nv);
+        if (w == 0) {
+            a.seeds_out[a.t] = v;
+            a.gains_out[a.t] = key >> 32;
+            a.sel[v] = 1;
+            *a.flag = 1;
+        }
+    }
+}
+
+// return the kept slots to zero (grid KC_G x slots) and clear the flag
+__global__ __launch_bounds__(256) void k_kept_clear(const uint32_t *nvis, const uint32_t *vis,
+                                                    uint64_t *reach, uint32_t slot_n, uint32_t *flag)
+{
+    const uint32_t task = blockIdx.y, part = blockIdx.x;
+    const uint32_t nv = nvis[task];
+    const uint32_t *vl = vis + (uint64_t)task * slot_n;
+    uint64_t *rc = reach + (uint64_t)task * slot_n * 2;
+    for (uint32_t i = part * 256 + threadIdx.x; i < nv; i += KC_G * 256) rc[(uint64_t)vl[i] * 2] = 0;
+    if (task == 0 && part == 0 && threadIdx.x == 0) *flag = 0;
+}
+
 static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, const im_mlp *model,
                        uint32_t *seeds_out, uint64_t *gains_out, im_workspace *ws, hipStream_t s)
 {
@@ -2896,15 +3062,14 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
     const bool learned = model != nullptr;
     const float invR = 1.0f / (float)R;
     if ((rc = reserve_celf(ws, n))) return rc;
-    const uint32_t vmax = ws->lazy_engine ? eval_vmax(n, W) : 0u;
+    const uint32_t vmax = ws->lazy_engine == 1 ? eval_vmax(n, W) : 0u;
     if (vmax && (rc = reserve_eval(ws, n, vmax))) return rc;
     k_copy_u32<<<grid_for(n, 256), 256, 0, s>>>(ws->gain, ws->c_bound, n);
     fill<uint32_t>(ws->c_fresh, n, 0u, s);
     fill<uint32_t>(ws->c_ctl, CC_COUNT, 0u, s);
     if (learned) {
         PhaseTimer pt(ws, IM_PH_SCORE, s);
-        k_features<<<grid_for((uint64_t)n * 64, 256, 16384), 256, 0, s>>>(ws->row32, g->col, g->prob,
-                                                                            ws->in_row, n, ws->c_feat);
+        launch_features(ws->row32, g->col, g->prob, ws->in_row, n, ws->c_feat, s);
         k_celf_score<<<grid_for(n, 256, 4096), 256, 0, s>>>(model->wb, ws->c_feat, ws->c_bound, invR,
                                                             nullptr, n, nullptr, ws->c_score);
     }
@@ -2925,6 +3090,15 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
                                                          ws->pk, (uint32_t)PK_ZERO);
     }
     if ((rc = commit_seed(g, R, 0, seeds_out, gains_out, ws, s))) return rc;
+    // the last batch's searches kept in the slots (last-tier engine): their count
+    uint32_t kept_tasks = 0, kept_ncand = 0;
+    auto clear_kept = [&]() {
+        if (!kept_tasks) return;
+        PhaseTimer pt(ws, IM_PH_CLEAR, s);
+        k_kept_clear<<<dim3(KC_G, kept_tasks), 256, 0, s>>>(ws->c_kept, ws->b_vis, ws->b_reach,
+                                                             ws->slots_n, ws->c_ctl + CC_KEPT);
+        kept_tasks = 0;
+    };
     for (uint32_t t = 1; t < k; t++) {
         pa.t = t;
         pa.best = ws->keys + t;
@@ -2942,6 +3116,7 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
             HIPCHK(hipStreamSynchronize(s));
             const uint32_t ncand = *ws->host_err;
             if (ncand == 0) break;
+            clear_kept();   // the slots are about to be reused
             if (vmax) {
                 PhaseTimer pt(ws, IM_PH_EVAL_T2, s);
                 if ((rc = eval_coop(g, R, ncand, vmax, ws, s))) return rc;
@@ -2956,7 +3131,14 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
                 a.sp = sparse_lists(ws, 0);
                 a.pass = PASS_EVAL;
                 a.st_trav = ST_TRAV_EVAL;
-                run_tiers<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T0, s);
+                if (ws->lazy_engine == 2 && ws->batch.count == 1 && ncand * W <= ws->slots) {
+                    run_last_tier<MODE_COUNT, true, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T2, s);
+                    kept_tasks = ncand * W;
+                    kept_ncand = ncand;
+                } else if (ws->lazy_engine == 2)
+                    run_last_tier<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T2, s);
+                else
+                    run_tiers<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T0, s);
             }
             {
                 PhaseTimer pt(ws, IM_PH_UPDATE, s);
@@ -2967,7 +3149,18 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
             }
             moved_bound += ncand;
         }
-        if ((rc = commit_seed(g, R, t, seeds_out, gains_out, ws, s))) return rc;
+        if (kept_tasks) {
+            KeptArgs ka;
+            ka.key = ws->keys + t; ka.t = t; ka.ncand = kept_ncand; ka.n = n; ka.W = W;
+            ka.slot_n = ws->slots_n; ka.nvis = ws->c_kept; ka.src = ws->c_kept + ws->cap_kept;
+            ka.reach = ws->b_reach; ka.vis = ws->b_vis; ka.row = ws->row32; ka.covered = ws->covered;
+            ka.seeds_out = seeds_out; ka.gains_out = gains_out; ka.tcounts = ws->tcounts;
+            ka.flag = ws->c_ctl + CC_KEPT; ka.sel = ws->sel; ka.stats = ws->stats;
+            PhaseTimer pt(ws, IM_PH_FORWARD, s);
+            k_kept_commit<<<dim3(KC_G, W), 256, 0, s>>>(ka);
+        }
+        if ((rc = commit_seed(g, R, t, seeds_out, gains_out, ws, s, ws->c_ctl + CC_KEPT))) return rc;
+        clear_kept();
     }
     HIPCHK(hipGetLastError());
     return IM_OK;
@@ -3528,7 +3721,7 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         ws->learned_policy = (int)value;
         return IM_OK;
     case IM_OPT_LAZY_ENGINE:
-        if (value != 0 && value != 1) return im_fail(IM_EINVAL, "lazy engine must be 0 or 1");
+        if (value < 0 || value > 2) return im_fail(IM_EINVAL, "lazy engine must be 0, 1 or 2");
         ws->lazy_engine = (int)value;
         return IM_OK;
     case IM_OPT_PAIR_COINS:
@@ -3996,8 +4189,7 @@ extern "C" int im_node_features(const im_graph *g, float *feat_out, im_workspace
     if ((rc = check_and_reserve(g, 1, 0, ws, s))) return rc;
     if (g->n == 0) return IM_OK;
     build_reverse(g, ws, s);
-    k_features<<<grid_for((uint64_t)g->n * 64, 256, 16384), 256, 0, s>>>(ws->row32, g->col, g->prob,
-                                                                           ws->in_row, g->n, feat_out);
+    launch_features(ws->row32, g->col, g->prob, ws->in_row, g->n, feat_out, s);
     HIPCHK(hipGetLastError());
     ws->last_stream = s;
     return IM_OK;

@@ -149,6 +149,9 @@ struct BfsArgs {
     const uint32_t *inst_R;     // batches: snapshots per instance
     const uint32_t *inst_off;   // batches: first node of each instance
     uint32_t slot_n;            // length of each global-engine slot array
+    // last tier, KEEP launches (one task per workgroup, task = slot): the
+    // search state stays in the slot, with its visit count and source here
+    uint32_t *kept_nvis, *kept_src;
     HubLists hub;
     SparseLists sp;
     const uint64_t *prune;    // [W][n] or nullptr
@@ -863,9 +866,12 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
     }
 }
 
-template <int MODE, int NT, int U, bool PRUNE>
+template <int MODE, int NT, int U, bool PRUNE, bool KEEP = false>
 __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
 {
+    // KEEP (MODE_COUNT, single graph, tasks routed here directly): workgroup
+    // b runs task b alone and leaves its fixpoint (reach bits, visit list) in
+    // slot b for a later kernel, which returns the slot to zero
     __shared__ BlockLds<NT> L;
     __shared__ uint32_t wpre[65];
     const int tid = threadIdx.x;
@@ -878,15 +884,18 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     uint32_t *vis = a.b_vis + slot * a.slot_n;
     if (tid == 0 && MODE == MODE_DEC) fill_wpre(a, wpre);
     __syncthreads();
-    const uint32_t nq = *a.in_n;
+    // in_q = nullptr: every task id below ntasks (tasks routed straight here)
+    const uint32_t nq = a.in_q ? *a.in_n : a.ntasks;
     // In a batch a packed reverse task may hold sources of several instances;
     // its sources are then searched one after the other, each inside its own
     // instance (their bits are disjoint, so the decrements add up to those of
     // the joint search). A single graph searches all sources together.
     const bool split = a.node_inst != nullptr;
     uint64_t arcs = 0, relax = 0, reached = 0, trav = 0, dec = 0, levels = 0;
+    bool first = true;
     for (;;) {
-        if (tid == 0) L.task = atomicAdd(a.grab, 1u);
+        if (tid == 0) L.task = KEEP ? (first ? (uint32_t)blockIdx.x : nq) : atomicAdd(a.grab, 1u);
+        first = false;
         __syncthreads();
         const uint32_t q = L.task;
         __syncthreads();
@@ -895,7 +904,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         {
             uint32_t ww, ss;
             uint64_t bb;
-            task_source(a, MODE, a.in_q[q], wpre, (uint32_t)(tid & 63), ww, ss, bb);
+            task_source(a, MODE, a.in_q ? a.in_q[q] : q, wpre, (uint32_t)(tid & 63), ww, ss, bb);
             w = ww;
             if (tid < 64) { L.gsrc[tid] = ss; L.gbits[tid] = bb; }
         }
@@ -928,11 +937,15 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
                 trav += (uint64_t)pc * dg;
                 if (MODE == MODE_COUNT) cnt += pc;
                 else { atomicSub(&a.gain[x], pc); dec += pc; }
-                reach[(uint64_t)(x - base) * 2] = 0;   // pend is zero at the fixpoint
+                if (!KEEP) reach[(uint64_t)(x - base) * 2] = 0;   // pend is zero at the fixpoint
             }
             if (MODE == MODE_COUNT) {
                 cnt = group_sum<NT>(cnt, L.red);
                 if (tid == 0) atomicAdd(&a.gain[src0], (uint32_t)cnt);
+            }
+            if (KEEP && tid == 0) {
+                a.kept_nvis[q] = nvis;
+                a.kept_src[q] = src0;
             }
             __syncthreads();
         }

@@ -75,3 +75,27 @@ __device__ __forceinline__ float mlp_eval(const float *sw, const float *x)
     }
     return y;
 }
+
+// Forward pass of one input by a whole wavefront (all 64 lanes call it with
+// the same x): lane j computes hidden unit j of both layers; the second
+// layer takes the first layer's units lane by lane (uniform index: a scalar
+// read of that lane), the output is a wavefront sum. Every lane returns y.
+__device__ __forceinline__ float mlp_eval_wave(const float *sw, const float *x)
+{
+    static_assert(MLP_H == 64, "one hidden unit per lane");
+    const int j = threadIdx.x & 63;
+    float z = sw[MLP_OFF_B1 + j];
+#pragma unroll
+    for (int i = 0; i < MLP_IN; i++) z = fmaf(sw[MLP_OFF_W1 + j * MLP_IN + i], x[i], z);
+    const float h1 = fmaxf(z, 0.0f);
+    float z2 = sw[MLP_OFF_B2 + j];
+#pragma unroll 16
+    for (int i = 0; i < MLP_H; i++) {
+        const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), i));
+        z2 = fmaf(sw[MLP_OFF_W2 + j * MLP_H + i], hi, z2);
+    }
+    float y = sw[MLP_OFF_W3 + j] * fmaxf(z2, 0.0f);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) y += __shfl_xor(y, d, 64);
+    return y + sw[MLP_OFF_B3];
+}

@@ -47,7 +47,7 @@ def _random_params(seed, scale=0.2):
 # ------------------------------------------------------------------- lazy path
 
 
-@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("engine", [0, 1, 2])
 @pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
 @pytest.mark.parametrize("batch", [1, 7, 64, 1024])
 def test_lazy_bound_order_matches_golden(im, name, batch, engine):
@@ -65,7 +65,7 @@ def test_lazy_bound_order_matches_golden(im, name, batch, engine):
     assert st["celf_evals"] >= w["k"] - 1
 
 
-@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("engine", [0, 1, 2])
 @pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
 def test_lazy_batch1_evaluations_equal_oracle_celf(im, name, engine):
     w = gg.WORKLOADS[name]
@@ -120,13 +120,40 @@ def test_lazy_learned_constant_and_adversarial_models(im):
             assert gains.cpu().tolist() == gold["gains"]
 
 
+def test_lazy_learned_fallback_to_bound_order(im):
+    # every probability is 0, so all gains stay R and the lowest ids win; node
+    # u has out-degree u // 1000 and the network scores by out-degree, so the
+    # first batch of a round takes the highest ids and nearly every unselected
+    # node can still win after it: more than the 2048 a learned pick gathers,
+    # and policy 1 falls back to bound order
+    n = 20000
+    arcs = [(u, (u + 1 + j) % n) for u in range(n) for j in range(u // 1000)]
+    g = _csr(n, arcs, 0.0)
+    R, k, seed = 64, 4, 1
+    s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
+    assert s_ref.tolist() == [0, 1, 2, 3]
+    prm = np.zeros(NP, np.float32)
+    prm[0 * 5 + 1] = 1.0                      # W1[0][1]: ln(1 + out-degree)
+    prm[320 + 64 + 0 * 64 + 0] = 1.0          # W2[0][0]
+    prm[320 + 64 + 4096 + 64 + 0] = 1.0       # w3[0]
+    model = im.Mlp(prm)
+    d = _dev(im, g)
+    for engine in (0, 1, 2):
+        ws = im.Workspace()
+        ws.set_lazy_engine(engine)
+        ws.set_learned_policy(1)
+        seeds, gains = im.select_lazy(d, R, k, seed, batch=2, model=model, ws=ws)
+        assert seeds.cpu().tolist() == s_ref.tolist() and gains.cpu().tolist() == g_ref.tolist()
+        assert ws.stats()["celf_fallbacks"] >= k - 1
+
+
 def test_lazy_million_golden(im):
     gold = _gold("million_uic")
     w = gg.WORKLOADS["million_uic"]
     g = gg.workload_graph("million_uic")
     d = _dev(im, g)
     for engine, model, batch in ((1, None, 64), (1, im.Mlp(_random_params(12)), 16), (0, None, 64),
-                                 (1, None, 1)):
+                                 (1, None, 1), (2, None, 4), (2, im.Mlp(_random_params(12)), 16)):
         ws = im.Workspace()
         ws.set_lazy_engine(engine)
         seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=batch, model=model, ws=ws)
@@ -152,7 +179,7 @@ def test_lazy_small_cases_match_oracle(im, case, learned):
     s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed)
     d = _dev(im, g)
     model = im.Mlp(_random_params(13)) if learned else None
-    for engine in (0, 1):
+    for engine in (0, 1, 2):
         ws = im.Workspace()
         ws.set_lazy_engine(engine)
         for batch in (1, 5, 1024):
@@ -253,8 +280,22 @@ def test_mlp_training_reduces_loss(im):
     assert l1 < 0.1 * l0
 
 
+def _csr(n, arcs, p):
+    arcs = sorted(arcs)
+    row_ptr = np.zeros(n + 1, np.uint64)
+    for u, _ in arcs:
+        row_ptr[u + 1] += 1
+    col = np.array([v for _, v in arcs], np.uint32)
+    return gg.Graph(n, np.cumsum(row_ptr).astype(np.uint64), col, np.full(len(arcs), p, np.float32))
+
+
 def test_node_features_match_oracle(im):
-    for g in (gg.workload_graph("tiny_uic"), gg.workload_graph("nethept_wc")):
+    # out-degrees on both sides of the one-thread / one-wavefront split (64)
+    arcs = ([(0, v) for v in range(1, 65)] + [(1, v) for v in range(2, 67)] +
+            [(2, v) for v in range(3, 66)] + [(3, 4)])
+    hand = _csr(300, arcs, 0.3)
+    for g in (gg.workload_graph("tiny_uic"), gg.workload_graph("nethept_wc"), hand,
+              gg.chung_lu_graph(5000, 80000, 2.1, 8, True, 0.02)):
         d = _dev(im, g)
         f = im.node_features(d).cpu().numpy()
         ref = oracle.node_features(g.row_ptr, g.col, g.prob)
