@@ -121,11 +121,21 @@ int im_workspace_destroy(im_workspace *ws);
  *     (a part past 2^32 is never drawn), and the top 32 bits of output r+1
  *     of SplitMix64 seeded with output v+1 of SplitMix64(seed) keep the arc
  *     whose sub-interval holds them in snapshot r. Not for batches, plans,
- *     pair coins or im_spread. */
+ *     pair coins or im_spread.
+ *   IM_OPT_LAZY_BATCH: the batch im_select_lazy uses when called with
+ *     batch = 0 (1..1024, default 4; im_autotune_lazy sets it).
+ *   IM_OPT_AFFECTED_GAIN: how a round of im_select / plans on a single graph
+ *     brings the gains up to date (Sec. 4, Algorithm 2's delete loop). Rounds
+ *     whose seed gain is at least this value (all rounds at the default 0)
+ *     take one reverse search per newly covered node and subtract its counts;
+ *     the others recompute, from scratch, the gain of every node that reaches
+ *     a newly covered node in its snapshot (found by one union search per
+ *     word over the reverse arcs), which gives the same integers. Costs
+ *     28 W + 12 bytes per node of extra workspace when non-zero. */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
        IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10,
-       IM_OPT_LIVE_EDGE = 11 };
+       IM_OPT_LIVE_EDGE = 11, IM_OPT_LAZY_BATCH = 12, IM_OPT_AFFECTED_GAIN = 13 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -171,7 +181,7 @@ enum {
     IM_PH_INIT_T0, IM_PH_INIT_T1, IM_PH_INIT_T2, IM_PH_ARGMAX, IM_PH_FORWARD,
     IM_PH_REV_T0, IM_PH_REV_T1, IM_PH_REV_T2, IM_PH_CLEAR, IM_PH_CALL, IM_PH_HUBS,
     IM_PH_PACK, IM_PH_ORDER, IM_PH_SCORE, IM_PH_PICK, IM_PH_EVAL_T0, IM_PH_EVAL_T1,
-    IM_PH_EVAL_T2, IM_PH_UPDATE, IM_PH_COUNT
+    IM_PH_EVAL_T2, IM_PH_UPDATE, IM_PH_AFFECTED, IM_PH_COUNT
 };
 #define IM_PH_MAX 24
 typedef struct im_profile {
@@ -270,7 +280,11 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
  * is timed on a trial selection of the given graph -- the initial reach
  * counts (Algorithm 2's initial loop) and the first four greedy rounds --
  * and the fastest is set on the workspace and returned in *out (host, may
- * be NULL).
+ * be NULL). im_autotune then times, with that schedule, the initial counts
+ * and the first 16 rounds under four per-round update strategies (the
+ * IM_OPT_AFFECTED_GAIN thresholds 0, n R / 4096, n R / 256 and 2^62: reverse
+ * decrements in every round, the affected-set recompute in the small, in
+ * most or in all rounds) and keeps the fastest.
  * im_autotune caches its choice per graph signature (n, m, R and a checksum
  * of col and prob) for the life of the process; a cached choice is applied
  * without timing (out->tried = 0). im_autotune_batch tunes on the instances
@@ -283,6 +297,7 @@ typedef struct im_tuning {
     int32_t  coop_forward; /* 1: cooperative forward search (IM_OPT_COOP_GAIN 0), 0: one workgroup per word */
     float    ms;           /* trial time of the chosen schedule         */
     uint32_t tried;        /* schedules timed (0: taken from the cache)  */
+    uint64_t affected_gain;/* IM_OPT_AFFECTED_GAIN chosen (single graphs) */
 } im_tuning;
 int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,
                 im_tuning *out);
@@ -371,7 +386,8 @@ int im_mlp_samples(const float *feat, const uint32_t *trace, uint32_t n, uint32_
                    float *x_out, float *t_out, void *stream);
 /* k-seed selection by lazy exact evaluation (the paper's StaticGreedyCELF,
  * Sec. 5, on the snapshots of Sec. 3.3): stale gains are upper bounds; each
- * round evaluates candidates exactly, `batch` at a time (1..1024), until the
+ * round evaluates candidates exactly, `batch` at a time (1..1024; 0: the
+ * workspace's IM_OPT_LAZY_BATCH), until the
  * best exact (gain, lowest id) beats the bound of every candidate not yet
  * evaluated in the round. model = NULL: candidates in bound order; otherwise
  * as IM_OPT_LEARNED_POLICY says (score order falls back to bound order when
@@ -382,6 +398,23 @@ int im_mlp_samples(const float *feat, const uint32_t *trace, uint32_t n, uint32_
 int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uint32_t batch,
                    const im_mlp *model, uint32_t *seeds_out, uint64_t *gains_out,
                    im_workspace *ws, void *stream);
+
+/* Lazy-path tuning (synchronous; the schedule part of the autotuner, like
+ * im_autotune, never changes a result): the lazy selection of the first
+ * min(k, 8) rounds (at least 2) is timed under each evaluation engine
+ * (IM_OPT_LAZY_ENGINE 2 and 0) and batch size (1, 2, 4, 8, 16) with the
+ * given model (NULL: bound order); the fastest pair is set on the workspace
+ * (IM_OPT_LAZY_ENGINE, IM_OPT_LAZY_BATCH), so that im_select_lazy with
+ * batch = 0 uses it, and returned in *out (host, may be NULL). The engine
+ * schedule set by im_autotune is kept. */
+typedef struct im_lazy_tuning {
+    int32_t  engine;   /* IM_OPT_LAZY_ENGINE chosen       */
+    uint32_t batch;    /* IM_OPT_LAZY_BATCH chosen        */
+    float    ms;       /* trial time of the chosen pair   */
+    uint32_t tried;    /* pairs timed                     */
+} im_lazy_tuning;
+int im_autotune_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, const im_mlp *model,
+                     im_workspace *ws, void *stream, im_lazy_tuning *out);
 
 /* Spread evaluation (the snapshot estimator of Sec. 3.1; the paper scores
  * seed sets on independent simulations, Sec. 5.2). With f(T) = sum_r |R_r(T)|

@@ -9,4 +9,4 @@ from ._native import ImError  # noqa: F401
 from .api import (Workspace, Graph, Plan, BatchPlan, Mlp, select, select_batch, select_lazy,  # noqa: F401
                   initial_gains, snapshot_masks, transpose, validate, node_features,
                   mlp_samples, autotune, autotune_batch, spread,
-                  pair_ids, select_undirected, select_noalloc)
+                  pair_ids, select_undirected, select_noalloc, autotune_lazy)

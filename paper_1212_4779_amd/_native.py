@@ -21,7 +21,7 @@ EXPORTS = ("im_workspace_create", "im_workspace_destroy", "im_stats_get", "im_la
            "im_mlp_get_params", "im_mlp_forward", "im_mlp_loss_grad", "im_mlp_adam",
            "im_mlp_train_step", "im_node_features", "im_mlp_samples", "im_select_lazy",
            "im_autotune", "im_autotune_batch", "im_plan_create_batch", "im_spread",
-           "im_pair_ids", "im_select_undirected", "im_select_noalloc")
+           "im_pair_ids", "im_select_undirected", "im_select_noalloc", "im_autotune_lazy")
 IM_MLP_NPARAM = 4609
 IM_SPREAD_R_MAX = 1 << 20
 IM_PH_MAX = 24
@@ -29,7 +29,7 @@ IM_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 PHASES = ("validate", "transpose", "mask_gen", "mask_gather", "init_t0", "init_t1", "init_t2",
           "argmax", "forward", "rev_t0", "rev_t1", "rev_t2", "clear", "call", "hubs",
-          "pack", "order", "score", "pick", "eval_t0", "eval_t1", "eval_t2", "update")
+          "pack", "order", "score", "pick", "eval_t0", "eval_t1", "eval_t2", "update", "affected")
 IM_OPT_HUB_DEGREE = 1
 IM_OPT_COOP_GAIN = 2
 IM_OPT_LAZY_ENGINE = 3
@@ -41,6 +41,8 @@ IM_OPT_FWD_GROUPS = 8
 IM_OPT_LEARNED_POLICY = 9
 IM_OPT_PAIR_COINS = 10
 IM_OPT_LIVE_EDGE = 11
+IM_OPT_LAZY_BATCH = 12
+IM_OPT_AFFECTED_GAIN = 13
 
 
 class ImGraph(ctypes.Structure):
@@ -86,7 +88,16 @@ class ImStats(ctypes.Structure):
 class ImTuning(ctypes.Structure):
     _fields_ = [("hub_degree", ctypes.c_int32), ("tier1_shape", ctypes.c_int32),
                 ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32)]
+                ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32),
+                ("affected_gain", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ImLazyTuning(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("batch", ctypes.c_uint32), ("ms", ctypes.c_float),
+                ("tried", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -150,6 +161,7 @@ def lib():
         L.im_pair_ids.argtypes = [G, p, p, p]
         L.im_select_undirected.argtypes = [G, u32, u32, u64, p, p, p, p, p]
         L.im_select_noalloc.argtypes = [G, u32, u32, u64, p, p, p]
+        L.im_autotune_lazy.argtypes = [G, u32, u32, u64, p, p, p, ctypes.POINTER(ImLazyTuning)]
         for name in EXPORTS:
             getattr(L, name).restype = ctypes.c_int if name != "im_last_error" else ctypes.c_char_p
         _lib = L

@@ -121,6 +121,15 @@ class Workspace:
         """Workgroups per snapshot word of the grid-wide forward search. No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_FWD_GROUPS, int(per_word)))
 
+    def set_lazy_batch(self, batch):
+        """Batch of select_lazy(batch=0) (1..1024)."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LAZY_BATCH, int(batch)))
+
+    def set_affected_gain(self, gain):
+        """Rounds whose seed gain is below `gain` update the gains by the
+        affected-set recompute instead of reverse decrements (0: never)."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_AFFECTED_GAIN, int(gain)))
+
     def set_learned_policy(self, policy):
         """1: score order among can-win nodes; 2: first batch sized by the predicted gain."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LEARNED_POLICY, int(policy)))
@@ -444,7 +453,8 @@ def mlp_samples(feat, trace, R, node, tprev, tcur):
 
 
 def select_lazy(graph, R, k, seed, batch=64, model=None, ws=None):
-    """Lazy exact evaluation (bound order, or `model`'s score order).
+    """Lazy exact evaluation (bound order, or `model`'s score order); batch 0
+    takes the workspace's batch (set by autotune_lazy).
 
     Returns (seeds int64 [k], gains int64 [k]) -- always those of select().
     """
@@ -457,6 +467,19 @@ def select_lazy(graph, R, k, seed, batch=64, model=None, ws=None):
                                    model.handle if model is not None else ctypes.c_void_p(0),
                                    _ptr(seeds), _ptr(gains), ws.handle, _stream(dev)))
     return _u32(seeds), gains
+
+
+def autotune_lazy(graph, R, k, seed, model=None, ws=None):
+    """Pick the lazy path's evaluation engine and batch size (set on `ws`,
+    used by select_lazy(batch=0)); returns them as a dict."""
+    dev = graph.device
+    g = graph.c_struct()
+    ws = _ws(ws, dev)
+    t = N.ImLazyTuning()
+    N.check(N.lib().im_autotune_lazy(ctypes.byref(g), R, k, seed,
+                                     model.handle if model is not None else ctypes.c_void_p(0),
+                                     ws.handle, _stream(dev), ctypes.byref(t)))
+    return t.as_dict()
 
 
 def pair_ids(graph, ws=None):

@@ -1159,10 +1159,17 @@ constexpr int PK_ZERO = 64 * 64 * 2 + 128;  // bcnt, bcur [W][64]; gcnt, mcnt [6
 __global__ __launch_bounds__(PK_NT) void k_pack_fill(const uint32_t *tnodes, const uint32_t *tcounts,
                                                      const uint64_t *newly, uint32_t n,
                                                      const uint32_t *bcnt, uint32_t *boff,
-                                                     uint32_t *gcnt, uint32_t *bcur, uint32_t *plist)
+                                                     uint32_t *gcnt, uint32_t *bcur, uint32_t *plist,
+                                                     uint32_t *mcnt, const unsigned long long *key,
+                                                     uint64_t aff_gain)
 {
     __shared__ uint32_t cnt[64], base0[64];
     const uint32_t w = blockIdx.y;
+    if (aff_gain && (*key >> 32) < aff_gain) {
+        // a round updated by the affected-set recompute: no reverse tasks
+        if (blockIdx.x == 0 && threadIdx.x == 0) { gcnt[w] = 0; mcnt[w] = 0; }
+        return;
+    }
     const uint64_t off = (uint64_t)w * n;
     const uint32_t c = tcounts[w];
     if (threadIdx.x < 64) {
@@ -1312,6 +1319,7 @@ struct im_workspace {
     int lazy_engine = 2;     // 2: the last tier only (one workgroup per task), 0: the
                              // three tiers, 1: cooperative batched evaluation
     int learned_policy = 2;  // 1: score order among can-win nodes, 2: predicted-gain batches
+    uint32_t lazy_batch = 4; // batch of im_select_lazy when it is called with batch = 0
     unsigned eval_grid = 0;
     uint64_t cap_eval = 0;
     uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
@@ -1334,6 +1342,13 @@ struct im_workspace {
     uint32_t *pair = nullptr;
     uint64_t cap_pair = 0;
     UndState *und = nullptr;
+    // affected-set recompute (rounds whose gain is below aff_gain; 0: never)
+    uint64_t aff_gain = 0;
+    uint64_t cap_aff_nW = 0;
+    uint32_t cap_aff_n = 0, cap_aff_k = 0;
+    uint64_t *a_reach = nullptr, *a_pend = nullptr;
+    uint32_t *a_qa = nullptr, *a_qb = nullptr, *a_vis = nullptr;
+    uint32_t *a_mark = nullptr, *a_list = nullptr, *a_cnt = nullptr, *a_ctrs = nullptr;
     // misc
     unsigned long long *stats = nullptr;
     uint32_t *err = nullptr;
@@ -1509,6 +1524,8 @@ extern "C" int im_workspace_destroy(im_workspace *ws)
     ws->und = nullptr;
     dfree(ws->pair);
     dfree(ws->lt_start); dfree(ws->lt_task);
+    dfree(ws->a_reach); dfree(ws->a_pend); dfree(ws->a_qa); dfree(ws->a_qb); dfree(ws->a_vis);
+    dfree(ws->a_mark); dfree(ws->a_list); dfree(ws->a_cnt); dfree(ws->a_ctrs);
     dfree(ws->v_row32); dfree(ws->v_mask); dfree(ws->v_reach); dfree(ws->v_pend); dfree(ws->v_cov);
     dfree(ws->v_qa); dfree(ws->v_qb); dfree(ws->v_vis);
     dfree(ws->stats); dfree(ws->err);
@@ -2008,6 +2025,118 @@ static void initial_gains(const im_graph *g, uint32_t R, im_workspace *ws, uint3
     run_tiers<MODE_COUNT, false>(a, ws, ctr, IM_PH_INIT_T0, s);
 }
 
+// ---------------------------------------------------------------------------
+// A6, the affected-set recompute: the other way to bring the gains up to date
+// after a round (identical integers; the autotuner picks the rounds). The
+// nodes whose gain changes are exactly those that reach a newly covered node
+// in its snapshot (their reach sets lose it): one union search per word over
+// the reverse arcs from every newly covered node, carrying its newly covered
+// bits, finds them. Each such node's gain is then recomputed from scratch,
+// sum over r of |R_r(u) \ covered_r|, by the count engine pruned at covered
+// (covered already holds this round's newly covered bits). For a node that
+// reaches none, nothing changed.
+// ---------------------------------------------------------------------------
+constexpr int AFF_NT = 1024;
+
+struct AffArgs {
+    const unsigned long long *key;   // the round's key
+    uint64_t aff_gain;               // rounds whose gain is below this use the recompute
+    const uint32_t *row, *col;       // reverse CSR
+    const uint64_t *mask;            // reverse masks [W][m]
+    uint64_t m;
+    HubLists hub;
+    SparseLists sp;
+    uint32_t n, W;
+    const uint32_t *tnodes, *tcounts;
+    const uint64_t *newly;
+    uint64_t *reach, *pend;          // [W][n], zero at rest
+    uint32_t *qa, *qb, *vis;         // [W][n]
+    uint32_t *mark, *list, *cnt;     // affected nodes: mark [n] (zero at rest), list, count
+    uint32_t *gain;
+};
+
+// one workgroup per word
+__global__ __launch_bounds__(AFF_NT) void k_aff_search(AffArgs a)
+{
+    __shared__ BlockLds<AFF_NT> L;
+    const unsigned long long key = *a.key;
+    if (key == 0 || (key >> 32) >= a.aff_gain) return;   // a dynamic-update round
+    const uint32_t w = blockIdx.x, tid = threadIdx.x;
+    const uint64_t off = (uint64_t)w * a.n;
+    uint64_t *reach = a.reach + off, *pend = a.pend + off;
+    uint32_t *qa = a.qa + off, *qb = a.qb + off, *vis = a.vis + off;
+    if (tid == 0) { L.nf = 0; L.nn = 0; L.nvis = 0; L.H.n = 0; L.levels = 0; L.entries = 0; }
+    __syncthreads();
+    const uint32_t c = a.tcounts[w];
+    for (uint32_t i = tid; i < c; i += AFF_NT) {
+        const uint32_t x = a.tnodes[off + i];
+        global_relax<1>(reach, pend, 0u, vis, qa, &L.nvis, &L.nf, x, a.newly[off + x]);
+    }
+    __syncthreads();
+    uint64_t arcs = 0;
+    block_bfs_run<AFF_NT, 8, false, true, 1>(L, 0u, 0ull, a.row, a.col, a.mask + (uint64_t)w * a.m,
+                                             a.hub, a.sp, a.n, a.W, w, nullptr, reach, pend, 0u, qa,
+                                             qb, vis, arcs, true);
+    const uint32_t nv = L.nvis;
+    for (uint32_t b0 = 0; b0 < nv; b0 += AFF_NT) {   // whole wavefronts per step
+        const uint32_t i = b0 + tid;
+        uint32_t x = 0;
+        bool first = false;
+        if (i < nv) {
+            x = vis[i];
+            reach[x] = 0;   // pend is zero at the fixpoint
+            first = atomicExch(&a.mark[x], 1u) == 0u;
+        }
+        const uint32_t p = wave_append(first, a.cnt);
+        if (first) {
+            a.list[p] = x;
+            a.gain[x] = 0;   // recomputed from scratch below
+        }
+    }
+}
+
+__global__ void k_aff_clear(uint32_t *mark, const uint32_t *list, const uint32_t *cnt)
+{
+    const uint32_t c = *cnt;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < c; i += gridDim.x * blockDim.x)
+        mark[list[i]] = 0;
+}
+
+static void affected_update(const im_graph *g, uint32_t R, uint32_t t, im_workspace *ws,
+                            hipStream_t s)
+{
+    const uint32_t n = g->n, W = (R + 63) / 64;
+    {
+        AffArgs f;
+        f.key = ws->keys + t; f.aff_gain = ws->aff_gain;
+        f.row = ws->in_row; f.col = ws->in_col; f.mask = ws->mask_in; f.m = g->m;
+        f.hub = hub_lists(ws, 1); f.sp = sparse_lists(ws, 1);
+        f.n = n; f.W = W;
+        f.tnodes = ws->tnodes; f.tcounts = ws->tcounts; f.newly = ws->newly;
+        f.reach = ws->a_reach; f.pend = ws->a_pend;
+        f.qa = ws->a_qa; f.qb = ws->a_qb; f.vis = ws->a_vis;
+        f.mark = ws->a_mark; f.list = ws->a_list; f.cnt = ws->a_cnt; f.gain = ws->gain;
+        PhaseTimer pt(ws, IM_PH_AFFECTED, s);
+        k_aff_search<<<W, AFF_NT, 0, s>>>(f);
+    }
+    BfsArgs a = bfs_args(ws, ws->row32, g->col, ws->mask_out, g->m, n, R, W);
+    a.cand = ws->a_list;
+    a.ncand_dev = ws->a_cnt;
+    a.ntasks = 0;
+    a.gain = ws->gain;
+    a.prune = ws->covered;
+    a.hub = hub_lists(ws, 0);
+    a.sp = sparse_lists(ws, 0);
+    a.pass = PASS_EVAL;
+    a.st_trav = ST_TRAV_EVAL;
+    run_tiers<MODE_COUNT, true>(a, ws, ws->a_ctrs + (uint64_t)t * PH_CTRS, IM_PH_EVAL_T0, s);
+    {
+        PhaseTimer pt(ws, IM_PH_AFFECTED, s);
+        k_aff_clear<<<grid_for(n, 256, 1024), 256, 0, s>>>(ws->a_mark, ws->a_list, ws->a_cnt);
+        fill<uint32_t>(ws->a_cnt, 1, 0u, s);
+    }
+}
+
 // A4-A6: one greedy round
 static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seeds_out,
                         uint64_t *gains_out, im_workspace *ws, uint32_t *ctr, hipStream_t s)
@@ -2055,8 +2184,10 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
         // listed the others
         PhaseTimer pt(ws, IM_PH_PACK, s);
         dim3 pg(grid_for(n, PK_NT, 64), W);
+        const uint64_t aff = ws->batch.count == 1 ? ws->aff_gain : 0ull;
         k_pack_fill<<<pg, PK_NT, 0, s>>>(ws->tnodes, ws->tcounts, ws->newly, n, bcnt, ws->boff,
-                                         gcnt, bcur, ws->plist);
+                                         gcnt, bcur, ws->plist, mcnt, ws->keys + (uint64_t)t * ws->batch.count,
+                                         aff);
     }
     BfsArgs a = bfs_args(ws, ws->in_row, ws->in_col, ws->mask_in, g->m, n, R, W);
     a.gcnt = gcnt; a.mcnt = mcnt; a.bcnt = bcnt; a.boff = ws->boff;
@@ -2066,6 +2197,7 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     a.pass = PASS_REV;
     a.st_trav = ST_TRAV_REV;
     run_tiers<MODE_DEC, false>(a, ws, ctr, IM_PH_REV_T0, s);
+    if (ws->batch.count == 1 && ws->aff_gain) affected_update(g, R, t, ws, s);
     {
         PhaseTimer pt(ws, IM_PH_CLEAR, s);
         k_clear_newly<<<grid_for(n, 256, 1024), 256, 0, s>>>(ws->newly, ws->tnodes, ws->tcounts, n, W);
@@ -2079,6 +2211,32 @@ static int check_and_reserve(const im_graph *g, uint32_t R, uint32_t k, im_works
 {
     int rc;
     if ((rc = ws_reserve(ws, g->n, g->m, (R + 63) / 64, k, g->n))) return rc;
+    if (ws->aff_gain && ws->batch.count == 1) {
+        const uint64_t nW = (uint64_t)g->n * ((R + 63) / 64);
+        if (nW > ws->cap_aff_nW || !ws->a_reach) {
+            if ((rc = dalloc(&ws->a_reach, nW)) || (rc = dalloc(&ws->a_pend, nW)) ||
+                (rc = dalloc(&ws->a_qa, nW)) || (rc = dalloc(&ws->a_qb, nW)) ||
+                (rc = dalloc(&ws->a_vis, nW)))
+                return rc;
+            if ((rc = ws_memset(ws->a_reach, nW * sizeof(uint64_t))) ||
+                (rc = ws_memset(ws->a_pend, nW * sizeof(uint64_t))))
+                return rc;
+            ws->cap_aff_nW = nW;
+        }
+        if (g->n > ws->cap_aff_n || !ws->a_mark) {
+            if ((rc = dalloc(&ws->a_mark, g->n)) || (rc = dalloc(&ws->a_list, g->n)) ||
+                (rc = dalloc(&ws->a_cnt, 1)))
+                return rc;
+            if ((rc = ws_memset(ws->a_mark, (uint64_t)g->n * sizeof(uint32_t))) ||
+                (rc = ws_memset(ws->a_cnt, sizeof(uint32_t))))
+                return rc;
+            ws->cap_aff_n = g->n;
+        }
+        if (k + 1 > ws->cap_aff_k || !ws->a_ctrs) {
+            if ((rc = dalloc(&ws->a_ctrs, (uint64_t)(k + 1) * PH_CTRS))) return rc;
+            ws->cap_aff_k = k + 1;
+        }
+    }
     if ((rc = validate(g, ws, s, ws->row32))) return rc;
     if (ws->live_edge == 1) {
         if (ws->batch.count > 1) return im_fail(IM_EINVAL, "linear-threshold snapshots apply to single graphs only");
@@ -2115,6 +2273,7 @@ static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_
     fill<uint32_t>(ws->ctrs, (uint64_t)(k + 1) * PH_CTRS, 0u, s);
     fill<unsigned long long>(ws->keys, (uint64_t)(k + 1) * ws->batch.count, 0ull, s);
     fill<uint32_t>(ws->fctr, (uint64_t)(k ? k : 1) * FWD_CTRS, 0u, s);
+    if (ws->aff_gain && ws->batch.count == 1) fill<uint32_t>(ws->a_ctrs, (uint64_t)(k + 1) * PH_CTRS, 0u, s);
     fill<uint32_t>(ws->gain, n, 0u, s);
     fill<uint8_t>(ws->sel, n, (uint8_t)0, s);
     fill<uint64_t>(ws->covered, (uint64_t)n * W, 0ull, s);
@@ -3720,6 +3879,14 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
         if (value != 1 && value != 2) return im_fail(IM_EINVAL, "learned policy must be 1 or 2");
         ws->learned_policy = (int)value;
         return IM_OK;
+    case IM_OPT_AFFECTED_GAIN:
+        if (value < 0) return im_fail(IM_EINVAL, "affected-set gain threshold must be >= 0");
+        ws->aff_gain = (uint64_t)value;
+        return IM_OK;
+    case IM_OPT_LAZY_BATCH:
+        if (value < 1 || value > (int64_t)CELF_BMAX) return im_fail(IM_EINVAL, "lazy batch must be in [1, %u]", CELF_BMAX);
+        ws->lazy_batch = (uint32_t)value;
+        return IM_OK;
     case IM_OPT_LAZY_ENGINE:
         if (value < 0 || value > 2) return im_fail(IM_EINVAL, "lazy engine must be 0, 1 or 2");
         ws->lazy_engine = (int)value;
@@ -4065,6 +4232,51 @@ static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
     best->coop_forward = kSchedules[best_i].coop_forward;
     best->ms = best_ms;
     best->tried = N_SCHEDULES;
+    best->affected_gain = 0;
+    return IM_OK;
+}
+
+// The per-round update strategy under the chosen schedule: reverse decrements
+// in every round, or the affected-set recompute below one of three gain
+// thresholds. `run(kt)` enqueues a trial of kt rounds (after its reservation).
+constexpr uint32_t TUNE_AFF_ROUNDS = 16;
+
+template <typename Run>
+static int tune_affected(uint64_t nR, im_workspace *ws, hipStream_t s, Run run, im_tuning *best)
+{
+    int rc = IM_OK;
+    const uint64_t cand[4] = {0ull, nR / 4096, nR / 256, 1ull << 62};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const uint32_t saved_mask = ws->prof_mask;
+    ws->prof_mask = 0;
+    float best_ms = -1.0f;
+    uint64_t best_t = 0;
+    for (int i = 0; i < 4 && !rc; i++) {
+        if (i > 0 && cand[i] == cand[i - 1]) continue;
+        ws->aff_gain = cand[i];
+        float ms_min = -1.0f;
+        for (int rep = 0; rep < 2 && !rc; rep++) {
+            if ((rc = run(true))) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = IM_EHIP; break; }
+            rc = run(false);
+            if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = IM_EHIP;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = IM_EHIP;
+            float ms = 0;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = IM_EHIP;
+            if (!rc && (ms_min < 0 || ms < ms_min)) ms_min = ms;
+        }
+        if (!rc && (best_ms < 0 || ms_min < best_ms)) { best_ms = ms_min; best_t = cand[i]; }
+    }
+    ws->prof_mask = saved_mask;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ws->aff_gain = best_t;
+    if (rc) return rc == IM_EHIP ? im_fail(IM_EHIP, "event timing of an update-strategy trial failed") : rc;
+    best->affected_gain = best_t;
+    best->ms = best_ms;
+    best->tried += 4;
     return IM_OK;
 }
 
@@ -4075,6 +4287,7 @@ static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, boo
             const im_tuning &t = kv.second;
             apply_schedule(ws, Schedule{t.hub_degree, t.tier1_shape, t.tier2_lanes, t.max_slots,
                                         t.coop_forward});
+            ws->aff_gain = t.affected_gain;
             if (out) { *out = t; out->tried = 0; }
             *hit = true;
             return IM_OK;
@@ -4107,17 +4320,26 @@ extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_work
     if (hit) return IM_OK;
     im_tuning best;
     // the trial: initial counts and the first few greedy rounds (whose
-    // reverse steps are the largest of the selection)
+    // reverse steps are the largest of the selection), under reverse
+    // decrements; then the update strategy over a longer trial
     const uint32_t kt = std::min<uint32_t>(TUNE_ROUNDS, g->n);
+    const uint32_t ka = std::min<uint32_t>(TUNE_AFF_ROUNDS, g->n);
     uint32_t *sd = nullptr;
     uint64_t *gd = nullptr;
-    if ((rc = dalloc(&sd, kt)) || (rc = dalloc(&gd, kt))) { dfree(sd); return rc; }
+    if ((rc = dalloc(&sd, ka)) || (rc = dalloc(&gd, ka))) { dfree(sd); return rc; }
+    ws->aff_gain = 0;
     auto prep = [&](bool reserve) -> int {
         if (reserve) return check_and_reserve(g, R, kt, ws, s);
         int r = enqueue_prepare(g, R, seed, kt, ws, s);
         return r ? r : enqueue_rounds(g, R, kt, sd, gd, nullptr, ws, s);
     };
     rc = tune(ws, s, prep, &best);
+    auto run = [&](bool reserve) -> int {
+        if (reserve) return check_and_reserve(g, R, ka, ws, s);
+        int r = enqueue_prepare(g, R, seed, ka, ws, s);
+        return r ? r : enqueue_rounds(g, R, ka, sd, gd, nullptr, ws, s);
+    };
+    if (!rc) rc = tune_affected((uint64_t)g->n * R, ws, s, run, &best);
     (void)hipStreamSynchronize(s);
     dfree(sd);
     dfree(gd);
@@ -4161,6 +4383,74 @@ extern "C" int im_autotune_batch(const im_instance *inst, uint32_t count, im_wor
     return IM_OK;
 }
 
+// Lazy-path tuning: the evaluation engine and the batch size, timed on the
+// lazy selection's first rounds (the largest searches of the selection)
+constexpr uint32_t LAZY_TUNE_ROUNDS = 8;
+static const int32_t kLazyEngines[] = {2, 0};
+static const uint32_t kLazyBatches[] = {1, 2, 4, 8, 16};
+
+extern "C" int im_autotune_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
+                                const im_mlp *model, im_workspace *ws, void *stream,
+                                im_lazy_tuning *out)
+{
+    int rc;
+    if ((rc = check_args(g, R))) return rc;
+    if (!ws) return im_fail(IM_EINVAL, "null workspace");
+    if (k > g->n) return im_fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t kt = std::min<uint32_t>(std::max<uint32_t>(k, 2u), std::min<uint32_t>(LAZY_TUNE_ROUNDS, g->n));
+    if (g->n == 0 || kt < 2) {
+        if (out) { out->engine = ws->lazy_engine; out->batch = ws->lazy_batch; out->ms = 0; out->tried = 0; }
+        return IM_OK;
+    }
+    uint32_t *sd = nullptr;
+    uint64_t *gd = nullptr;
+    if ((rc = dalloc(&sd, kt)) || (rc = dalloc(&gd, kt))) { dfree(sd); return rc; }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        dfree(sd); dfree(gd);
+        if (e0) (void)hipEventDestroy(e0);
+        return im_fail(IM_EHIP, "hipEventCreate failed");
+    }
+    const uint32_t saved_mask = ws->prof_mask;
+    ws->prof_mask = 0;
+    float best_ms = -1.0f;
+    int32_t best_e = ws->lazy_engine;
+    uint32_t best_b = ws->lazy_batch, tried = 0;
+    for (int32_t eng : kLazyEngines) {
+        for (uint32_t B : kLazyBatches) {
+            ws->lazy_engine = eng;
+            float ms_min = -1.0f;
+            for (int rep = 0; rep < 2 && !rc; rep++) {
+                if ((rc = check_and_reserve(g, R, kt, ws, s))) break;
+                if ((rc = (int)(hipEventRecord(e0, s) != hipSuccess ? IM_EHIP : IM_OK))) break;
+                rc = enqueue_prepare(g, R, seed, kt, ws, s);
+                if (!rc) rc = select_lazy(g, R, kt, B, model, sd, gd, ws, s);
+                if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = IM_EHIP;
+                if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = IM_EHIP;
+                float ms = 0;
+                if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = IM_EHIP;
+                if (!rc && (ms_min < 0 || ms < ms_min)) ms_min = ms;
+            }
+            if (rc) break;
+            tried++;
+            if (best_ms < 0 || ms_min < best_ms) { best_ms = ms_min; best_e = eng; best_b = B; }
+        }
+        if (rc) break;
+    }
+    ws->prof_mask = saved_mask;
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dfree(sd);
+    dfree(gd);
+    ws->lazy_engine = best_e;
+    ws->lazy_batch = best_b;
+    if (rc) return rc == IM_EHIP ? im_fail(IM_EHIP, "event timing of a lazy trial failed") : rc;
+    if (out) { out->engine = best_e; out->batch = best_b; out->ms = best_ms; out->tried = tried; }
+    return IM_OK;
+}
+
 extern "C" int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed,
                               uint32_t batch, const im_mlp *model, uint32_t *seeds_out,
                               uint64_t *gains_out, im_workspace *ws, void *stream)
@@ -4170,8 +4460,9 @@ extern "C" int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_
     if (!ws) return im_fail(IM_EINVAL, "null workspace");
     if (k > g->n) return im_fail(IM_EINVAL, "k = %u exceeds n = %u", k, g->n);
     if (k && (!seeds_out || !gains_out)) return im_fail(IM_EINVAL, "null seeds or gains output");
-    if (batch == 0 || batch > CELF_BMAX)
-        return im_fail(IM_EINVAL, "batch = %u must be in [1, %u]", batch, CELF_BMAX);
+    if (batch == 0) batch = ws->lazy_batch;   // the workspace's (tuned) batch
+    if (batch > CELF_BMAX)
+        return im_fail(IM_EINVAL, "batch = %u must be in [0, %u]", batch, CELF_BMAX);
     if ((uint64_t)batch * ((R + 63) / 64) >= (1ull << 32)) return im_fail(IM_EINVAL, "batch too large");
     hipStream_t s = (hipStream_t)stream;
     PhaseTimer pt(ws, IM_PH_CALL, s);

@@ -167,6 +167,8 @@ struct BfsArgs {
     uint32_t ntasks;
     const uint32_t *cand;
     uint32_t ncand;
+    const uint32_t *ncand_dev;      // MODE_COUNT: the candidate count in device memory
+                                    // (overrides ncand and ntasks = ncand * W), or nullptr
     const uint32_t *gcnt, *mcnt;    // [W]
     const uint32_t *bcnt, *boff;    // [W][64]
     const uint32_t *plist, *mlist;  // [W][n]
@@ -442,6 +444,7 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     __shared__ LdsState<NT, T, CS> L;
     const int tid = threadIdx.x;
+    if (MODE == MODE_COUNT && a.ncand_dev) { a.ncand = *a.ncand_dev; a.ntasks = a.ncand * a.W; }
 
     for (int i = tid; i < N; i += NT) {
         L.keys[i] = IM_EMPTY; L.reach[i] = 0; L.pend[i] = 0; L.deg[i] = 0;
@@ -766,15 +769,19 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                               uint32_t W, uint32_t w,
                               const uint64_t *prune, uint64_t *reach, uint64_t *pend,
                               uint32_t base, uint32_t *qa, uint32_t *qb, uint32_t *vis,
-                              uint64_t &arcs)
+                              uint64_t &arcs, bool preseeded = false)
 {
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     const int tid = threadIdx.x;
-    if (tid == 0) { L.nf = 0; L.nn = 0; L.nvis = 0; L.H.n = 0; L.levels = 0; L.entries = 0; }
-    __syncthreads();
-    // seeds: every lane with start bits (lanes 0..63 for multi-source tasks)
-    if (start) global_relax<S>(reach, pend, base, vis, qa, &L.nvis, &L.nf, src, start);
-    __syncthreads();
+    // preseeded: the caller has already entered the seeds with global_relax
+    // (after setting L.nf = L.nn = L.nvis = L.H.n = L.levels = L.entries = 0)
+    if (!preseeded) {
+        if (tid == 0) { L.nf = 0; L.nn = 0; L.nvis = 0; L.H.n = 0; L.levels = 0; L.entries = 0; }
+        __syncthreads();
+        // seeds: every lane with start bits (lanes 0..63 for multi-source tasks)
+        if (start) global_relax<S>(reach, pend, base, vis, qa, &L.nvis, &L.nf, src, start);
+        __syncthreads();
+    }
     uint32_t *cur = qa, *nxt = qb;
     for (;;) {
         const uint32_t nf = L.nf;
@@ -876,6 +883,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     __shared__ uint32_t wpre[65];
     const int tid = threadIdx.x;
     const uint64_t slot = blockIdx.x;
+    if (MODE == MODE_COUNT && a.ncand_dev) { a.ncand = *a.ncand_dev; a.ntasks = a.ncand * a.W; }
     // the slot's (reach, pend) records, interleaved
     uint64_t *reach = a.b_reach + slot * a.slot_n * 2;
     uint64_t *pend = reach + 1;

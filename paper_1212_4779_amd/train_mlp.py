@@ -10,7 +10,8 @@ gather, forward, backward, Adam) runs in libim's kernels; numpy only draws
 the random sample indices and the initial weights.
 
 Usage:
-    python -m paper_1212_4779_amd.train_mlp [--graphs 40] [--steps 4000] [--out FILE]
+    python -m paper_1212_4779_amd.train_mlp [--graphs 180] [--val 20] [--budget-s 0]
+        [--steps 4000] [--out FILE]
 """
 import argparse
 import json
@@ -81,10 +82,25 @@ def train(x, t, xv, tv, params, steps, batch, lr, seed, log=print):
     return model, hist
 
 
+def _order(recipes):
+    """Smallest graphs first, the two probability models interleaved, so that
+    a time budget cut keeps a balanced subset."""
+    uic = sorted((r for r in recipes if r["p"] is not None), key=lambda r: r["n"])
+    wc = sorted((r for r in recipes if r["p"] is None), key=lambda r: r["n"])
+    out = []
+    for i in range(max(len(uic), len(wc))):
+        out += [x[i] for x in (uic, wc) if i < len(x)]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--graphs", type=int, default=40, help="uniform-IC training graphs used")
-    ap.add_argument("--val", type=int, default=4, help="held-out validation graphs used")
+    ap.add_argument("--graphs", type=int, default=180, help="training graphs used (at most)")
+    ap.add_argument("--val", type=int, default=20, help="held-out validation graphs used")
+    ap.add_argument("--models", default="both", choices=("both", "uic"),
+                    help="probability models of the graphs: uniform IC and weighted cascade, or uniform IC only")
+    ap.add_argument("--budget-s", type=float, default=0.0,
+                    help="stop adding training graphs once the traces took this long (0: no limit)")
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -94,25 +110,41 @@ def main(argv=None):
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     rec = gg.training_recipes(**{k: v for k, v in gg.TRAINING_WORKLOAD.items()})
-    uic = [r for r in rec if r["p"] is not None]
-    train_rec = [r for r in uic if not r["validation"]][:a.graphs]
-    val_rec = [r for r in uic if r["validation"]][:a.val]
+    if a.models == "uic":
+        rec = [r for r in rec if r["p"] is not None]
+    train_rec = _order([r for r in rec if not r["validation"]])[:a.graphs]
+    val_rec = _order([r for r in rec if r["validation"]])[:a.val]
     rng = np.random.default_rng(a.seed)
     xs, ts = {"train": [], "val": []}, {"train": [], "val": []}
+    used = {"train": [], "val": []}
     t0 = time.time()
+    trace_s = 0.0
     import multiprocessing as mp
-    jobs = [("train", r) for r in train_rec] + [("val", r) for r in val_rec]
+    jobs = [("val", r) for r in val_rec] + [("train", r) for r in train_rec]
     # the generator workers are forked before this process touches the GPU
-    with mp.get_context("fork").Pool(a.workers) as pool:
+    pool = mp.get_context("fork").Pool(a.workers)
+    try:
         graphs = pool.imap(gg.graph_from_recipe, [r for _, r in jobs])
         ws = api.Workspace()
         for (split, r), g in zip(jobs, graphs):
+            if split == "train" and a.budget_s and trace_s > a.budget_s:
+                log(f"trace budget of {a.budget_s:.0f}s reached: {len(used['train'])} training graphs")
+                break
+            torch.cuda.synchronize()
+            t1 = time.time()
             x, t = samples_from_graph(r, g, rng, ws)
+            torch.cuda.synchronize()
+            dt = time.time() - t1
+            trace_s += dt
             xs[split].append(x)
             ts[split].append(t)
+            used[split].append(dict(graph_seed=r["graph_seed"], n=g.n, m=g.m, p=r["p"],
+                                    trace_s=round(dt, 3)))
             log(f"{split} graph seed {r['graph_seed']}: n={g.n} m={g.m} p={r['p']} "
-                f"samples={x.shape[0]} ({time.time() - t0:.1f}s)")
+                f"samples={x.shape[0]} trace {dt:.2f}s ({time.time() - t0:.1f}s)")
             del g
+    finally:
+        pool.terminate()
     x, t = torch.cat(xs["train"]), torch.cat(ts["train"])
     xv, tv = torch.cat(xs["val"]), torch.cat(ts["val"])
     log(f"samples: train {x.shape[0]}, val {xv.shape[0]}")
@@ -120,8 +152,9 @@ def main(argv=None):
     master, _ = model.params()
     out = dict(params=[float(v) for v in master], layout="W1[64][5] b1 W2[64][64] b2 w3 b3",
                features="ln1p(indeg, outdeg, sum p_out, sum outdeg(out-nbrs), gain/R)",
-               training=dict(graphs=[r["graph_seed"] for r in train_rec],
-                             validation=[r["graph_seed"] for r in val_rec],
+               training=dict(graphs=used["train"], validation=used["val"],
+                             trace_seconds=round(trace_s, 1), budget_s=a.budget_s,
+                             recipes_available=dict(train=len(train_rec), val=len(val_rec)),
                              samples=int(x.shape[0]), steps=a.steps, batch=a.batch, lr=a.lr,
                              seed=a.seed, history=hist))
     with open(a.out, "w") as f:

@@ -200,9 +200,16 @@ def test_lazy_edge_cases_and_errors(im):
                  torch.zeros(0, dtype=torch.float32, device="cuda:0"))
     seeds, gains = im.select_lazy(e, 70, 4, 1, batch=3)
     assert seeds.cpu().tolist() == [0, 1, 2, 3] and gains.cpu().tolist() == [70] * 4
-    for bad in (0, 1025):
-        with pytest.raises(im.ImError):
-            im.select_lazy(d, 64, 3, 1, batch=bad)
+    with pytest.raises(im.ImError):
+        im.select_lazy(d, 64, 3, 1, batch=1025)
+    # batch 0: the workspace's batch
+    s_ref, g_ref, _, _ = oracle.select_du(g.row_ptr, g.col, g.prob, 64, 3, 1)
+    ws = im.Workspace()
+    ws.set_lazy_batch(3)
+    seeds, gains = im.select_lazy(d, 64, 3, 1, batch=0, ws=ws)
+    assert seeds.cpu().tolist() == s_ref.tolist() and gains.cpu().tolist() == g_ref.tolist()
+    with pytest.raises(im.ImError):
+        ws.set_lazy_batch(0)
     with pytest.raises(im.ImError):
         im.select_lazy(d, 64, g.n + 1, 1)
 
@@ -341,3 +348,29 @@ def test_trained_network_evaluations_reported(im):
         rows[label] = (st["celf_evals"], st["celf_batches"])
     print("exact evaluations, batches:", rows)
     assert all(e >= w["k"] - 1 for e, _ in rows.values())
+    # sizing the first batch of a round by the network's predicted gain never
+    # evaluates more than bound order at the same batch cap here
+    assert rows["predicted"][0] <= rows["plain"][0]
+
+
+def test_trained_network_saves_exact_evaluations(im):
+    # what the network gains over the method without it: at a batch cap of 16
+    # the first batch of a round is sized by the predicted gain of the
+    # best-scored node, and far fewer exact evaluations are needed than in
+    # bound order, with the same seeds, gains and number of batches
+    from paper_1212_4779_amd.train_mlp import load
+    model = load()
+    for name in ("tiny_uic", "million_uic"):
+        gold = _gold(name)
+        w = gg.WORKLOADS[name]
+        d = _dev(im, gg.workload_graph(name))
+        evals = {}
+        for label, m in (("plain", None), ("learned", model)):
+            ws = im.Workspace()
+            seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=16, model=m, ws=ws)
+            assert seeds.cpu().tolist() == gold["seeds"] and gains.cpu().tolist() == gold["gains"]
+            st = ws.stats()
+            evals[label] = (st["celf_evals"], st["celf_batches"])
+        print(name, "exact evaluations, batches:", evals)
+        assert evals["learned"][0] * 3 <= evals["plain"][0] * 2, evals
+        assert evals["learned"][1] <= evals["plain"][1], evals

@@ -122,3 +122,79 @@ def test_batch_plan_replays(im):
         torch.cuda.synchronize()
     assert plan.stats()["trav_init"] > 0
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["tiny_uic", "nethept_wc"])
+def test_lazy_autotune_then_select(im, name):
+    # the lazy tuner's engine and batch size, and every pair it tries, give
+    # the oracle's seeds and gains
+    from paper_1212_4779_amd.train_mlp import load
+    with open(os.path.join(GOLDEN, f"{name}.json")) as f:
+        gold = json.load(f)
+    w = gg.WORKLOADS[name]
+    d = _dev(im, gg.workload_graph(name))
+    for model in (None, load()):
+        ws = im.Workspace()
+        t = im.autotune_lazy(d, w["R"], w["k"], w["seed"], model=model, ws=ws)
+        assert t["tried"] == 10 and t["ms"] > 0
+        assert t["engine"] in (0, 2) and t["batch"] in (1, 2, 4, 8, 16)
+        seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=0, model=model, ws=ws)
+        assert seeds.cpu().tolist() == gold["seeds"] and gains.cpu().tolist() == gold["gains"]
+        st = ws.stats()
+        assert st["celf_batches"] >= w["k"] - 1
+        for engine in (0, 2):
+            for batch in (1, 2, 4, 8, 16):
+                ws.set_lazy_engine(engine)
+                ws.set_lazy_batch(batch)
+                seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=0, model=model,
+                                              ws=ws)
+                assert seeds.cpu().tolist() == gold["seeds"], (engine, batch)
+                assert gains.cpu().tolist() == gold["gains"], (engine, batch)
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
+def test_affected_set_recompute_gives_the_oracle_trace(im, case):
+    # the other per-round update (recompute the gains of the nodes that reach
+    # a newly covered node) in every round, and from a middle gain on (mixed
+    # rounds), gives the same gain vector as reverse decrements in every round
+    _, g, R, k, seed = case
+    s_ref, g_ref, tr_ref, _ = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    d = _dev(im, g)
+    mid = int(g_ref[len(g_ref) // 2]) + 1
+    for thr in (1 << 62, mid):
+        for hub, t1, lanes, slots in (SCHEDULES[0], SCHEDULES[5], SCHEDULES[6]):
+            ws = im.Workspace()
+            ws.set_hub_degree(hub)
+            ws.set_tier1_shape(t1)
+            ws.set_tier2_lanes(lanes)
+            ws.set_max_slots(slots)
+            ws.set_affected_gain(thr)
+            seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
+            assert seeds.cpu().tolist() == s_ref.tolist(), (thr, hub, t1, lanes, slots)
+            assert gains.cpu().tolist() == g_ref.tolist()
+            assert np.array_equal(tr.cpu().numpy().astype(np.uint32), tr_ref), (thr, hub)
+            st = ws.stats()
+            if thr == 1 << 62:
+                assert st["trav_rev"] == 0 and st["trav_eval"] > 0
+
+
+def test_affected_set_recompute_in_a_plan_and_the_tuner(im):
+    import torch
+    with open(os.path.join(GOLDEN, "nethept_wc.json")) as f:
+        gold = json.load(f)
+    w = gg.WORKLOADS["nethept_wc"]
+    d = _dev(im, gg.workload_graph("nethept_wc"))
+    t = im.autotune(d, w["R"], w["seed"], ws=im.Workspace())
+    assert t["affected_gain"] in (0, d.n * w["R"] // 4096, d.n * w["R"] // 256, 1 << 62)
+    ws = im.Workspace()
+    ws.set_affected_gain(1 << 62)
+    seeds, gains, _ = im.select(d, w["R"], w["k"], w["seed"], ws=ws)
+    assert seeds.cpu().tolist() == gold["seeds"] and gains.cpu().tolist() == gold["gains"]
+    # a plan captured after the tuner chose a strategy for this graph uses it
+    plan = im.Plan(d, w["R"], w["k"], w["seed"])
+    for _ in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        assert plan.seeds.cpu().tolist() == gold["seeds"]
+        assert plan.gains.cpu().tolist() == gold["gains"]
+    plan.close()
