@@ -76,8 +76,9 @@ def load_traffic(phase, workload):
         return None
     with open(path) as f:
         t = json.load(f)
+    t = t.get("workloads", {}).get(workload, {})
     k = t.get("kernels", {}).get(phase)
-    if t.get("workload") != workload or not k:
+    if not k:
         return None
     if k.get("source_digest") != source_digest(k.get("sources", [])):
         return None
@@ -126,18 +127,25 @@ def spread_leg(im, dg, R, seed, seeds, gains, stream, log):
 
 
 def lazy_paths(im, dg, w, seeds, gains, ws, stream, steps, log):
-    """Lazy exact evaluation, plain (bound order) vs learned (network order)."""
+    """Lazy exact evaluation, plain (bound order) vs learned (network order).
+    For each, the lazy tuner first picks the evaluation engine and batch size
+    (on the first rounds); then the whole selection is timed at that batch
+    and at batches 1, 2, 4 and 16 (same engine)."""
     import torch
     from paper_1212_4779_amd.train_mlp import DEFAULT_OUT, load
     model = load(DEFAULT_OUT) if os.path.exists(DEFAULT_OUT) else None
-    out = {"dynamic_update_ms": None, "plain": [], "learned": [], "learned_score_order": []}
+    out = {"dynamic_update_ms": None, "plain": [], "learned": [], "learned_score_order": [],
+           "tuned": {}}
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for label, m, policy in (("plain", None, 2), ("learned", model, 2),
                              ("learned_score_order", model, 1)):
         if m is None and label != "plain":
             continue
         ws.set_learned_policy(policy)
-        for B in (1, 2, 4, 16):
+        t = im.autotune_lazy(dg, w["R"], w["k"], w["seed"], model=m, ws=ws)
+        out["tuned"][label] = t
+        log(f"lazy tuner {label}: {t}")
+        for B in (0, 1, 2, 4, 16):
             s, g = im.select_lazy(dg, w["R"], w["k"], w["seed"], batch=B, model=m, ws=ws)
             torch.cuda.synchronize()
             ev0.record(stream)
@@ -148,11 +156,13 @@ def lazy_paths(im, dg, w, seeds, gains, ws, stream, steps, log):
             ms = ev0.elapsed_time(ev1) / steps
             st = ws.stats()
             same = s.cpu().tolist() == seeds.cpu().tolist() and g.cpu().tolist() == gains.cpu().tolist()
-            out[label].append({"batch": B, "ms": round(ms, 3), "exact_evaluations": st["celf_evals"],
+            out[label].append({"batch": B if B else t["batch"], "tuned": B == 0, "engine": t["engine"],
+                               "ms": round(ms, 3), "exact_evaluations": st["celf_evals"],
                                "batches": st["celf_batches"], "fallbacks": st["celf_fallbacks"],
                                "traversals": st["trav_init"] + st["trav_fwd"] + st["trav_eval"],
                                "same_output": same})
-            log(f"lazy {label} B={B}: {ms:.2f} ms, {st['celf_evals']} evaluations, same={same}")
+            log(f"lazy {label} B={B if B else t['batch']}{' (tuned)' if B == 0 else ''}: {ms:.2f} ms, "
+                f"{st['celf_evals']} evaluations, same={same}")
     ws.set_learned_policy(2)
     for label in ("plain", "learned", "learned_score_order"):
         if out[label]:
@@ -180,6 +190,18 @@ def run_batch(args, log):
     insts = [(im.Graph.from_numpy(g.row_ptr, g.col, g.prob, device=dev), w["R"], w["k"], w["seed"])
              for g, w in zip(graphs, rec)]
     ws = im.Workspace()
+    if args.once:
+        # counter profiling: the autotuner's schedule for this batch, one
+        # selection, then the calibration stream
+        ws.set_tier2_lanes(64)
+        ws.set_max_slots(8192)
+        im.select_batch(insts, ws=ws)
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = src.mul(1.0)
+        torch.cuda.synchronize()
+        log(f"once: batched selection and a {4 * dst.numel()} B read+write stream done")
+        return None
     # schedule: tuned on the largest instances of each probability model
     order = sorted(range(len(rec)), key=lambda i: -graphs[i].n)
     wc = [i for i in order if rec[i]["p"] is None][:6]
@@ -219,27 +241,52 @@ def run_batch(args, log):
     bpl = kb[dom] / launches
     ach = bpl / (avg_ms / 1e3) / 1e9
     gold_path = os.path.join(ROOT, "tests", "golden", "batch512.json")
-    parity = None
+    parity, parity_n = None, 0
     if os.path.exists(gold_path):
         with open(gold_path) as f:
             gold = json.load(f)["instances"]
         parity = all(res[gi["i"]][0].cpu().tolist() == gi["seeds"] and
                      res[gi["i"]][1].cpu().tolist() == gi["gains"] for gi in gold)
-    cpu = None
+        parity_n = len(gold)
+    cpu = cpu_all = None
     if not args.no_cpu_baseline:
+        # a sample stratified by size: every 16th instance in order of n
+        by_n = sorted(range(len(rec)), key=lambda i: graphs[i].n)
+        sample = by_n[8::16]
         oracle._load()
         t0 = time.perf_counter()
-        tr, used = 0, 0
-        for g, w in zip(graphs, rec):
-            _, _, _, ost = oracle.select_du(g.row_ptr, g.col, g.prob, w["R"], w["k"], w["seed"])
+        tr, used = 0, []
+        for i in sample:   # one thread, smallest first, about 20 s
+            _, _, _, ost = oracle.select_du(graphs[i].row_ptr, graphs[i].col, graphs[i].prob,
+                                            rec[i]["R"], rec[i]["k"], rec[i]["seed"])
             tr += ost["trav_init"] + ost["trav_fwd"] + ost["trav_rev"]
-            used += 1
+            used.append(i)
             if time.perf_counter() - t0 > 20:
                 break
         dt = time.perf_counter() - t0
         cpu = {"value": tr / dt, "unit": "snapshot-edge traversals/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {used} of {len(graphs)} instances, StaticGreedyDU oracle, one thread",
+               "sample": f"{len(used)} instances (n {graphs[used[0]].n}..{graphs[used[-1]].n}) of a "
+                         f"size-stratified sample (every 16th instance in order of n), "
+                         f"StaticGreedyDU oracle, one thread",
                "seconds": round(dt, 3)}
+        log(f"cpu oracle, one thread: {dt:.1f}s, {len(used)} instances")
+        # all host cores: the 32 sampled instances in worker processes (fresh
+        # interpreters; each regenerates its graph, untimed, and times the oracle)
+        import multiprocessing as mp
+        workers = min(16, os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        with mp.get_context("forkserver").Pool(workers) as pool:
+            res_cpu = pool.map(_oracle_on_recipe, [rec[i] for i in sample], chunksize=1)
+        wall = time.perf_counter() - t0
+        tr_all = sum(r[0] for r in res_cpu)
+        busy = sum(r[1] for r in res_cpu)
+        cpu_all = {"value": tr_all / wall, "unit": "snapshot-edge traversals/s", "cores": workers,
+                   "kind": "oracle",
+                   "sample": f"the {len(sample)} size-stratified instances, StaticGreedyDU oracle, "
+                             f"one process per core ({workers}); wall time includes each worker's "
+                             f"graph generation",
+                   "seconds": round(wall, 3), "oracle_busy_seconds": round(busy, 3)}
+        log(f"cpu oracle, {workers} processes: {wall:.1f}s wall, {busy:.1f}s busy")
     return {
         "metric": METRIC,
         "value": trav / (ms / 1e3), "unit": "snapshot-edge traversals/s", "n_gpus": 1,
@@ -251,12 +298,23 @@ def run_batch(args, log):
         "selection_ms": ms, "traversals_per_step": trav,
         "phase_ms": {p: round(prof[p][0], 4) for p in prof},
         "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, "batch512"),
                      "kernel": KERNEL_NAMES[dom], "phase": dom,
                      "algorithmic_bytes_per_launch": int(bpl), "avg_launch_ms": round(avg_ms, 4)},
         "schedule": tuning,
-        "cpu_baseline": cpu, "parity_vs_oracle_golden": parity,
+        "cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all, "parity_vs_oracle_golden": parity,
+        "parity_instances": parity_n,
     }
+
+
+def _oracle_on_recipe(w):
+    """(traversals, oracle seconds) of one batch instance (worker process)."""
+    import oracle
+    from paper_1212_4779_amd import graphgen as gg
+    g = gg.graph_from_recipe(w)
+    t0 = time.perf_counter()
+    _, _, _, st = oracle.select_du(g.row_ptr, g.col, g.prob, w["R"], w["k"], w["seed"])
+    return st["trav_init"] + st["trav_fwd"] + st["trav_rev"], time.perf_counter() - t0
 
 
 UNDIRECTED = ("nethept_uic", "million_undirected_uic")
@@ -437,7 +495,9 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch512":
-        print(json.dumps(run_batch(args, log)), flush=True)
+        res = run_batch(args, log)
+        if res is not None:
+            print(json.dumps(res), flush=True)
         return
     if args.workload in UNDIRECTED:
         print(json.dumps(run_undirected(args, log)), flush=True)
@@ -518,6 +578,17 @@ def main():
     avg_launch_ms = dprof[0] / max(1, dprof[1])
     bytes_per_launch = kb[dom] / launches_per_step
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    # every propagation phase of the profiled call against the same peak
+    per_kernel = {}
+    for ph in PROPAGATION:
+        tms, nl = prof[ph]
+        if nl == 0 or tms <= 0:
+            continue
+        a_gbs = kb[ph] / (tms / 1e3) / 1e9
+        per_kernel[ph] = {"kernel": KERNEL_NAMES[ph], "launches": nl, "ms": round(tms, 4),
+                          "algorithmic_bytes_per_launch": int(kb[ph] / nl),
+                          "achieved": round(a_gbs, 2), "frac": round(a_gbs / HBM_PEAK_GBS, 5),
+                          "traffic": load_traffic(ph, args.workload)}
     traffic = load_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -541,6 +612,11 @@ def main():
 
     lazy = lazy_paths(im, dg, w, seeds, gains, ws, stream, max(1, min(args.steps, 3)), log)
     lazy["dynamic_update_ms"] = round(ms_per_step, 3)
+    if "learned_best_ms" in lazy:
+        lazy["learned_faster_than_dynamic_update"] = lazy["learned_best_ms"] < lazy["dynamic_update_ms"]
+        lazy["learned_faster_than_plain_lazy"] = lazy["learned_best_ms"] < lazy["plain_best_ms"]
+        lazy["all_same_output"] = all(r["same_output"] for lab in ("plain", "learned", "learned_score_order")
+                                      for r in lazy[lab])
     spread_eval = spread_leg(im, dg, R, seed, seeds, gains, stream, log)
 
     gold_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}.json")
@@ -573,6 +649,7 @@ def main():
         "counters": st,
         "schedule": tuning,
         "roofline": roofline,
+        "roofline_kernels": per_kernel,
         "learned_vs_plain": lazy,
         "spread_eval": spread_eval,
         "cpu_baseline": cpu,

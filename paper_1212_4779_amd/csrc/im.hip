@@ -2399,35 +2399,53 @@ __global__ __launch_bounds__(256) void k_features_small(const uint32_t *row, con
     }
 }
 
-// the other nodes: one wavefront each (fixed lane order: deterministic)
-__global__ __launch_bounds__(256) void k_features(const uint32_t *row, const uint32_t *col,
-                                                  const float *prob, const uint32_t *in_row,
-                                                  uint32_t n, float *feat)
+// the other nodes: one 1024-lane workgroup each, so that a hub with 10^5
+// arcs is not one wavefront's serial walk; the workgroup scans 1024 nodes'
+// degrees in one load and takes their large ones in turn (each node's sums
+// in a fixed thread and reduction order: deterministic)
+constexpr int FEAT_NT = 1024;
+
+__global__ __launch_bounds__(FEAT_NT) void k_features(const uint32_t *row, const uint32_t *col,
+                                                      const float *prob, const uint32_t *in_row,
+                                                      uint32_t n, float *feat)
 {
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * 256u) >> 6;
-    for (uint32_t b0 = wave * 64; b0 < n; b0 += nwaves * 64) {
-      // 64 nodes' degrees in one load, then each large one by the whole wavefront
-      const uint32_t ul = b0 + (uint32_t)lane;
-      const uint32_t dl = ul < n ? row[ul + 1] - row[ul] : 0u;
-      uint64_t big = __ballot(dl > FEAT_SMALL);
-      while (big) {
-        const uint32_t u = b0 + (uint32_t)(__ffsll((unsigned long long)big) - 1);
-        big &= big - 1;
-        const uint32_t rs = row[u], re = row[u + 1];
-        float ps = 0.0f;
-        uint64_t two = 0;
-        for (uint32_t e = rs + lane; e < re; e += 64) {
-            ps += prob[e];
-            const uint32_t v = col[e];
-            two += row[v + 1] - row[v];
-        }
+    __shared__ uint32_t big[FEAT_NT];
+    __shared__ uint32_t nbig;
+    __shared__ float fred[FEAT_NT / 64];
+    __shared__ unsigned long long ured[FEAT_NT / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (uint32_t b0 = blockIdx.x * FEAT_NT; b0 < n; b0 += gridDim.x * FEAT_NT) {
+        if (tid == 0) nbig = 0;
+        __syncthreads();
+        const uint32_t ul = b0 + tid;
+        if (ul < n && row[ul + 1] - row[ul] > FEAT_SMALL) big[atomicAdd(&nbig, 1u)] = ul;
+        __syncthreads();
+        const uint32_t nb = nbig;
+        // (the list order is arbitrary; each node's sums do not depend on it)
+        for (uint32_t q = 0; q < nb; q++) {
+            const uint32_t u = big[q];
+            const uint32_t rs = row[u], re = row[u + 1];
+            float ps = 0.0f;
+            uint64_t two = 0;
+#pragma unroll 4
+            for (uint32_t e = rs + tid; e < re; e += FEAT_NT) {
+                ps += prob[e];
+                const uint32_t v = col[e];
+                two += row[v + 1] - row[v];
+            }
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) ps += __shfl_xor(ps, d, 64);
-        two = wave_sum_u64(two);
-        if (lane == 0) feat_store(feat, u, in_row[u + 1] - in_row[u], re - rs, ps, two);
-      }
+            for (int d = 32; d >= 1; d >>= 1) ps += __shfl_xor(ps, d, 64);
+            two = wave_sum_u64(two);
+            if (lane == 0) { fred[wv] = ps; ured[wv] = two; }
+            __syncthreads();
+            if (tid == 0) {
+                float fs = 0.0f;
+                uint64_t us = 0;
+                for (int i = 0; i < FEAT_NT / 64; i++) { fs += fred[i]; us += ured[i]; }
+                feat_store(feat, u, in_row[u + 1] - in_row[u], re - rs, fs, us);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -2436,7 +2454,7 @@ static void launch_features(const uint32_t *row, const uint32_t *col, const floa
 {
     if (n == 0) return;
     k_features_small<<<grid_for(n, 256, 8192), 256, 0, s>>>(row, col, prob, in_row, n, feat);
-    k_features<<<grid_for(n, 256, 8192), 256, 0, s>>>(row, col, prob, in_row, n, feat);
+    k_features<<<grid_for(n, FEAT_NT, 4096), FEAT_NT, 0, s>>>(row, col, prob, in_row, n, feat);
 }
 
 // score[u] = network(feat[u], ln(1 + bound[u] / R)) for u in list[0..cnt)

@@ -100,7 +100,7 @@ def main(argv=None):
     ap.add_argument("--models", default="both", choices=("both", "uic"),
                     help="probability models of the graphs: uniform IC and weighted cascade, or uniform IC only")
     ap.add_argument("--budget-s", type=float, default=0.0,
-                    help="stop adding training graphs once the traces took this long (0: no limit)")
+                    help="stop adding graphs once the traces took this long (0: no limit)")
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -112,23 +112,26 @@ def main(argv=None):
     rec = gg.training_recipes(**{k: v for k, v in gg.TRAINING_WORKLOAD.items()})
     if a.models == "uic":
         rec = [r for r in rec if r["p"] is not None]
-    train_rec = _order([r for r in rec if not r["validation"]])[:a.graphs]
-    val_rec = _order([r for r in rec if r["validation"]])[:a.val]
+    train_rec = [r for r in rec if not r["validation"]][:a.graphs]
+    val_rec = [r for r in rec if r["validation"]][:a.val]
     rng = np.random.default_rng(a.seed)
     xs, ts = {"train": [], "val": []}, {"train": [], "val": []}
     used = {"train": [], "val": []}
     t0 = time.time()
     trace_s = 0.0
     import multiprocessing as mp
-    jobs = [("val", r) for r in val_rec] + [("train", r) for r in train_rec]
+    # smallest graphs first, both models and both splits interleaved, so that
+    # a budget cut keeps a balanced subset
+    jobs = [("val" if r["validation"] else "train", r) for r in _order(val_rec + train_rec)]
     # the generator workers are forked before this process touches the GPU
     pool = mp.get_context("fork").Pool(a.workers)
     try:
         graphs = pool.imap(gg.graph_from_recipe, [r for _, r in jobs])
         ws = api.Workspace()
         for (split, r), g in zip(jobs, graphs):
-            if split == "train" and a.budget_s and trace_s > a.budget_s:
-                log(f"trace budget of {a.budget_s:.0f}s reached: {len(used['train'])} training graphs")
+            if a.budget_s and trace_s > a.budget_s:
+                log(f"trace budget of {a.budget_s:.0f}s reached: {len(used['train'])} training, "
+                    f"{len(used['val'])} validation graphs")
                 break
             torch.cuda.synchronize()
             t1 = time.time()
