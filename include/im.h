@@ -357,7 +357,11 @@ int im_mlp_set_params(im_mlp *model, const float *host_params);
 /* Host outputs (either may be NULL): master weights, bfloat16 bit patterns
  * of the copies used by every forward pass (synchronous). */
 int im_mlp_get_params(const im_mlp *model, float *host_master, uint16_t *host_bf16);
-/* y[i] = network(x[i]) for x [N][5] float, y [N] float (device). */
+/* y[i] = network(x[i]) for x [N][5] float, y [N] float (device). The
+ * 64 x 64 second layer runs on the matrix cores (bfloat16 products, FP32
+ * accumulation) with each first-layer activation entered as the sum of two
+ * bfloat16 parts, so y is the FP32 network's to about 2^-16 relative; the
+ * lazy path scores candidates the same way. */
 int im_mlp_forward(const im_mlp *model, const float *x, uint32_t N, float *y, void *stream);
 /* Loss L = sum_i (y_i - t_i)^2 / (2N) of the bfloat16 network on x [N][5],
  * t [N] and its gradient with respect to the parameters (grad [IM_MLP_NPARAM],

@@ -2464,16 +2464,30 @@ __global__ __launch_bounds__(256) void k_celf_score(const uint16_t *wb, const fl
                                                     const uint32_t *list, uint32_t cnt,
                                                     const uint32_t *cnt_dev, float *score)
 {
-    __shared__ float sw[MLP_NP];
-    mlp_stage(wb, sw);
+    // 16 nodes per wavefront and step on the matrix cores (mlp_tile_mfma)
+    MlpFrag f;
+    mlp_frag_load(wb, f);
     const uint32_t c = cnt_dev ? *cnt_dev : cnt;
-    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < c; i += gridDim.x * 256u) {
-        const uint32_t u = list ? list[i] : i;
-        float x[MLP_IN];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * 256u) >> 6;
+    for (uint32_t base = wave * 16u; base < c; base += nwaves * 16u) {
+        const uint32_t i = base + (lane & 15u);
+        float x[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (i < c) {
+            const uint32_t u = list ? list[i] : i;
 #pragma unroll
-        for (int q = 0; q < 4; q++) x[q] = feat[(uint64_t)u * 4 + q];
-        x[4] = log1pf((float)bound[u] * invR);
-        score[u] = mlp_eval(sw, x);
+            for (int q = 0; q < 4; q++) x[q] = feat[(uint64_t)u * 4 + q];
+            x[4] = log1pf((float)bound[u] * invR);
+        }
+        float yo[4];
+        mlp_tile_mfma(f, x, yo);
+        if ((lane & 15u) == 0)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t o = base + 4u * (lane >> 4) + (uint32_t)q;
+                if (o < c) score[list ? list[o] : o] = yo[q];
+            }
     }
 }
 

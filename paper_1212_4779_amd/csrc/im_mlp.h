@@ -99,3 +99,103 @@ __device__ __forceinline__ float mlp_eval_wave(const float *sw, const float *x)
     for (int d = 32; d >= 1; d >>= 1) y += __shfl_xor(y, d, 64);
     return y + sw[MLP_OFF_B3];
 }
+
+// ---------------------------------------------------------------------------
+// Forward pass of 16 inputs per wavefront on the matrix cores. The second
+// layer, H2 = H1 W2^T with H1 [16 nodes][64] and W2 [64][64], is a dense
+// contraction: 4 column tiles x 4 k-steps of v_mfma_f32_16x16x16_bf16
+// (16 x 16 outputs, k = 16, FP32 accumulation). Lane layout of that
+// instruction (A: 16 x 16, B: 16 x 16, D: 16 x 16): lane l supplies row l % 16
+// of A and column l % 16 of B at k = 4 (l / 16) .. 4 (l / 16) + 3, and holds
+// D rows 4 (l / 16) .. + 3 of column l % 16. So lane l computes the first-
+// layer units it feeds to A itself (node l % 16, units 16 s + 4 (l / 16) + q)
+// and no data moves between lanes before the multiply. The weights are
+// bfloat16 already; an activation h enters as hi + lo, both bfloat16
+// (hi = bf16(h), lo = bf16(h - hi)), two products per step, so the result is
+// the FP32 network's to about 2^-16 relative.
+// ---------------------------------------------------------------------------
+typedef short mlp_v4s __attribute__((ext_vector_type(4)));
+typedef float mlp_v4f __attribute__((ext_vector_type(4)));
+
+struct MlpFrag {
+    mlp_v4s b[4][4];        // W2 fragments: [column tile][k-step]
+    float w1[16][MLP_IN];   // first-layer rows of this lane's 16 units
+    float b1[16];
+    float b2[4], w3[4];     // second-layer bias and output weight of column 16 t + l % 16
+    float b3;
+};
+
+__device__ __forceinline__ uint32_t mlp_unit(int s, int q)   // k index of (k-step s, element q)
+{
+    return 16u * (uint32_t)s + 4u * ((threadIdx.x & 63u) >> 4) + (uint32_t)q;
+}
+
+__device__ __forceinline__ void mlp_frag_load(const uint16_t *wb, MlpFrag &f)
+{
+    const uint32_t c = threadIdx.x & 15u;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const uint32_t j = 16u * t + c;
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            mlp_v4s v;
+#pragma unroll
+            for (int q = 0; q < 4; q++) v[q] = (short)wb[MLP_OFF_W2 + j * MLP_H + mlp_unit(s, q)];
+            f.b[t][s] = v;
+        }
+        f.b2[t] = bf16_bits_to_f32(wb[MLP_OFF_B2 + j]);
+        f.w3[t] = bf16_bits_to_f32(wb[MLP_OFF_W3 + j]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint32_t k = mlp_unit(s, q);
+            f.b1[4 * s + q] = bf16_bits_to_f32(wb[MLP_OFF_B1 + k]);
+#pragma unroll
+            for (int i = 0; i < MLP_IN; i++)
+                f.w1[4 * s + q][i] = bf16_bits_to_f32(wb[MLP_OFF_W1 + k * MLP_IN + i]);
+        }
+    f.b3 = bf16_bits_to_f32(wb[MLP_OFF_B3]);
+}
+
+// x: the input of node l % 16 (every lane of the wavefront calls, with its
+// node's input). Returns, on lanes with l % 16 == 0, the outputs of nodes
+// 4 (l / 16) .. 4 (l / 16) + 3 in y[0..3] (other lanes: partial sums).
+__device__ __forceinline__ void mlp_tile_mfma(const MlpFrag &f, const float *x, float y[4])
+{
+    mlp_v4s ahi[4], alo[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            float z = f.b1[4 * s + q];
+#pragma unroll
+            for (int i = 0; i < MLP_IN; i++) z = fmaf(f.w1[4 * s + q][i], x[i], z);
+            const float h = fmaxf(z, 0.0f);
+            const uint16_t hi = f32_to_bf16_bits(h);
+            const uint16_t lo = f32_to_bf16_bits(h - bf16_bits_to_f32(hi));
+            ahi[s][q] = (short)hi;
+            alo[s][q] = (short)lo;
+        }
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        mlp_v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi[s], f.b[t][s], d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo[s], f.b[t][s], d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) acc[q] = fmaf(f.w3[t], fmaxf(d[q] + f.b2[t], 0.0f), acc[q]);
+    }
+    // sum over the 16 columns held by the 16 lanes of this row group
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        float v = acc[q];
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        y[q] = v + f.b3;
+    }
+}

@@ -25,16 +25,28 @@ __global__ void k_mlp_to_bf16(const float *w, uint16_t *wb)
     if (i < MLP_NP) wb[i] = f32_to_bf16_bits(w[i]);
 }
 
+// 16 inputs per wavefront and step on the matrix cores (mlp_tile_mfma)
 __global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t *wb, const float *x, uint32_t N,
                                                      float *y)
 {
-    __shared__ float sw[MLP_NP];
-    mlp_stage(wb, sw);
-    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < N; i += gridDim.x * 256u) {
+    MlpFrag f;
+    mlp_frag_load(wb, f);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * 256u) >> 6;
+    for (uint32_t base = wave * 16u; base < N; base += nwaves * 16u) {
+        const uint32_t i = base + (lane & 15u);
         float xi[MLP_IN];
 #pragma unroll
-        for (int c = 0; c < MLP_IN; c++) xi[c] = x[(uint64_t)i * MLP_IN + c];
-        y[i] = mlp_eval(sw, xi);
+        for (int c = 0; c < MLP_IN; c++) xi[c] = i < N ? x[(uint64_t)i * MLP_IN + c] : 0.0f;
+        float yo[4];
+        mlp_tile_mfma(f, xi, yo);
+        if ((lane & 15u) == 0)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t o = base + 4u * (lane >> 4) + (uint32_t)q;
+                if (o < N) y[o] = yo[q];
+            }
     }
 }
 
@@ -271,7 +283,7 @@ extern "C" int im_mlp_forward(const im_mlp *m, const float *x, uint32_t N, float
     if (!m) return im_fail(IM_EINVAL, "im_mlp_forward: null model");
     if (N == 0) return IM_OK;
     if (!x || !y) return im_fail(IM_EINVAL, "im_mlp_forward: null input or output");
-    const unsigned g = (unsigned)std::min<uint64_t>(((uint64_t)N + 255) / 256, 8192);
+    const unsigned g = (unsigned)std::min<uint64_t>(((uint64_t)N + 63) / 64, 8192);
     k_mlp_forward<<<g, 256, 0, (hipStream_t)stream>>>(m->wb, x, N, y);
     HIPCHK(hipGetLastError());
     return IM_OK;

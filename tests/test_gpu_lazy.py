@@ -231,7 +231,7 @@ def test_mlp_bf16_copies_match_oracle_rounding(im):
     assert np.array_equal(got_bf16.astype(np.uint32), want)
 
 
-@pytest.mark.parametrize("N", [1, 64, 1000])
+@pytest.mark.parametrize("N", [1, 17, 64, 1000, 4097])
 def test_mlp_forward_and_gradient_match_oracle(im, N):
     import torch
     master = _random_params(22)
