@@ -76,6 +76,11 @@ int im_workspace_destroy(im_workspace *ws);
  *     least this value run the forward search on a cooperative grid
  *     (IM_OPT_FWD_GROUPS workgroups per snapshot word); smaller rounds use
  *     one workgroup per word. Default 0 (always the cooperative grid).
+ *     Cooperative launches can be refused while another process on the
+ *     same device holds the hardware's global barrier resource: a single
+ *     graph's round then runs one workgroup per word (same result), while
+ *     batched selection, lazy engine 1 and a refusal during stream capture
+ *     return IM_EHIP naming the cooperative kernel.
  *   IM_OPT_LAZY_ENGINE: exact evaluations of the lazy path run on the last
  *     engine tier alone, one workgroup per (candidate, word) search (2,
  *     default: candidates are the nodes with the largest bounds, whose
@@ -287,7 +292,10 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
  * most or in all rounds) and keeps the fastest.
  * im_autotune caches its choice per graph signature (n, m, R and a checksum
  * of col and prob) for the life of the process; a cached choice is applied
- * without timing (out->tried = 0). im_autotune_batch tunes on the instances
+ * without timing (out->tried = 0). When the environment variable
+ * IM_TUNE_CACHE names a file, choices are also appended to it (one text line
+ * per signature) and looked up there on a miss, so that they persist across
+ * processes; an unreadable or unwritable file only disables that. im_autotune_batch tunes on the instances
  * it is given (a caller may pass a representative subset of a batch). */
 typedef struct im_tuning {
     int32_t  hub_degree;

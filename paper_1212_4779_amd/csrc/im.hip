@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -735,6 +736,7 @@ struct FwdArgs {
     uint64_t *fq0, *fq1;        // frontier entries (word << 32 | node), capacity W*n
     uint32_t *bq0, *bq1;        // per-word frontier queues of the one-workgroup kernel [W][n]
     uint64_t coop_gain;         // rounds whose seed gain reaches this use the cooperative kernel
+    uint64_t block_floor;       // ... and k_forward_block takes those in [block_floor, coop_gain)
     uint32_t *cnt;              // [3] frontier counts (ring), [3] visit count, [4..4+W) per-word
                                 // visit counts; zero on entry
     uint64_t *vis;              // visited (word << 32 | node), capacity W*n
@@ -1082,6 +1084,7 @@ __global__ __launch_bounds__(FWB_NT) void k_forward_block(FwdArgs a)
     if (a.skip && *a.skip) return;
     if (key == 0) return;
     if ((key >> 32) >= a.coop_gain) return;  // the cooperative kernel runs this round
+    if ((key >> 32) < a.block_floor) return; // an earlier launch ran it
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
     const uint32_t w = blockIdx.x;
     const uint64_t off = (uint64_t)w * a.n;
@@ -2137,6 +2140,39 @@ static void affected_update(const im_graph *g, uint32_t R, uint32_t t, im_worksp
     }
 }
 
+// The forward search of one round. A single graph's round runs in
+// k_forward_block (one workgroup per word) when its seed's gain is below
+// coop_gain, else in the cooperative kernel. A cooperative launch can be
+// refused while another process on the device holds the hardware's global
+// barrier resource; a single graph's round then runs in k_forward_block
+// after all (block_floor keeps the first launch's rounds from running twice).
+// Batches have no such fallback. During stream capture a refusal is an error:
+// the capture would not survive it.
+static int launch_forward(FwdArgs f, im_workspace *ws, bool single, hipStream_t s)
+{
+    f.block_floor = 0;
+    // (with a zero threshold every round is cooperative: the one-workgroup
+    // kernel would return at once)
+    if (single && f.coop_gain > 0) k_forward_block<<<f.W, FWB_NT, 0, s>>>(f);
+    // (a gain is a 32-bit count: above that every round is a small one)
+    if (single && f.coop_gain > 0xFFFFFFFFull) return IM_OK;
+    void *args[] = {&f};
+    const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * f.W);
+    const hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
+                                                    dim3(FWD_NT), args, 0, s);
+    if (e == hipSuccess) return IM_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!single || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return im_fail(IM_EHIP, "cooperative launch of k_forward_coop: %s%s", hipGetErrorString(e),
+                       single ? " (during stream capture)"
+                              : " (batched selection needs cooperative launches)");
+    (void)hipGetLastError();
+    f.block_floor = f.coop_gain;
+    f.coop_gain = ~0ull;
+    k_forward_block<<<f.W, FWB_NT, 0, s>>>(f);
+    return IM_OK;
+}
+
 // A4-A6: one greedy round
 static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seeds_out,
                         uint64_t *gains_out, im_workspace *ws, uint32_t *ctr, hipStream_t s)
@@ -2168,15 +2204,8 @@ static int greedy_round(const im_graph *g, uint32_t R, uint32_t t, uint32_t *see
     f.stats = ws->stats;
     {
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
-        // (with a zero threshold every round is cooperative: the one-workgroup
-        // kernel would return at once)
-        if (ws->batch.count == 1 && ws->coop_gain > 0) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
-        void *args[] = {&f};
-        const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * W);
-        hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
-                                                  dim3(FWD_NT), args, 0, s);
-        if (e != hipSuccess)
-            return im_fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
+        const int rc = launch_forward(f, ws, ws->batch.count == 1, s);
+        if (rc) return rc;
     }
 
     {
@@ -3147,13 +3176,8 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
     f.stats = ws->stats;
     {
         PhaseTimer pt(ws, IM_PH_FORWARD, s);
-        if (ws->coop_gain > 0) k_forward_block<<<W, FWB_NT, 0, s>>>(f);
-        void *args[] = {&f};
-        const unsigned fg = std::min<unsigned>(ws->fwd_grid, ws->fwd_per_word * W);
-        hipError_t e = hipLaunchCooperativeKernel((const void *)k_forward_coop, dim3(fg),
-                                                  dim3(FWD_NT), args, 0, s);
-        if (e != hipSuccess)
-            return im_fail(IM_EHIP, "cooperative launch of k_forward_coop: %s", hipGetErrorString(e));
+        const int rc = launch_forward(f, ws, true, s);
+        if (rc) return rc;
     }
     {
         PhaseTimer pt(ws, IM_PH_CLEAR, s);
@@ -4208,6 +4232,53 @@ struct TuneKey {
     bool operator==(const TuneKey &o) const { return n == o.n && m == o.m && R == o.R && sum == o.sum; }
 };
 static std::vector<std::pair<TuneKey, im_tuning>> g_tune_cache;
+static std::mutex g_tune_mu;   // guards g_tune_cache and the cache file
+
+// The cache file named by IM_TUNE_CACHE (if set): one line per graph
+// signature, "im-tune-1 n m R sum hub tier1 lanes slots coop affected ms".
+// Lines that do not parse are ignored; the last line for a key wins.
+static const char *tune_file() { return getenv("IM_TUNE_CACHE"); }
+
+static void tune_file_lookup(const TuneKey &key)
+{
+    const char *path = tune_file();
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        unsigned long long n, m, R, sum, aff;
+        int hub, t1, lanes, slots, coop;
+        float ms;
+        if (sscanf(line, "im-tune-1 %llu %llu %llu %llu %d %d %d %d %d %llu %f", &n, &m, &R, &sum, &hub,
+                   &t1, &lanes, &slots, &coop, &aff, &ms) != 11)
+            continue;
+        const TuneKey k{n, m, R, sum};
+        if (!(k == key)) continue;
+        im_tuning t;
+        memset(&t, 0, sizeof t);
+        t.hub_degree = hub; t.tier1_shape = t1; t.tier2_lanes = lanes; t.max_slots = slots;
+        t.coop_forward = coop; t.affected_gain = aff; t.ms = ms; t.tried = 0;
+        bool found = false;
+        for (auto &kv : g_tune_cache)
+            if (kv.first == k) { kv.second = t; found = true; }
+        if (!found) g_tune_cache.push_back({k, t});
+    }
+    fclose(f);
+}
+
+static void tune_file_append(const TuneKey &k, const im_tuning &t)
+{
+    const char *path = tune_file();
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;   // the in-process cache still holds the choice
+    fprintf(f, "im-tune-1 %llu %llu %llu %llu %d %d %d %d %d %llu %.4f\n", (unsigned long long)k.n,
+            (unsigned long long)k.m, (unsigned long long)k.R, (unsigned long long)k.sum, t.hub_degree,
+            t.tier1_shape, t.tier2_lanes, t.max_slots, t.coop_forward,
+            (unsigned long long)t.affected_gain, t.ms);
+    fclose(f);
+}
 
 static int graph_signature(const im_graph *g, uint32_t R, im_workspace *ws, hipStream_t s, TuneKey *key)
 {
@@ -4314,6 +4385,10 @@ static int tune_affected(uint64_t nR, im_workspace *ws, hipStream_t s, Run run, 
 
 static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, bool *hit)
 {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    bool mem = false;
+    for (auto &kv : g_tune_cache) mem = mem || kv.first == key;
+    if (!mem) tune_file_lookup(key);
     for (auto &kv : g_tune_cache)
         if (kv.first == key) {
             const im_tuning &t = kv.second;
@@ -4376,7 +4451,11 @@ extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_work
     dfree(sd);
     dfree(gd);
     if (rc) return rc;
-    g_tune_cache.push_back({key, best});
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache.push_back({key, best});
+        tune_file_append(key, best);
+    }
     if (out) *out = best;
     return IM_OK;
 }

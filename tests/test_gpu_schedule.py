@@ -198,3 +198,73 @@ def test_affected_set_recompute_in_a_plan_and_the_tuner(im):
         assert plan.seeds.cpu().tolist() == gold["seeds"]
         assert plan.gains.cpu().tolist() == gold["gains"]
     plan.close()
+
+
+def test_autotune_choice_persists_in_the_cache_file(im, tmp_path):
+    # IM_TUNE_CACHE: the first process tunes and appends its choice; a second
+    # process finds it in the file and applies it without timing
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, IM_TUNE_CACHE=str(cache))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import json, sys; sys.path.insert(0, %r)\n"
+            "import paper_1212_4779_amd as im\n"
+            "from paper_1212_4779_amd import graphgen as gg\n"
+            "g = gg.workload_graph('tiny_uic')\n"
+            "d = im.Graph.from_numpy(g.row_ptr, g.col, g.prob, device='cuda:0')\n"
+            "t = im.autotune(d, 64, 1)\n"
+            "s, gn, _ = im.select(d, 64, 10, 1)\n"
+            "print(json.dumps([t, s.cpu().tolist()]))\n" % root)
+    outs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    (t1, s1), (t2, s2) = outs
+    assert t1["tried"] > 0 and t2["tried"] == 0
+    keys = ("hub_degree", "tier1_shape", "tier2_lanes", "max_slots", "coop_forward", "affected_gain")
+    assert {k: t1[k] for k in keys} == {k: t2[k] for k in keys}
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("im-tune-1 2000 20000 64 ")
+    with open(os.path.join(GOLDEN, "tiny_uic.json")) as f:
+        assert s1 == s2 == json.load(f)["seeds"]
+
+
+def test_second_process_selects_with_every_round_cooperative(im, tmp_path):
+    # a process started while this one holds the device: when its cooperative
+    # launches are refused, a single graph's rounds run in the per-word
+    # workgroups instead and the seeds are unchanged; a batch either runs or
+    # reports an error that names the cooperative launch
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import json, sys; sys.path.insert(0, %r)\n"
+            "import paper_1212_4779_amd as im\n"
+            "from paper_1212_4779_amd import graphgen as gg\n"
+            "g = gg.workload_graph('tiny_uic')\n"
+            "d = im.Graph.from_numpy(g.row_ptr, g.col, g.prob, device='cuda:0')\n"
+            "out = {}\n"
+            "for gain in (0, 64, 2**63 - 1):\n"
+            "    ws = im.Workspace()\n"
+            "    ws.set_coop_gain(gain)\n"
+            "    s, gn, _ = im.select(d, 64, 10, 1, ws=ws)\n"
+            "    out[str(gain)] = [s.cpu().tolist(), gn.cpu().tolist()]\n"
+            "try:\n"
+            "    b = im.select_batch([(d, 64, 10, 1), (d, 64, 10, 1)])\n"
+            "    out['batch'] = [[s.cpu().tolist(), gn.cpu().tolist()] for s, gn in b]\n"
+            "except im.ImError as e:\n"
+            "    out['batch_error'] = str(e)\n"
+            "print(json.dumps(out))\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    with open(os.path.join(GOLDEN, "tiny_uic.json")) as f:
+        gold = json.load(f)
+    for gain in ("0", "64", str(2**63 - 1)):
+        assert out[gain] == [gold["seeds"], gold["gains"]], gain
+    if "batch" in out:
+        assert out["batch"] == [[gold["seeds"], gold["gains"]]] * 2
+    else:
+        assert "k_forward_coop" in out["batch_error"]
