@@ -171,7 +171,10 @@ typedef struct im_stats {
     uint64_t max_levels[3][3]; /* per pass and tier: the most search levels one   */
                                /* workgroup ran in any launch of the call (the    */
                                /* launch's critical path in levels)               */
-    uint64_t reserved[7];
+    uint64_t barrier_failures; /* grid barriers of the cooperative kernels whose */
+                               /* wait timed out (always 0 on a working device;   */
+                               /* the launch was then abandoned, results invalid) */
+    uint64_t reserved[6];
 } im_stats;
 
 int im_stats_get(im_workspace *ws, im_stats *out);

@@ -67,11 +67,13 @@ class ImStats(ctypes.Structure):
                 [("fwd_levels", ctypes.c_uint64), ("fwd_entries", ctypes.c_uint64),
                  ("celf_batches", ctypes.c_uint64), ("celf_fallbacks", ctypes.c_uint64),
                  ("max_levels", (ctypes.c_uint64 * 3) * 3),
-                 ("reserved", ctypes.c_uint64 * 7)])
+                 ("barrier_failures", ctypes.c_uint64),
+                 ("reserved", ctypes.c_uint64 * 6)])
 
     def as_dict(self):
         d = {f: int(getattr(self, f)) for f in STAT_FIELDS + ("fwd_levels", "fwd_entries",
-                                                               "celf_batches", "celf_fallbacks")}
+                                                               "celf_batches", "celf_fallbacks",
+                                                               "barrier_failures")}
         for p, pn in enumerate(PASSES):
             for t in range(3):
                 d[f"max_levels_{pn}_t{t}"] = int(self.max_levels[p][t])

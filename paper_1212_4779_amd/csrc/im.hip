@@ -724,6 +724,11 @@ __global__ __launch_bounds__(256) void k_argmax(const uint32_t *gain, const uint
 // N[w][x] (newly) collects the newly covered bits; afterwards covered |= N and
 // tnodes[w] lists the nodes with N[w][x] != 0 (the reverse tasks).
 // ---------------------------------------------------------------------------
+// per-round forward counters: 3 frontier counts, the visit count, one visit
+// count per word, then the grid barrier's arrival counter and abort flag
+constexpr int FWD_CTRS = 4 + 64 + 4;
+constexpr int FWD_BAR = 4 + 64;
+
 struct FwdArgs {
     const uint32_t *skip;       // non-zero *skip: the round was committed already (lazy path)
     const uint32_t *row, *col;
@@ -738,7 +743,7 @@ struct FwdArgs {
     uint64_t coop_gain;         // rounds whose seed gain reaches this use the cooperative kernel
     uint64_t block_floor;       // ... and k_forward_block takes those in [block_floor, coop_gain)
     uint32_t *cnt;              // [3] frontier counts (ring), [3] visit count, [4..4+W) per-word
-                                // visit counts; zero on entry
+                                // visit counts, [FWD_BAR..+2) grid barrier; zero on entry
     uint64_t *vis;              // visited (word << 32 | node), capacity W*n
     uint32_t *tnodes, *tcounts;
     // reverse-task packing counts of the newly covered (word, node) pairs, or
@@ -817,11 +822,58 @@ __device__ __forceinline__ void wave_append_n(uint32_t cnt, const uint64_t *ent,
     for (uint32_t i = 0; i < cnt; i++) list[base + i] = ent[i];
 }
 
+// Grid-wide barrier of a cooperative launch. The hardware barrier behind
+// cooperative_groups' grid sync costs about 9 us for 64 workgroups on this
+// device (and 33 us for 256); this one, about 2 us for 64. bar[0] counts
+// arrivals (zero at launch, never reset): the k-th barrier of the launch is
+// complete once it reaches k * gridDim.x. Each wavefront first waits for its
+// own loads, stores and atomics (a workgroup-scope release does not wait for
+// them on this target), so that one agent-scope release by the arriving lane
+// publishes the whole workgroup's writes; that lane polls with relaxed loads
+// and then acquires for the workgroup (the vector L1 is per compute unit).
+// The launch is cooperative, so every workgroup is resident and the poll
+// ends; it is bounded all the same (about 10 s of the 100 MHz wall clock).
+// A workgroup whose poll times out raises bar[1], counts the failure in
+// stats[ST_BARRIER_FAIL] and returns false, as does every later barrier of
+// any workgroup: the caller then leaves the kernel, so every workgroup exits.
+constexpr int ST_BARRIER_FAIL = 60;
+static_assert(ST_BARRIER_FAIL >= ST_MAXLV_BASE + 9 && ST_BARRIER_FAIL < ST_COUNT,
+              "barrier failure counter must use a free statistics slot");
+constexpr uint64_t BARRIER_TIMEOUT_TICKS = 1000000000ull;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t &k, unsigned long long *stats)
+{
+    __shared__ uint32_t s_ok;
+    k++;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = k * gridDim.x;
+        const uint64_t t0 = wall_clock64();
+        uint32_t polls = 0;
+        while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if ((++polls & 255u) == 0 &&
+                (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                 wall_clock64() - t0 > BARRIER_TIMEOUT_TICKS)) {
+                ok = 0;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (ok && __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+        if (!ok && atomicExch(&bar[1], 1u) == 0) atomicAdd(&stats[ST_BARRIER_FAIL], 1ull);
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
 __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
 {
-    namespace cg = cooperative_groups;
-    cg::grid_group grid = cg::this_grid();
     __shared__ FwdLds L;
+    uint32_t nbar = 0;
     const int tid = threadIdx.x;
     const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
     const bool single = a.b.count == 1;
@@ -864,7 +916,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     uint32_t lev0 = 0;
     // the seed's visit entries and counts above must be in place before any
     // workgroup appends to the same lists
-    grid.sync();
+    if (!grid_barrier(a.cnt + FWD_BAR, nbar, a.stats)) return;
     if (split0) {
         // every workgroup builds the prefix over (word, bit) of the seed's
         // live-list lengths restricted to its uncovered bits, then takes an
@@ -909,7 +961,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
         arcs += tot;
         lev0 = 1;
     }
-    grid.sync();
+    if (!grid_barrier(a.cnt + FWD_BAR, nbar, a.stats)) return;
     for (uint32_t lev = lev0;; lev++) {
         const uint32_t nf = group_load(&a.cnt[lev % 3], &L.bcast);
         if (nf == 0) break;
@@ -1008,7 +1060,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 expand_hubs<FWD_NT, 16, FWD_U>(L.H, nhub, a.hub, a.W, word_of, relax, flush, arcs);
             }
         }
-        grid.sync();
+        if (!grid_barrier(a.cnt + FWD_BAR, nbar, a.stats)) return;
     }
     // covered |= newly for every visited (word, node); per-word visit lists
     // (the reverse tasks) are built from the unified list, one atomic per
@@ -1058,7 +1110,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
     if (pack)
         for (uint32_t j = tid; j < a.W * 64; j += FWD_NT)
             if (L.pk[j]) atomicAdd(&a.bcnt[j], L.pk[j]);
-    grid.sync();
+    if (!grid_barrier(a.cnt + FWD_BAR, nbar, a.stats)) return;
     if (gtid < a.W) {
         const uint32_t c = coherent_load(&a.cnt[4 + gtid]);
         a.tcounts[gtid] = c;
@@ -1246,8 +1298,6 @@ constexpr int T2W_NT = 1024;   // the wide variant: more lanes per task
 constexpr int T2S_NT = 64;     // the narrow variant: more tasks at once (long, thin searches)
 // per-phase device counters: grab0, n1, grab1, n2, grab2
 constexpr int PH_CTRS = 8;
-// per-round forward counters: 3 frontier counts + one visit count per word
-constexpr int FWD_CTRS = 4 + 64;
 
 // ---------------------------------------------------------------------------
 // workspace
@@ -2869,7 +2919,7 @@ struct EvalArgs {
     const uint64_t *covered;
     uint64_t *reach, *pend;      // [Vmax][n], zero on entry and on exit
     uint64_t *fq0, *fq1, *vis;   // (vw << 32 | node), capacity V * n each
-    uint32_t *cnt;               // [4]: frontier ring [3], visit count; zero on entry
+    uint32_t *cnt;               // [8]: frontier ring [3], visit count, [4..6) grid barrier; zero on entry
     const uint32_t *cand;        // V / W candidates
     uint32_t *ev;
     unsigned long long *stats;
@@ -2893,9 +2943,8 @@ __device__ __forceinline__ void eval_relax(const EvalArgs &a, uint32_t vw, uint3
 
 __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
 {
-    namespace cg = cooperative_groups;
-    cg::grid_group grid = cg::this_grid();
     __shared__ FwdLds L;
+    uint32_t nbar = 0;
     __shared__ uint32_t slot_sum[256];
     const int tid = threadIdx.x;
     const uint64_t gtid = (uint64_t)blockIdx.x * FWD_NT + tid;
@@ -2911,7 +2960,7 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
             a.fq0[atomicAdd(&a.cnt[0], 1u)] = ((uint64_t)vw << 32) | c;
         }
     }
-    grid.sync();
+    if (!grid_barrier(a.cnt + 4, nbar, a.stats)) return;
     uint64_t arcs = 0;
     for (uint32_t lev = 0;; lev++) {
         const uint32_t nf = group_load(&a.cnt[lev % 3], &L.bcast);
@@ -3013,7 +3062,7 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
                 expand_hubs<FWD_NT, 16, FWD_U>(L.H, nhub, a.hub, a.W, word_of, relax, flush, arcs);
             }
         }
-        grid.sync();
+        if (!grid_barrier(a.cnt + 4, nbar, a.stats)) return;
     }
     // per-candidate sums of the reached bits; reach returns to zero
     const uint32_t nslot = a.V / a.W;
@@ -3092,7 +3141,7 @@ static int reserve_eval(im_workspace *ws, uint32_t n, uint32_t V)
     if (need > ws->cap_eval) {
         if ((rc = dalloc(&ws->e_reach, need)) || (rc = dalloc(&ws->e_pend, need)) ||
             (rc = dalloc(&ws->e_fq0, need)) || (rc = dalloc(&ws->e_fq1, need)) ||
-            (rc = dalloc(&ws->e_vis, need)) || (rc = dalloc(&ws->e_cnt, 4)))
+            (rc = dalloc(&ws->e_vis, need)) || (rc = dalloc(&ws->e_cnt, 8)))
             return rc;
         HIPCHK(hipMemset(ws->e_reach, 0, need * sizeof(uint64_t)));
         HIPCHK(hipMemset(ws->e_pend, 0, need * sizeof(uint64_t)));
@@ -3117,7 +3166,7 @@ static int eval_coop(const im_graph *g, uint32_t R, uint32_t ncand, uint32_t vma
         const uint32_t nc = std::min(per, ncand - c0);
         e.cand = ws->c_cand + c0;
         e.V = nc * W;
-        fill<uint32_t>(ws->e_cnt, 4, 0u, s);
+        fill<uint32_t>(ws->e_cnt, 8, 0u, s);   // counters and the grid barrier's pair
         void *args[] = {&e};
         hipError_t err = hipLaunchCooperativeKernel((const void *)k_eval_coop, dim3(ws->eval_grid),
                                                     dim3(FWD_NT), args, 0, s);
@@ -3600,6 +3649,7 @@ extern "C" int im_stats_get(im_workspace *ws, im_stats *out)
     out->fwd_entries = h[ST_FWD_ENTRIES];
     out->celf_batches = h[ST_CELF_BATCHES];
     out->celf_fallbacks = h[ST_CELF_FALLBACKS];
+    out->barrier_failures = h[ST_BARRIER_FAIL];
     for (int p = 0; p < 3; p++)
         for (int t = 0; t < 3; t++) {
             out->relax[p][t] = h[st_tier(p, t, F_RELAX)];

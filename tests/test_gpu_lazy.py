@@ -78,6 +78,7 @@ def test_lazy_batch1_evaluations_equal_oracle_celf(im, name, engine):
     assert seeds.cpu().tolist() == s_ref.tolist()
     assert gains.cpu().tolist() == g_ref.tolist()
     assert ws.stats()["celf_evals"] == st_ref["celf_evals"]
+    assert ws.stats()["barrier_failures"] == 0
 
 
 @pytest.mark.parametrize("policy", [1, 2])

@@ -118,6 +118,7 @@ def test_select_full_trace(im, case):
     for a, b in (("trav_init", "trav_init"), ("trav_fwd", "trav_fwd"), ("trav_rev", "trav_rev"),
                  ("decrements", "decrements")):
         assert gs[a] == st[b], a
+    assert gs["barrier_failures"] == 0
 
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[6]], ids=["tiny_uic", "dense_p30", "hub_star"])
@@ -160,6 +161,7 @@ def test_schedule_invariance_forward(im, case):
         assert np.array_equal(o[1], g_ref.astype(np.int64))
         assert np.array_equal(o[2], outs[0][2])
         assert o[3]["trav_fwd"] == st["trav_fwd"]
+        assert o[3]["barrier_failures"] == 0
 
 
 def test_repeat_and_workspace_reuse(im):
