@@ -369,6 +369,7 @@ struct LdsState {
     uint32_t wsum[NT / 64 + 1];
     unsigned long long red[NT / 64];
     uint32_t s_task[T], s_src[T], s_word[T], s_cnt[T], s_next[T], s_ovf[T], s_act[T], s_new[T];
+    uint32_t s_sum[T];   // MODE_COUNT: reached bits of each finishing slot
     uint32_t wpre[65];
     HubBatch<NT, (NT == 64 ? 2 : 16)> H;
     uint32_t nf, nn, tnext, tend, ntasks, done, chunk, snext;
@@ -450,11 +451,19 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
         L.keys[i] = IM_EMPTY; L.reach[i] = 0; L.pend[i] = 0; L.deg[i] = 0;
     }
     if (tid < T) {
-        L.s_act[tid] = 0; L.s_cnt[tid] = 0; L.s_next[tid] = 0; L.s_ovf[tid] = 0;
+        L.s_act[tid] = 0; L.s_cnt[tid] = 0; L.s_next[tid] = 0; L.s_ovf[tid] = 0; L.s_sum[tid] = 0;
     }
+    if (MODE == MODE_DEC && tid < 64) {
+        // exclusive prefix over words of the task counts, one lane per word
+        // (the loads are issued together instead of one after another)
+        const uint32_t c = (uint32_t)tid < a.W ? a.gcnt[tid] + a.mcnt[tid] : 0u;
+        const uint32_t incl = wave_incl_scan(c);
+        if ((uint32_t)tid < a.W) L.wpre[tid] = incl - c;
+        if (tid == 63) L.wpre[a.W] = incl;
+    }
+    __syncthreads();
     if (tid == 0) {
         L.nf = 0; L.nn = 0; L.tnext = 0; L.tend = 0; L.done = 0; L.H.n = 0;
-        if (MODE == MODE_DEC) fill_wpre(a, L.wpre);
         L.ntasks = a.in_q ? *a.in_n : (MODE == MODE_COUNT ? a.ntasks : L.wpre[a.W]);
         // Task assignment. When the grid has a slot for every task, each
         // workgroup strides over the task ids (no atomics, every task starts
@@ -501,7 +510,32 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
         // ---- seed the new tasks: lane l of the first wavefront inserts source l.
         // The sources of all new slots are looked up first, so that their
         // dependent load chains overlap instead of running one slot after another.
-        if (tid < 64) {
+        if (MODE == MODE_COUNT) {
+            // one source per task: lane s seeds slot s. A new slot's table is
+            // empty (every finished slot is cleared), so the source takes its
+            // hash position without probing, and the seeds join the frontier
+            // with one wavefront-wide append.
+            if (tid < 64) {
+                const uint32_t sn = (uint32_t)tid < (uint32_t)T ? L.s_new[tid] : NONE;
+                uint64_t bits = 0;
+                uint32_t pos = 0;
+                if (sn != NONE) {
+                    const uint32_t tq = a.in_q ? a.in_q[sn] : sn;
+                    uint32_t w, src;
+                    task_source(a, MODE, tq, L.wpre, 0u, w, src, bits);
+                    L.s_task[tid] = tq; L.s_src[tid] = src; L.s_word[tid] = w;
+                    // a task without start bits leaves the slot idle
+                    L.s_act[tid] = bits ? 1u : 0u;
+                    if (bits) {
+                        pos = (uint32_t)tid * CS + ((src * 0x9E3779B1u) >> (32 - LOG_CS));
+                        L.keys[pos] = src; L.reach[pos] = bits; L.pend[pos] = bits;
+                        L.s_cnt[tid] = 1;
+                    }
+                }
+                const uint32_t at = wave_append(bits != 0, &L.nf);
+                if (bits) L.fr[cur][at] = pos;
+            }
+        } else if (tid < 64) {
             uint32_t tt[T], ww[T], ss[T];
             uint64_t bb[T];
 #pragma unroll
@@ -641,44 +675,65 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
             }
         }
 
-        // ---- finish slots whose search ended or overflowed
-        bool any_ovf_fin = false;
+        // ---- finish slots whose search ended or overflowed, all in one pass:
+        // fin (bit s: slot s finishes) and ovfm (bit s: it is handed over)
+        // are the same in every thread (read from LDS after a barrier)
+        uint32_t fin = 0, ovfm = 0;
+#pragma unroll
         for (int s = 0; s < T; s++) {
             if (!L.s_act[s]) continue;
             const bool ovf = L.s_ovf[s] != 0;
             if (!ovf && L.s_next[s] != 0) continue;
-            const uint32_t base = s * CS;
-            if (ovf) {
-                any_ovf_fin = true;
-                if (tid == 0) {
-                    uint32_t q = atomicAdd(a.out_n, 1u);
-                    a.out_q[q] = L.s_task[s];
-                    st_ovf += 1;
-                }
-            } else {
-                uint64_t cnt = 0;
-                for (int i = tid; i < CS; i += NT) {
-                    uint32_t key = L.keys[base + i];
-                    if (key == IM_EMPTY) continue;
-                    uint32_t pc = (uint32_t)__popcll(L.reach[base + i]);
-                    uint32_t dg = L.deg[base + i];
+            fin |= 1u << s;
+            if (ovf) ovfm |= 1u << s;
+        }
+        const bool any_ovf_fin = ovfm != 0;
+        if (fin) {
+            if (tid < 64) {
+                // handed-over tasks: one append for the wavefront
+                const bool h = (uint32_t)tid < (uint32_t)T && ((ovfm >> tid) & 1u);
+                const uint64_t bal = __ballot(h);
+                uint32_t q0 = 0;
+                if (bal && tid == 0) q0 = atomicAdd(a.out_n, (uint32_t)__popcll(bal));
+                q0 = __shfl(q0, 0, 64);
+                if (h) a.out_q[q0 + (uint32_t)__popcll(bal & ((1ull << tid) - 1ull))] = L.s_task[tid];
+                if (tid == 0) st_ovf += (uint64_t)__popcll(bal);
+            }
+            // the entries of the finishing slots, slot after slot, spread
+            // over all threads
+            const uint32_t nfin = (uint32_t)__popc(fin);
+            for (uint32_t j = tid; j < nfin * CS; j += NT) {
+                uint32_t r = j / CS, f = fin;
+                for (uint32_t c = 0; c < r; c++) f &= f - 1u;
+                const uint32_t s = (uint32_t)__ffs(f) - 1u;
+                const uint32_t i = s * CS + (j % CS);
+                const uint32_t key = L.keys[i];
+                uint32_t pc = 0;
+                if (key != IM_EMPTY && !((ovfm >> s) & 1u)) {
+                    pc = (uint32_t)__popcll(L.reach[i]);
+                    const uint32_t dg = L.deg[i];
                     st_relax += dg;
                     st_reached += 1;
                     st_trav += (uint64_t)pc * dg;
-                    if (MODE == MODE_COUNT) cnt += pc;
-                    else { atomicSub(&a.gain[key], pc); st_dec += pc; }
+                    if (MODE == MODE_DEC) { atomicSub(&a.gain[key], pc); st_dec += pc; }
                 }
                 if (MODE == MODE_COUNT) {
-                    cnt = group_sum<NT>(cnt, L.red);
-                    if (tid == 0) atomicAdd(&a.gain[L.s_src[s]], (uint32_t)cnt);
+                    // one slot per aligned segment of min(CS, 64) lanes: sum
+                    // within the segment, one LDS add per segment
+                    constexpr int SEG = CS < 64 ? CS : 64;
+#pragma unroll
+                    for (int o = SEG / 2; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+                    if ((tid & (SEG - 1)) == 0 && pc) atomicAdd(&L.s_sum[s], pc);
                 }
-            }
-            for (int i = tid; i < CS; i += NT) {
-                L.keys[base + i] = IM_EMPTY; L.reach[base + i] = 0;
-                L.pend[base + i] = 0; L.deg[base + i] = 0;
+                L.keys[i] = IM_EMPTY; L.reach[i] = 0; L.pend[i] = 0; L.deg[i] = 0;
             }
             __syncthreads();
-            if (tid == 0) { L.s_act[s] = 0; L.s_cnt[s] = 0; L.s_ovf[s] = 0; }
+            if ((uint32_t)tid < (uint32_t)T && ((fin >> tid) & 1u)) {
+                if (MODE == MODE_COUNT && !((ovfm >> tid) & 1u))
+                    atomicAdd(&a.gain[L.s_src[tid]], L.s_sum[tid]);
+                L.s_sum[tid] = 0;
+                L.s_act[tid] = 0; L.s_cnt[tid] = 0; L.s_ovf[tid] = 0;
+            }
             __syncthreads();
         }
 
