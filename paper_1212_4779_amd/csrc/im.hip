@@ -797,13 +797,17 @@ __device__ __forceinline__ void fwd_relax(const FwdArgs &a, uint32_t w, uint32_t
     const uint64_t off = (uint64_t)w * a.n;
     first = false;
     push = false;
-    if (bits) bits &= ~a.covered[off + v];
     if (!bits) return;
-    uint64_t old = atomicOr((unsigned long long *)&a.newly[off + v], (unsigned long long)bits);
-    uint64_t nb = bits & ~old;
+    // covered takes this round's bits as they are reached: the bits it did
+    // not hold are new (covered by earlier rounds or reached already this
+    // round, they are not), and the newly / pend updates, which depend only
+    // on them, go out together
+    const uint64_t oc = atomicOr((unsigned long long *)&a.covered[off + v], (unsigned long long)bits);
+    const uint64_t nb = bits & ~oc;
     if (!nb) return;
-    first = old == 0;
-    uint64_t op = atomicOr((unsigned long long *)&a.pend[off + v], (unsigned long long)nb);
+    const uint64_t on = atomicOr((unsigned long long *)&a.newly[off + v], (unsigned long long)nb);
+    const uint64_t op = atomicOr((unsigned long long *)&a.pend[off + v], (unsigned long long)nb);
+    first = on == 0;
     push = op == 0;
 }
 
@@ -901,6 +905,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 uint64_t start = im_valid_bits(R, w) & ~a.covered[off + sv];
                 if (!start) continue;
                 a.newly[off + sv] = start;
+                a.covered[off + sv] |= start;
                 a.vis[atomicAdd(&a.cnt[3], 1u)] = ((uint64_t)w << 32) | sv;
                 if (!split0) {
                     a.pend[off + sv] = start;
@@ -924,7 +929,8 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
         const uint32_t w = tid / 64, b = tid % 64;
         uint32_t c = 0, o = 0;
         if (w < a.W) {
-            const uint64_t start = im_valid_bits(a.R, w) & ~a.covered[(uint64_t)w * a.n + v];
+            // the seed's start bits as committed (covered holds them already)
+            const uint64_t start = a.newly[(uint64_t)w * a.n + v];
             const uint32_t *ho = a.hub.off + ((uint64_t)hs0 * a.W + w) * 65;
             o = ho[b];
             c = ((start >> b) & 1ull) ? ho[b + 1] - o : 0u;
@@ -962,11 +968,16 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
         lev0 = 1;
     }
     if (!grid_barrier(a.cnt + FWD_BAR, nbar, a.stats)) return;
+    const uint64_t fcap = (uint64_t)a.W * a.n;   // capacity of each frontier queue
     for (uint32_t lev = lev0;; lev++) {
-        const uint32_t nf = group_load(&a.cnt[lev % 3], &L.bcast);
-        if (nf == 0) break;
         const uint64_t *cur = (lev & 1) ? a.fq1 : a.fq0;
         uint64_t *nxt = (lev & 1) ? a.fq0 : a.fq1;
+        // this workgroup's first frontier entry is loaded while the level's
+        // size is read (it is used only if it lies below that size)
+        const uint32_t i0 = blockIdx.x * FWD_NT + tid;
+        const uint64_t e0 = i0 < fcap ? cur[i0] : 0ull;
+        const uint32_t nf = group_load(&a.cnt[lev % 3], &L.bcast);
+        if (nf == 0) break;
         uint32_t *ncnt = &a.cnt[(lev + 1) % 3];
         // the ring slot of level lev-1 was last read before the previous barrier
         if (gtid == 0) a.cnt[(lev + 2) % 3] = 0;
@@ -975,7 +986,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
             uint32_t deg = 0, rs = 0, w = 0, aux = 0;
             uint64_t d = 0;
             if (i < nf) {
-                uint64_t e = cur[i];
+                const uint64_t e = i == i0 ? e0 : cur[i];
                 w = (uint32_t)(e >> 32);
                 uint32_t x = (uint32_t)e;
                 uint32_t hs = a.hub.slot[x];
@@ -1062,9 +1073,8 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
         }
         if (!grid_barrier(a.cnt + FWD_BAR, nbar, a.stats)) return;
     }
-    // covered |= newly for every visited (word, node); per-word visit lists
-    // (the reverse tasks) are built from the unified list, one atomic per
-    // (workgroup, word) and chunk
+    // per-word visit lists (the reverse tasks) are built from the unified
+    // list, one atomic per (workgroup, word) and chunk
     uint64_t relax = 0, trav = 0;
     const uint32_t nv = group_load(&a.cnt[3], &L.bcast);
     // reused (W <= 64): per-word visit and multi-bit counts of this chunk, and
@@ -1083,8 +1093,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
             w = (uint32_t)(e >> 32);
             x = (uint32_t)e;
             const uint64_t off = (uint64_t)w * a.n;
-            uint64_t b = a.newly[off + x];
-            a.covered[off + x] |= b;
+            uint64_t b = a.newly[off + x];   // covered took these bits as they were reached
             uint32_t dg = a.row[x + 1] - a.row[x];
             relax += dg;
             trav += (uint64_t)__popcll(b) * dg;
