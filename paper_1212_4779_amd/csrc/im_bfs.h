@@ -465,13 +465,15 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
     if (tid == 0) {
         L.nf = 0; L.nn = 0; L.tnext = 0; L.tend = 0; L.done = 0; L.H.n = 0;
         L.ntasks = a.in_q ? *a.in_n : (MODE == MODE_COUNT ? a.ntasks : L.wpre[a.W]);
-        // Task assignment. When the grid has a slot for every task, each
-        // workgroup strides over the task ids (no atomics, every task starts
-        // at once, spread over all workgroups: chunk = 0). Otherwise tasks
-        // are grabbed from one counter in chunks of at least 8, so that the
-        // counter, one address for the whole grid, sees few atomics.
+        // Task assignment. With up to 64 tasks per slot, each workgroup
+        // strides over the task ids (no atomics; the workgroups' task counts
+        // differ by at most one, and all of them start at once: chunk = 0).
+        // With more, tasks are grabbed from one counter in chunks of at least
+        // 8 (the counter, one address for the whole grid, sees few atomics),
+        // which balances long runs of tasks better and keeps consecutive
+        // task ids, whose sources share cache lines, in one workgroup.
         const uint32_t slots = gridDim.x * (uint32_t)T;
-        L.chunk = L.ntasks <= slots ? 0u : min(256u, max(8u, L.ntasks / slots));
+        L.chunk = L.ntasks <= 64u * slots ? 0u : min(256u, max(8u, L.ntasks / slots));
         L.snext = blockIdx.x;
     }
     __syncthreads();
