@@ -292,14 +292,17 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
  * and the first 16 rounds under four per-round update strategies (the
  * IM_OPT_AFFECTED_GAIN thresholds 0, n R / 4096, n R / 256 and 2^62: reverse
  * decrements in every round, the affected-set recompute in the small, in
- * most or in all rounds) and keeps the fastest.
+ * most or in all rounds) and keeps the fastest; when the schedule uses the
+ * cooperative forward search, it last times that search's width
+ * (IM_OPT_FWD_GROUPS 16 or 32 workgroups per word) on the same trial.
  * im_autotune caches its choice per graph signature (n, m, R and a checksum
  * of col and prob) for the life of the process; a cached choice is applied
  * without timing (out->tried = 0). When the environment variable
  * IM_TUNE_CACHE names a file, choices are also appended to it (one text line
  * per signature) and looked up there on a miss, so that they persist across
- * processes; an unreadable or unwritable file only disables that. im_autotune_batch tunes on the instances
- * it is given (a caller may pass a representative subset of a batch). */
+ * processes; an unreadable or unwritable file only disables that.
+ * im_autotune_batch tunes the schedule on the instances it is given (a
+ * caller may pass a representative subset of a batch). */
 typedef struct im_tuning {
     int32_t  hub_degree;
     int32_t  tier1_shape;
@@ -309,6 +312,9 @@ typedef struct im_tuning {
     float    ms;           /* trial time of the chosen schedule         */
     uint32_t tried;        /* schedules timed (0: taken from the cache)  */
     uint64_t affected_gain;/* IM_OPT_AFFECTED_GAIN chosen (single graphs) */
+    int32_t  fwd_groups;   /* IM_OPT_FWD_GROUPS chosen (single graphs with the
+                              cooperative forward search; else the workspace's) */
+    int32_t  reserved;
 } im_tuning;
 int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,
                 im_tuning *out);
@@ -416,7 +422,7 @@ int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_t seed, uin
 
 /* Lazy-path tuning (synchronous; the schedule part of the autotuner, like
  * im_autotune, never changes a result): the lazy selection of the first
- * min(k, 8) rounds (at least 2) is timed under each evaluation engine
+ * min(k, 64) rounds (at least 2) is timed under each evaluation engine
  * (IM_OPT_LAZY_ENGINE 2 and 0) and batch size (1, 2, 4, 8, 16) with the
  * given model (NULL: bound order); the fastest pair is set on the workspace
  * (IM_OPT_LAZY_ENGINE, IM_OPT_LAZY_BATCH), so that im_select_lazy with

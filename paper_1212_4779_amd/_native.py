@@ -91,10 +91,11 @@ class ImTuning(ctypes.Structure):
     _fields_ = [("hub_degree", ctypes.c_int32), ("tier1_shape", ctypes.c_int32),
                 ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32),
-                ("affected_gain", ctypes.c_uint64)]
+                ("affected_gain", ctypes.c_uint64), ("fwd_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class ImLazyTuning(ctypes.Structure):

@@ -4294,7 +4294,7 @@ static std::vector<std::pair<TuneKey, im_tuning>> g_tune_cache;
 static std::mutex g_tune_mu;   // guards g_tune_cache and the cache file
 
 // The cache file named by IM_TUNE_CACHE (if set): one line per graph
-// signature, "im-tune-1 n m R sum hub tier1 lanes slots coop affected ms".
+// signature, "im-tune-2 n m R sum hub tier1 lanes slots coop affected fwd ms".
 // Lines that do not parse are ignored; the last line for a key wins.
 static const char *tune_file() { return getenv("IM_TUNE_CACHE"); }
 
@@ -4307,17 +4307,17 @@ static void tune_file_lookup(const TuneKey &key)
     char line[512];
     while (fgets(line, sizeof line, f)) {
         unsigned long long n, m, R, sum, aff;
-        int hub, t1, lanes, slots, coop;
+        int hub, t1, lanes, slots, coop, fwd;
         float ms;
-        if (sscanf(line, "im-tune-1 %llu %llu %llu %llu %d %d %d %d %d %llu %f", &n, &m, &R, &sum, &hub,
-                   &t1, &lanes, &slots, &coop, &aff, &ms) != 11)
+        if (sscanf(line, "im-tune-2 %llu %llu %llu %llu %d %d %d %d %d %llu %d %f", &n, &m, &R, &sum, &hub,
+                   &t1, &lanes, &slots, &coop, &aff, &fwd, &ms) != 12)
             continue;
         const TuneKey k{n, m, R, sum};
         if (!(k == key)) continue;
         im_tuning t;
         memset(&t, 0, sizeof t);
         t.hub_degree = hub; t.tier1_shape = t1; t.tier2_lanes = lanes; t.max_slots = slots;
-        t.coop_forward = coop; t.affected_gain = aff; t.ms = ms; t.tried = 0;
+        t.coop_forward = coop; t.affected_gain = aff; t.fwd_groups = fwd; t.ms = ms; t.tried = 0;
         bool found = false;
         for (auto &kv : g_tune_cache)
             if (kv.first == k) { kv.second = t; found = true; }
@@ -4332,10 +4332,10 @@ static void tune_file_append(const TuneKey &k, const im_tuning &t)
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;   // the in-process cache still holds the choice
-    fprintf(f, "im-tune-1 %llu %llu %llu %llu %d %d %d %d %d %llu %.4f\n", (unsigned long long)k.n,
+    fprintf(f, "im-tune-2 %llu %llu %llu %llu %d %d %d %d %d %llu %d %.4f\n", (unsigned long long)k.n,
             (unsigned long long)k.m, (unsigned long long)k.R, (unsigned long long)k.sum, t.hub_degree,
             t.tier1_shape, t.tier2_lanes, t.max_slots, t.coop_forward,
-            (unsigned long long)t.affected_gain, t.ms);
+            (unsigned long long)t.affected_gain, t.fwd_groups, t.ms);
     fclose(f);
 }
 
@@ -4395,6 +4395,8 @@ static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
     best->ms = best_ms;
     best->tried = N_SCHEDULES;
     best->affected_gain = 0;
+    best->fwd_groups = (int32_t)ws->fwd_per_word;
+    best->reserved = 0;
     return IM_OK;
 }
 
@@ -4442,6 +4444,50 @@ static int tune_affected(uint64_t nR, im_workspace *ws, hipStream_t s, Run run, 
     return IM_OK;
 }
 
+// The width of the cooperative forward search (workgroups per snapshot
+// word) under the chosen schedule and update strategy: wider grids expand
+// large frontiers faster, narrower ones pay less per grid barrier.
+static const uint32_t kFwdGroups[] = {16, 32};
+
+template <typename Run>
+static int tune_fwd_groups(im_workspace *ws, hipStream_t s, Run run, im_tuning *best)
+{
+    if (ws->coop_gain != 0) return IM_OK;   // the per-word forward search has no grid
+    int rc = IM_OK;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const uint32_t saved_mask = ws->prof_mask;
+    ws->prof_mask = 0;
+    float best_ms = -1.0f;
+    uint32_t best_g = ws->fwd_per_word;
+    for (uint32_t g : kFwdGroups) {
+        ws->fwd_per_word = g;
+        float ms_min = -1.0f;
+        for (int rep = 0; rep < 2 && !rc; rep++) {
+            if ((rc = run(true))) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = IM_EHIP; break; }
+            rc = run(false);
+            if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = IM_EHIP;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = IM_EHIP;
+            float ms = 0;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = IM_EHIP;
+            if (!rc && (ms_min < 0 || ms < ms_min)) ms_min = ms;
+        }
+        if (rc) break;
+        if (best_ms < 0 || ms_min < best_ms) { best_ms = ms_min; best_g = g; }
+    }
+    ws->prof_mask = saved_mask;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ws->fwd_per_word = best_g;
+    if (rc) return rc == IM_EHIP ? im_fail(IM_EHIP, "event timing of a forward-width trial failed") : rc;
+    best->fwd_groups = (int32_t)best_g;
+    best->ms = best_ms;
+    best->tried += (uint32_t)(sizeof(kFwdGroups) / sizeof(kFwdGroups[0]));
+    return IM_OK;
+}
+
 static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, bool *hit)
 {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -4454,6 +4500,7 @@ static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, boo
             apply_schedule(ws, Schedule{t.hub_degree, t.tier1_shape, t.tier2_lanes, t.max_slots,
                                         t.coop_forward});
             ws->aff_gain = t.affected_gain;
+            if (t.fwd_groups > 0) ws->fwd_per_word = (uint32_t)t.fwd_groups;
             if (out) { *out = t; out->tried = 0; }
             *hit = true;
             return IM_OK;
@@ -4506,6 +4553,7 @@ extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_work
         return r ? r : enqueue_rounds(g, R, ka, sd, gd, nullptr, ws, s);
     };
     if (!rc) rc = tune_affected((uint64_t)g->n * R, ws, s, run, &best);
+    if (!rc) rc = tune_fwd_groups(ws, s, run, &best);
     (void)hipStreamSynchronize(s);
     dfree(sd);
     dfree(gd);
@@ -4554,8 +4602,11 @@ extern "C" int im_autotune_batch(const im_instance *inst, uint32_t count, im_wor
 }
 
 // Lazy-path tuning: the evaluation engine and the batch size, timed on the
-// lazy selection's first rounds (the largest searches of the selection)
-constexpr uint32_t LAZY_TUNE_ROUNDS = 8;
+// lazy selection's first rounds. The early rounds hold the largest searches
+// and favour small batches, the later ones favour batches that cover a
+// round's must-evaluate set at once, so the trial runs the whole selection
+// up to 64 rounds.
+constexpr uint32_t LAZY_TUNE_ROUNDS = 64;
 static const int32_t kLazyEngines[] = {2, 0};
 static const uint32_t kLazyBatches[] = {1, 2, 4, 8, 16};
 
