@@ -1759,8 +1759,10 @@ static void exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t len, uint
     k_scan_add<<<grid_for(len, 256), 256, 0, s>>>(out, len, sums);
 }
 
-// A1: reverse CSR (row32 must already hold the 32-bit offsets)
-static void build_reverse(const im_graph *g, im_workspace *ws, hipStream_t s)
+// A1: reverse CSR (row32 must already hold the 32-bit offsets). With
+// offsets_only, just the in-row offsets (in-degrees) are built: paths
+// without reverse searches need no more.
+static void build_reverse(const im_graph *g, im_workspace *ws, hipStream_t s, bool offsets_only = false)
 {
     uint32_t n = g->n;
     uint64_t m = g->m;
@@ -1771,6 +1773,7 @@ static void build_reverse(const im_graph *g, im_workspace *ws, hipStream_t s)
         k_transpose<false><<<tblocks, TR_NT, 0, s>>>(ws->row32, g->col, n, m, ws->cnt, nullptr,
                                                      nullptr, nullptr);
     exclusive_scan(ws->cnt, ws->in_row, (uint64_t)n + 1, ws->scan_sums, s);
+    if (offsets_only) return;
     fill<uint32_t>(ws->cnt, (uint64_t)n + 1, 0u, s);
     if (m)
         k_transpose<true><<<tblocks, TR_NT, 0, s>>>(ws->row32, g->col, n, m, ws->cnt, ws->in_row,
@@ -2350,11 +2353,18 @@ static int check_and_reserve(const im_graph *g, uint32_t R, uint32_t k, im_works
     return IM_OK;
 }
 
+// What a path reads of the reverse direction: the dynamic update's reverse
+// searches need all of it (reverse CSR, reverse-order masks, reverse hub and
+// sparse lists); the lazy path and the initial counts alone need none of it,
+// or only the in-degrees (the learned policy's node features). Linear
+// threshold snapshots are drawn per in-row and always build the reverse CSR.
+enum { PREP_FORWARD = 0, PREP_INDEG = 1, PREP_REVERSE = 2 };
+
 // everything after validation up to (and including) the initial gains:
 // kernel launches only (no host synchronisation, no memset), so that the
 // sequence can be captured into a graph
 static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k,
-                           im_workspace *ws, hipStream_t s)
+                           im_workspace *ws, hipStream_t s, int need = PREP_REVERSE)
 {
     uint32_t n = g->n, W = (R + 63) / 64;
     fill<unsigned long long>(ws->stats, (uint64_t)ST_COUNT * ST_STRIPES, 0ull, s);
@@ -2365,14 +2375,17 @@ static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_
     fill<uint32_t>(ws->gain, n, 0u, s);
     fill<uint8_t>(ws->sel, n, (uint8_t)0, s);
     fill<uint64_t>(ws->covered, (uint64_t)n * W, 0ull, s);
-    build_reverse(g, ws, s);
-    build_masks(g, R, seed, ws, ws->mask_out, true, s);
+    const bool rev = need == PREP_REVERSE || ws->live_edge == 1;
+    if (rev || need == PREP_INDEG) build_reverse(g, ws, s, !rev);
+    build_masks(g, R, seed, ws, ws->mask_out, rev, s);
     {
         PhaseTimer pt(ws, IM_PH_HUBS, s);
         build_hubs(0, ws->row32, g->col, ws->mask_out, n, g->m, W, ws, s);
-        build_hubs(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
         build_sparse(0, ws->row32, g->col, ws->mask_out, n, g->m, W, ws, s);
-        build_sparse(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
+        if (rev) {
+            build_hubs(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
+            build_sparse(1, ws->in_row, ws->in_col, ws->mask_in, n, g->m, W, ws, s);
+        }
     }
     initial_gains(g, R, ws, ws->ctrs, s);
     HIPCHK(hipGetLastError());
@@ -2381,11 +2394,11 @@ static int enqueue_prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_
 }
 
 static int prepare(const im_graph *g, uint32_t R, uint64_t seed, uint32_t k, im_workspace *ws,
-                   hipStream_t s)
+                   hipStream_t s, int need = PREP_REVERSE)
 {
     int rc;
     if ((rc = check_and_reserve(g, R, k, ws, s))) return rc;
-    return enqueue_prepare(g, R, seed, k, ws, s);
+    return enqueue_prepare(g, R, seed, k, ws, s, need);
 }
 
 // the k greedy rounds (kernel launches only)
@@ -3714,7 +3727,7 @@ extern "C" int im_initial_gains(const im_graph *g, uint32_t R, uint64_t seed, ui
     if ((rc = check_args(g, R))) return rc;
     if (!ws || (g->n && !gain_out)) return im_fail(IM_EINVAL, "null workspace or output");
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = prepare(g, R, seed, 0, ws, s))) return rc;
+    if ((rc = prepare(g, R, seed, 0, ws, s, PREP_FORWARD))) return rc;
     if (g->n)
         k_copy_u32<<<grid_for(g->n, 256), 256, 0, s>>>(ws->gain, gain_out, g->n);
     HIPCHK(hipGetLastError());
@@ -4645,7 +4658,7 @@ extern "C" int im_autotune_lazy(const im_graph *g, uint32_t R, uint32_t k, uint6
             for (int rep = 0; rep < 2 && !rc; rep++) {
                 if ((rc = check_and_reserve(g, R, kt, ws, s))) break;
                 if ((rc = (int)(hipEventRecord(e0, s) != hipSuccess ? IM_EHIP : IM_OK))) break;
-                rc = enqueue_prepare(g, R, seed, kt, ws, s);
+                rc = enqueue_prepare(g, R, seed, kt, ws, s, model ? PREP_INDEG : PREP_FORWARD);
                 if (!rc) rc = select_lazy(g, R, kt, B, model, sd, gd, ws, s);
                 if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = IM_EHIP;
                 if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = IM_EHIP;
@@ -4687,7 +4700,7 @@ extern "C" int im_select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint64_
     if ((uint64_t)batch * ((R + 63) / 64) >= (1ull << 32)) return im_fail(IM_EINVAL, "batch too large");
     hipStream_t s = (hipStream_t)stream;
     PhaseTimer pt(ws, IM_PH_CALL, s);
-    if ((rc = prepare(g, R, seed, k, ws, s))) return rc;
+    if ((rc = prepare(g, R, seed, k, ws, s, model ? PREP_INDEG : PREP_FORWARD))) return rc;
     if (g->n == 0 || k == 0) return IM_OK;
     return select_lazy(g, R, k, batch, model, seeds_out, gains_out, ws, s);
 }
