@@ -136,11 +136,18 @@ int im_workspace_destroy(im_workspace *ws);
  *     the others recompute, from scratch, the gain of every node that reaches
  *     a newly covered node in its snapshot (found by one union search per
  *     word over the reverse arcs), which gives the same integers. Costs
- *     28 W + 12 bytes per node of extra workspace when non-zero. */
+ *     28 W + 12 bytes per node of extra workspace when non-zero.
+ *   IM_OPT_EVAL_SPLIT: on the lazy path's last-tier engine, each kept
+ *     (candidate, word) evaluation runs as this many searches over disjoint
+ *     groups of the word's snapshot bits, one workgroup each, whose counts
+ *     add up (a large search's levels spread over more workgroups): 1, 2, 4
+ *     or 8, or 0 (default) for the most of 8, 4, 2 whose searches fit the
+ *     slots (IM_OPT_MAX_SLOTS). */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
        IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10,
-       IM_OPT_LIVE_EDGE = 11, IM_OPT_LAZY_BATCH = 12, IM_OPT_AFFECTED_GAIN = 13 };
+       IM_OPT_LIVE_EDGE = 11, IM_OPT_LAZY_BATCH = 12, IM_OPT_AFFECTED_GAIN = 13,
+       IM_OPT_EVAL_SPLIT = 14 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the

@@ -43,6 +43,7 @@ IM_OPT_PAIR_COINS = 10
 IM_OPT_LIVE_EDGE = 11
 IM_OPT_LAZY_BATCH = 12
 IM_OPT_AFFECTED_GAIN = 13
+IM_OPT_EVAL_SPLIT = 14
 
 
 class ImGraph(ctypes.Structure):

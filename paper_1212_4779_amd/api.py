@@ -125,6 +125,10 @@ class Workspace:
         """Batch of select_lazy(batch=0) (1..1024)."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_LAZY_BATCH, int(batch)))
 
+    def set_eval_split(self, groups):
+        """Bit groups per kept lazy evaluation search (0: automatic, 1, 2, 4, 8). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_EVAL_SPLIT, int(groups)))
+
     def set_affected_gain(self, gain):
         """Rounds whose seed gain is below `gain` update the gains by the
         affected-set recompute instead of reverse decrements (0: never)."""

@@ -1382,6 +1382,7 @@ struct im_workspace {
                              // three tiers, 1: cooperative batched evaluation
     int learned_policy = 2;  // 1: score order among can-win nodes, 2: predicted-gain batches
     uint32_t lazy_batch = 4; // batch of im_select_lazy when it is called with batch = 0
+    uint32_t eval_split = 0; // bit groups per kept evaluation search (0: the most of 8, 4, 2 that fit)
     unsigned eval_grid = 0;
     uint64_t cap_eval = 0;
     uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
@@ -1987,6 +1988,7 @@ static BfsArgs bfs_args(im_workspace *ws, const uint32_t *row, const uint32_t *c
     BfsArgs a;
     memset(&a, 0, sizeof(a));
     a.row = row; a.col = col; a.mask = mask; a.m = m; a.n = n; a.R = R; a.W = W;
+    a.bsplit = 1;
     a.node_inst = ws->batch.node_inst; a.inst_R = ws->batch.R; a.inst_off = ws->batch.node_off;
     a.slot_n = ws->slots_n;
     a.gain = ws->gain;
@@ -3268,6 +3270,7 @@ static int commit_seed(const im_graph *g, uint32_t R, uint32_t t, uint32_t *seed
 struct KeptArgs {
     const unsigned long long *key;   // the round's best key
     uint32_t t, ncand, n, W, slot_n;
+    uint32_t split;                  // bit groups per (candidate, word) search
     const uint32_t *nvis, *src;      // per kept search (task = slot)
     const uint64_t *reach;           // slots' (reach, pend) records
     const uint32_t *vis;             // slots' visit lists
@@ -3279,14 +3282,14 @@ struct KeptArgs {
     unsigned long long *stats;
 };
 
-// KC_G workgroups per word (grid KC_G x W)
+// KC_G workgroups per (word, bit group) (grid KC_G x W * split)
 constexpr uint32_t KC_G = 64;
 
 __global__ __launch_bounds__(256) void k_kept_commit(KeptArgs a)
 {
     __shared__ uint32_t found;
     __shared__ unsigned long long red[4];
-    const uint32_t w = blockIdx.y, part = blockIdx.x, tid = threadIdx.x;
+    const uint32_t w = blockIdx.y % a.W, grp = blockIdx.y / a.W, part = blockIdx.x, tid = threadIdx.x;
     const unsigned long long key = *a.key;
     if (key == 0) return;
     const uint32_t v = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
@@ -3297,28 +3300,36 @@ __global__ __launch_bounds__(256) void k_kept_commit(KeptArgs a)
     __syncthreads();
     const uint32_t j = found;
     if (j == 0xFFFFFFFFu) return;   // evaluated in an earlier batch: the forward search commits
-    const uint32_t task = w * a.ncand + j;
+    // the seed's search of word w over bit group grp; groups hold disjoint
+    // bits, and a node counts as covered in word w (degree, visit) once: in
+    // the first group that reached it
+    const uint32_t per = a.ncand * a.W;
+    const uint32_t task = grp * per + w * a.ncand + j;
     const uint32_t nv = a.nvis[task];
     const uint32_t *vis = a.vis + (uint64_t)task * a.slot_n;
     const uint64_t *reach = a.reach + (uint64_t)task * a.slot_n * 2;
-    uint64_t relax = 0, trav = 0;
+    uint64_t relax = 0, trav = 0, first_visits = 0;
     for (uint32_t i = part * 256 + tid; i < nv; i += KC_G * 256) {
         const uint32_t x = vis[i];
         const uint64_t b = reach[(uint64_t)x * 2];
-        a.covered[(uint64_t)w * a.n + x] |= b;
+        atomicOr((unsigned long long *)&a.covered[(uint64_t)w * a.n + x], (unsigned long long)b);
         const uint32_t dg = a.row[x + 1] - a.row[x];
-        relax += dg;
+        bool first = true;
+        for (uint32_t g = 0; g < grp; g++)
+            first = first && a.reach[((uint64_t)(g * per + w * a.ncand + j) * a.slot_n + x) * 2] == 0;
+        if (first) { relax += dg; first_visits += 1; }
         trav += (uint64_t)__popcll(b) * dg;
     }
     relax = group_sum<256>(relax, red);
     trav = group_sum<256>(trav, red);
-    if (tid == 0 && relax) {
+    first_visits = group_sum<256>(first_visits, red);
+    if (tid == 0 && (trav || first_visits)) {
         atomicAdd(&a.stats[ST_RELAX_FWD], (unsigned long long)relax);
         atomicAdd(&a.stats[ST_TRAV_FWD], (unsigned long long)trav);
+        atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)first_visits);
     }
-    if (tid == 0 && part == 0) {
+    if (tid == 0 && part == 0 && grp == 0) {
         a.tcounts[w] = 0;
-        atomicAdd(&a.stats[ST_TASKS_REV], (unsigned long long)nv);
         if (w == 0) {
             a.seeds_out[a.t] = v;
             a.gains_out[a.t] = key >> 32;
@@ -3377,7 +3388,7 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
     }
     if ((rc = commit_seed(g, R, 0, seeds_out, gains_out, ws, s))) return rc;
     // the last batch's searches kept in the slots (last-tier engine): their count
-    uint32_t kept_tasks = 0, kept_ncand = 0;
+    uint32_t kept_tasks = 0, kept_ncand = 0, kept_split = 1;
     auto clear_kept = [&]() {
         if (!kept_tasks) return;
         PhaseTimer pt(ws, IM_PH_CLEAR, s);
@@ -3418,9 +3429,16 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
                 a.pass = PASS_EVAL;
                 a.st_trav = ST_TRAV_EVAL;
                 if (ws->lazy_engine == 2 && ws->batch.count == 1 && ncand * W <= ws->slots) {
+                    // the bit groups per search: as many (of 8, 4, 2) as the
+                    // slots hold, or the workspace's fixed choice when it fits
+                    uint32_t split = ws->eval_split ? ws->eval_split : 8u;
+                    while (split > 1 && ncand * W * split > ws->slots) split >>= 1;
+                    a.bsplit = split;
+                    a.ntasks = ncand * W * split;
                     run_last_tier<MODE_COUNT, true, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T2, s);
-                    kept_tasks = ncand * W;
+                    kept_tasks = ncand * W * split;
                     kept_ncand = ncand;
+                    kept_split = split;
                 } else if (ws->lazy_engine == 2)
                     run_last_tier<MODE_COUNT, true>(a, ws, ws->c_ctl + CC_EVCTR, IM_PH_EVAL_T2, s);
                 else
@@ -3438,12 +3456,13 @@ static int select_lazy(const im_graph *g, uint32_t R, uint32_t k, uint32_t B, co
         if (kept_tasks) {
             KeptArgs ka;
             ka.key = ws->keys + t; ka.t = t; ka.ncand = kept_ncand; ka.n = n; ka.W = W;
+            ka.split = kept_split;
             ka.slot_n = ws->slots_n; ka.nvis = ws->c_kept; ka.src = ws->c_kept + ws->cap_kept;
             ka.reach = ws->b_reach; ka.vis = ws->b_vis; ka.row = ws->row32; ka.covered = ws->covered;
             ka.seeds_out = seeds_out; ka.gains_out = gains_out; ka.tcounts = ws->tcounts;
             ka.flag = ws->c_ctl + CC_KEPT; ka.sel = ws->sel; ka.stats = ws->stats;
             PhaseTimer pt(ws, IM_PH_FORWARD, s);
-            k_kept_commit<<<dim3(KC_G, W), 256, 0, s>>>(ka);
+            k_kept_commit<<<dim3(KC_G, W * kept_split), 256, 0, s>>>(ka);
         }
         if ((rc = commit_seed(g, R, t, seeds_out, gains_out, ws, s, ws->c_ctl + CC_KEPT))) return rc;
         clear_kept();
@@ -4010,6 +4029,11 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
     case IM_OPT_AFFECTED_GAIN:
         if (value < 0) return im_fail(IM_EINVAL, "affected-set gain threshold must be >= 0");
         ws->aff_gain = (uint64_t)value;
+        return IM_OK;
+    case IM_OPT_EVAL_SPLIT:
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+            return im_fail(IM_EINVAL, "evaluation split must be 0 (automatic), 1, 2, 4 or 8");
+        ws->eval_split = (uint32_t)value;
         return IM_OK;
     case IM_OPT_LAZY_BATCH:
         if (value < 1 || value > (int64_t)CELF_BMAX) return im_fail(IM_EINVAL, "lazy batch must be in [1, %u]", CELF_BMAX);

@@ -167,6 +167,10 @@ struct BfsArgs {
     uint32_t ntasks;
     const uint32_t *cand;
     uint32_t ncand;
+    // MODE_COUNT with candidates: every (candidate, word) search is split
+    // into bsplit searches over disjoint groups of 64 / bsplit snapshot bits
+    // (1: none); task t in [0, ncand * W * bsplit) -> group t / (ncand * W)
+    uint32_t bsplit;
     const uint32_t *ncand_dev;      // MODE_COUNT: the candidate count in device memory
                                     // (overrides ncand and ntasks = ncand * W), or nullptr
     const uint32_t *gcnt, *mcnt;    // [W]
@@ -196,7 +200,13 @@ __device__ __forceinline__ void task_source(const BfsArgs &a, int mode, uint32_t
     bits = 0;
     src = 0;
     if (mode == MODE_COUNT) {
+        uint64_t group = ~0ull;
         if (a.cand) {
+            if (a.bsplit > 1) {
+                const uint32_t per = a.ncand * a.W, g = t / per, width = 64u / a.bsplit;
+                t -= g * per;
+                group = ((1ull << width) - 1ull) << (g * width);
+            }
             w = t / a.ncand;
             src = a.cand[t - w * a.ncand];
         } else {
@@ -205,7 +215,7 @@ __device__ __forceinline__ void task_source(const BfsArgs &a, int mode, uint32_t
         }
         if (lane == 0) {
             const uint32_t R = a.node_inst ? a.inst_R[a.node_inst[src]] : a.R;
-            bits = im_valid_bits(R, w);
+            bits = im_valid_bits(R, w) & group;
             if (bits && a.prune) bits &= ~a.prune[(uint64_t)w * a.n + src];
         }
         return;
@@ -445,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_lds_bfs(BfsArgs a)
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     __shared__ LdsState<NT, T, CS> L;
     const int tid = threadIdx.x;
-    if (MODE == MODE_COUNT && a.ncand_dev) { a.ncand = *a.ncand_dev; a.ntasks = a.ncand * a.W; }
+    if (MODE == MODE_COUNT && a.ncand_dev) { a.ncand = *a.ncand_dev; a.ntasks = a.ncand * a.W * max(a.bsplit, 1u); }
 
     for (int i = tid; i < N; i += NT) {
         L.keys[i] = IM_EMPTY; L.reach[i] = 0; L.pend[i] = 0; L.deg[i] = 0;
@@ -940,7 +950,7 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     __shared__ uint32_t wpre[65];
     const int tid = threadIdx.x;
     const uint64_t slot = blockIdx.x;
-    if (MODE == MODE_COUNT && a.ncand_dev) { a.ncand = *a.ncand_dev; a.ntasks = a.ncand * a.W; }
+    if (MODE == MODE_COUNT && a.ncand_dev) { a.ncand = *a.ncand_dev; a.ntasks = a.ncand * a.W * max(a.bsplit, 1u); }
     // the slot's (reach, pend) records, interleaved
     uint64_t *reach = a.b_reach + slot * a.slot_n * 2;
     uint64_t *pend = reach + 1;

@@ -375,3 +375,41 @@ def test_trained_network_saves_exact_evaluations(im):
             evals[label] = (st["celf_evals"], st["celf_batches"])
         print(name, "exact evaluations, batches:", evals)
         assert evals["learned"][0] <= most * evals["plain"][0], (name, evals)
+
+_DEV_GRAPHS = {}
+
+
+@pytest.mark.parametrize("split", [1, 2, 4, 8])
+@pytest.mark.parametrize("name,batch", [("tiny_uic", 3), ("nethept_wc", 4), ("million_uic", 4)])
+def test_lazy_split_evaluations_match_golden(im, name, batch, split):
+    # every kept evaluation as `split` searches over disjoint bit groups:
+    # seeds, gains and the exact work counters of the commits are unchanged
+    gold = _gold(name)
+    w = gg.WORKLOADS[name]
+    if name not in _DEV_GRAPHS:
+        _DEV_GRAPHS.clear()
+        _DEV_GRAPHS[name] = _dev(im, gg.workload_graph(name))
+    d = _DEV_GRAPHS[name]
+    out = []
+    for sp in (1, split):
+        ws = im.Workspace()
+        ws.set_lazy_engine(2)
+        ws.set_eval_split(sp)
+        seeds, gains = im.select_lazy(d, w["R"], w["k"], w["seed"], batch=batch, ws=ws)
+        st = ws.stats()
+        out.append((seeds.cpu().tolist(), gains.cpu().tolist(),
+                    {key: st[key] for key in ("trav_fwd", "relax_fwd", "tasks_rev", "trav_eval",
+                                              "celf_evals", "barrier_failures")}))
+        ws.close()
+    assert out[1][0] == gold["seeds"] and out[1][1] == gold["gains"]
+    assert out[1][2] == out[0][2]
+    assert out[1][2]["barrier_failures"] == 0
+
+
+def test_eval_split_option_is_checked(im):
+    ws = im.Workspace()
+    for bad in (3, 16, -1):
+        with pytest.raises(im.ImError):
+            ws.set_eval_split(bad)
+    ws.set_eval_split(0)
+    ws.close()
