@@ -480,7 +480,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--schedule", default=None,
-                    help="hub,tier1,lanes,slots,coop[,fwd_groups]: use this engine schedule instead "
+                    help="hub,tier1,lanes,slots,coop[,fwd_groups[,rev_split]]: use this engine schedule instead "
                          "of autotuning")
     ap.add_argument("--once", action="store_true",
                     help="one selection and one 1 GiB read + 1 GiB write stream (counter profiling)")
@@ -526,14 +526,16 @@ def main():
         vals = [int(x) for x in args.schedule.split(",")]
         hub, t1, lanes, slots, coop = vals[:5]
         fwd = vals[5] if len(vals) > 5 else 16
+        rev = vals[6] if len(vals) > 6 else 1
         ws.set_forward_groups(fwd)
+        ws.set_rev_split(rev)
         ws.set_hub_degree(hub)
         ws.set_tier1_shape(t1)
         ws.set_tier2_lanes(lanes)
         ws.set_max_slots(slots)
         ws.set_coop_gain(0 if coop else (1 << 62))
         tuning = {"hub_degree": hub, "tier1_shape": t1, "tier2_lanes": lanes, "max_slots": slots,
-                  "coop_forward": coop, "fwd_groups": fwd, "tried": 0}
+                  "coop_forward": coop, "fwd_groups": fwd, "rev_split": rev, "tried": 0}
     else:
         tuning = im.autotune(dg, R, seed, ws=ws)
     log(f"schedule: {tuning}")

@@ -142,12 +142,17 @@ int im_workspace_destroy(im_workspace *ws);
  *     groups of the word's snapshot bits, one workgroup each, whose counts
  *     add up (a large search's levels spread over more workgroups): 1, 2, 4
  *     or 8, or 0 (default) for the most of 8, 4, 2 whose searches fit the
- *     slots (IM_OPT_MAX_SLOTS). */
+ *     slots (IM_OPT_MAX_SLOTS).
+ *   IM_OPT_REV_SPLIT: every reverse task that reaches the last engine tier
+ *     runs as this many tasks (1, default, 2 or 4), each with the sources of
+ *     one group of the word's snapshot bits, whose decrements add up (a
+ *     large search's levels spread over more workgroups; im_autotune picks
+ *     1 or 2). */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
        IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10,
        IM_OPT_LIVE_EDGE = 11, IM_OPT_LAZY_BATCH = 12, IM_OPT_AFFECTED_GAIN = 13,
-       IM_OPT_EVAL_SPLIT = 14 };
+       IM_OPT_EVAL_SPLIT = 14, IM_OPT_REV_SPLIT = 15 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -301,7 +306,9 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
  * decrements in every round, the affected-set recompute in the small, in
  * most or in all rounds) and keeps the fastest; when the schedule uses the
  * cooperative forward search, it last times that search's width
- * (IM_OPT_FWD_GROUPS 16 or 32 workgroups per word) on the same trial.
+ * (IM_OPT_FWD_GROUPS 16 or 32 workgroups per word) on the same trial, and
+ * then the split of last-tier reverse tasks (IM_OPT_REV_SPLIT 1 or 2; the
+ * batch tuner times that too, on its own trial).
  * im_autotune caches its choice per graph signature (n, m, R and a checksum
  * of col and prob) for the life of the process; a cached choice is applied
  * without timing (out->tried = 0). When the environment variable
@@ -321,7 +328,7 @@ typedef struct im_tuning {
     uint64_t affected_gain;/* IM_OPT_AFFECTED_GAIN chosen (single graphs) */
     int32_t  fwd_groups;   /* IM_OPT_FWD_GROUPS chosen (single graphs with the
                               cooperative forward search; else the workspace's) */
-    int32_t  reserved;
+    int32_t  rev_split;    /* IM_OPT_REV_SPLIT chosen                          */
 } im_tuning;
 int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,
                 im_tuning *out);

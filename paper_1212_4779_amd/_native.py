@@ -44,6 +44,7 @@ IM_OPT_LIVE_EDGE = 11
 IM_OPT_LAZY_BATCH = 12
 IM_OPT_AFFECTED_GAIN = 13
 IM_OPT_EVAL_SPLIT = 14
+IM_OPT_REV_SPLIT = 15
 
 
 class ImGraph(ctypes.Structure):
@@ -93,10 +94,10 @@ class ImTuning(ctypes.Structure):
                 ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32),
                 ("affected_gain", ctypes.c_uint64), ("fwd_groups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("rev_split", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class ImLazyTuning(ctypes.Structure):

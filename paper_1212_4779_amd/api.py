@@ -129,6 +129,10 @@ class Workspace:
         """Bit groups per kept lazy evaluation search (0: automatic, 1, 2, 4, 8). No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_EVAL_SPLIT, int(groups)))
 
+    def set_rev_split(self, groups):
+        """Bit groups per last-tier reverse task (1, 2 or 4). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_REV_SPLIT, int(groups)))
+
     def set_affected_gain(self, gain):
         """Rounds whose seed gain is below `gain` update the gains by the
         affected-set recompute instead of reverse decrements (0: never)."""

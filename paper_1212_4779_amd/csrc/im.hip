@@ -1383,6 +1383,7 @@ struct im_workspace {
     int learned_policy = 2;  // 1: score order among can-win nodes, 2: predicted-gain batches
     uint32_t lazy_batch = 4; // batch of im_select_lazy when it is called with batch = 0
     uint32_t eval_split = 0; // bit groups per kept evaluation search (0: the most of 8, 4, 2 that fit)
+    uint32_t rev_split = 1;  // bit groups per last-tier reverse task
     unsigned eval_grid = 0;
     uint64_t cap_eval = 0;
     uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
@@ -2046,6 +2047,7 @@ static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipSt
     }
     a.in_q = ws->ovf_q2; a.in_n = ctr + 3;
     a.out_q = nullptr; a.out_n = nullptr; a.grab = ctr + 4; a.tier = 2;
+    if (MODE == MODE_DEC) a.bsplit = ws->rev_split;
     {
         PhaseTimer pt(ws, ph0 + 2, s);
         if (ws->tier2_lanes == (uint32_t)T2W_NT)
@@ -4035,6 +4037,11 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
             return im_fail(IM_EINVAL, "evaluation split must be 0 (automatic), 1, 2, 4 or 8");
         ws->eval_split = (uint32_t)value;
         return IM_OK;
+    case IM_OPT_REV_SPLIT:
+        if (value != 1 && value != 2 && value != 4)
+            return im_fail(IM_EINVAL, "reverse split must be 1, 2 or 4");
+        ws->rev_split = (uint32_t)value;
+        return IM_OK;
     case IM_OPT_LAZY_BATCH:
         if (value < 1 || value > (int64_t)CELF_BMAX) return im_fail(IM_EINVAL, "lazy batch must be in [1, %u]", CELF_BMAX);
         ws->lazy_batch = (uint32_t)value;
@@ -4331,7 +4338,7 @@ static std::vector<std::pair<TuneKey, im_tuning>> g_tune_cache;
 static std::mutex g_tune_mu;   // guards g_tune_cache and the cache file
 
 // The cache file named by IM_TUNE_CACHE (if set): one line per graph
-// signature, "im-tune-2 n m R sum hub tier1 lanes slots coop affected fwd ms".
+// signature, "im-tune-3 n m R sum hub tier1 lanes slots coop affected fwd split ms".
 // Lines that do not parse are ignored; the last line for a key wins.
 static const char *tune_file() { return getenv("IM_TUNE_CACHE"); }
 
@@ -4344,17 +4351,18 @@ static void tune_file_lookup(const TuneKey &key)
     char line[512];
     while (fgets(line, sizeof line, f)) {
         unsigned long long n, m, R, sum, aff;
-        int hub, t1, lanes, slots, coop, fwd;
+        int hub, t1, lanes, slots, coop, fwd, split;
         float ms;
-        if (sscanf(line, "im-tune-2 %llu %llu %llu %llu %d %d %d %d %d %llu %d %f", &n, &m, &R, &sum, &hub,
-                   &t1, &lanes, &slots, &coop, &aff, &fwd, &ms) != 12)
+        if (sscanf(line, "im-tune-3 %llu %llu %llu %llu %d %d %d %d %d %llu %d %d %f", &n, &m, &R, &sum,
+                   &hub, &t1, &lanes, &slots, &coop, &aff, &fwd, &split, &ms) != 13)
             continue;
         const TuneKey k{n, m, R, sum};
         if (!(k == key)) continue;
         im_tuning t;
         memset(&t, 0, sizeof t);
         t.hub_degree = hub; t.tier1_shape = t1; t.tier2_lanes = lanes; t.max_slots = slots;
-        t.coop_forward = coop; t.affected_gain = aff; t.fwd_groups = fwd; t.ms = ms; t.tried = 0;
+        t.coop_forward = coop; t.affected_gain = aff; t.fwd_groups = fwd; t.rev_split = split;
+        t.ms = ms; t.tried = 0;
         bool found = false;
         for (auto &kv : g_tune_cache)
             if (kv.first == k) { kv.second = t; found = true; }
@@ -4369,10 +4377,10 @@ static void tune_file_append(const TuneKey &k, const im_tuning &t)
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;   // the in-process cache still holds the choice
-    fprintf(f, "im-tune-2 %llu %llu %llu %llu %d %d %d %d %d %llu %d %.4f\n", (unsigned long long)k.n,
+    fprintf(f, "im-tune-3 %llu %llu %llu %llu %d %d %d %d %d %llu %d %d %.4f\n", (unsigned long long)k.n,
             (unsigned long long)k.m, (unsigned long long)k.R, (unsigned long long)k.sum, t.hub_degree,
             t.tier1_shape, t.tier2_lanes, t.max_slots, t.coop_forward,
-            (unsigned long long)t.affected_gain, t.fwd_groups, t.ms);
+            (unsigned long long)t.affected_gain, t.fwd_groups, t.rev_split, t.ms);
     fclose(f);
 }
 
@@ -4433,7 +4441,7 @@ static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
     best->tried = N_SCHEDULES;
     best->affected_gain = 0;
     best->fwd_groups = (int32_t)ws->fwd_per_word;
-    best->reserved = 0;
+    best->rev_split = (int32_t)ws->rev_split;
     return IM_OK;
 }
 
@@ -4481,15 +4489,13 @@ static int tune_affected(uint64_t nR, im_workspace *ws, hipStream_t s, Run run, 
     return IM_OK;
 }
 
-// The width of the cooperative forward search (workgroups per snapshot
-// word) under the chosen schedule and update strategy: wider grids expand
-// large frontiers faster, narrower ones pay less per grid barrier.
-static const uint32_t kFwdGroups[] = {16, 32};
-
-template <typename Run>
-static int tune_fwd_groups(im_workspace *ws, hipStream_t s, Run run, im_tuning *best)
+// One more knob under the chosen schedule: each value of `cand` is set with
+// set(v) and timed on run (two trials, the faster counts); the fastest is
+// set and returned in *chosen.
+template <typename Run, typename Set>
+static int tune_knob(const uint32_t *cand, int ncand, im_workspace *ws, hipStream_t s, Run run, Set set,
+                     uint32_t *chosen, im_tuning *best)
 {
-    if (ws->coop_gain != 0) return IM_OK;   // the per-word forward search has no grid
     int rc = IM_OK;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -4497,9 +4503,9 @@ static int tune_fwd_groups(im_workspace *ws, hipStream_t s, Run run, im_tuning *
     const uint32_t saved_mask = ws->prof_mask;
     ws->prof_mask = 0;
     float best_ms = -1.0f;
-    uint32_t best_g = ws->fwd_per_word;
-    for (uint32_t g : kFwdGroups) {
-        ws->fwd_per_word = g;
+    uint32_t best_v = cand[0];
+    for (int i = 0; i < ncand && !rc; i++) {
+        set(cand[i]);
         float ms_min = -1.0f;
         for (int rep = 0; rep < 2 && !rc; rep++) {
             if ((rc = run(true))) break;
@@ -4511,17 +4517,39 @@ static int tune_fwd_groups(im_workspace *ws, hipStream_t s, Run run, im_tuning *
             if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = IM_EHIP;
             if (!rc && (ms_min < 0 || ms < ms_min)) ms_min = ms;
         }
-        if (rc) break;
-        if (best_ms < 0 || ms_min < best_ms) { best_ms = ms_min; best_g = g; }
+        if (!rc && (best_ms < 0 || ms_min < best_ms)) { best_ms = ms_min; best_v = cand[i]; }
     }
     ws->prof_mask = saved_mask;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    ws->fwd_per_word = best_g;
-    if (rc) return rc == IM_EHIP ? im_fail(IM_EHIP, "event timing of a forward-width trial failed") : rc;
-    best->fwd_groups = (int32_t)best_g;
+    set(best_v);
+    if (rc) return rc == IM_EHIP ? im_fail(IM_EHIP, "event timing of a schedule trial failed") : rc;
+    *chosen = best_v;
     best->ms = best_ms;
-    best->tried += (uint32_t)(sizeof(kFwdGroups) / sizeof(kFwdGroups[0]));
+    best->tried += (uint32_t)ncand;
+    return IM_OK;
+}
+
+// The width of the cooperative forward search (workgroups per snapshot
+// word): wider grids expand large frontiers faster, narrower ones pay less
+// per grid barrier. The split of last-tier reverse tasks into bit groups:
+// more workgroups per large search, more task starts.
+static const uint32_t kFwdGroups[] = {16, 32};
+static const uint32_t kRevSplits[] = {1, 2};
+
+template <typename Run>
+static int tune_fwd_and_split(im_workspace *ws, hipStream_t s, Run run, im_tuning *best, bool fwd)
+{
+    int rc;
+    uint32_t v;
+    if (fwd && ws->coop_gain == 0) {   // (the per-word forward search has no grid)
+        if ((rc = tune_knob(kFwdGroups, 2, ws, s, run, [&](uint32_t g) { ws->fwd_per_word = g; }, &v, best)))
+            return rc;
+        best->fwd_groups = (int32_t)v;
+    }
+    if ((rc = tune_knob(kRevSplits, 2, ws, s, run, [&](uint32_t g) { ws->rev_split = g; }, &v, best)))
+        return rc;
+    best->rev_split = (int32_t)v;
     return IM_OK;
 }
 
@@ -4538,6 +4566,7 @@ static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, boo
                                         t.coop_forward});
             ws->aff_gain = t.affected_gain;
             if (t.fwd_groups > 0) ws->fwd_per_word = (uint32_t)t.fwd_groups;
+            if (t.rev_split > 0) ws->rev_split = (uint32_t)t.rev_split;
             if (out) { *out = t; out->tried = 0; }
             *hit = true;
             return IM_OK;
@@ -4590,7 +4619,7 @@ extern "C" int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_work
         return r ? r : enqueue_rounds(g, R, ka, sd, gd, nullptr, ws, s);
     };
     if (!rc) rc = tune_affected((uint64_t)g->n * R, ws, s, run, &best);
-    if (!rc) rc = tune_fwd_groups(ws, s, run, &best);
+    if (!rc) rc = tune_fwd_and_split(ws, s, run, &best, true);
     (void)hipStreamSynchronize(s);
     dfree(sd);
     dfree(gd);
@@ -4629,6 +4658,7 @@ extern "C" int im_autotune_batch(const im_instance *inst, uint32_t count, im_wor
         return r ? r : enqueue_rounds(&mg, Rmax, kt, sd, gd, nullptr, ws, s);
     };
     rc = tune(ws, s, prep, &best);
+    if (!rc) rc = tune_fwd_and_split(ws, s, prep, &best, false);
     (void)hipStreamSynchronize(s);
     dfree(sd);
     dfree(gd);

@@ -167,9 +167,11 @@ struct BfsArgs {
     uint32_t ntasks;
     const uint32_t *cand;
     uint32_t ncand;
-    // MODE_COUNT with candidates: every (candidate, word) search is split
-    // into bsplit searches over disjoint groups of 64 / bsplit snapshot bits
-    // (1: none); task t in [0, ncand * W * bsplit) -> group t / (ncand * W)
+    // Bit groups (1: none). MODE_COUNT with candidates: every (candidate,
+    // word) search is split into bsplit searches over disjoint groups of
+    // 64 / bsplit snapshot bits; task t in [0, ncand * W * bsplit) -> group
+    // t / (ncand * W). MODE_DEC on the last tier: every queued task runs as
+    // bsplit tasks, each with the sources (and bits) of one group.
     uint32_t bsplit;
     const uint32_t *ncand_dev;      // MODE_COUNT: the candidate count in device memory
                                     // (overrides ncand and ntasks = ncand * W), or nullptr
@@ -960,7 +962,11 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
     if (tid == 0 && MODE == MODE_DEC) fill_wpre(a, wpre);
     __syncthreads();
     // in_q = nullptr: every task id below ntasks (tasks routed straight here)
-    const uint32_t nq = a.in_q ? *a.in_n : a.ntasks;
+    const uint32_t nq0 = a.in_q ? *a.in_n : a.ntasks;
+    // reverse tasks split into bit groups: task q -> group q / nq0 of queued
+    // task q % nq0 (the groups' decrements add up to the task's)
+    const uint32_t spl = MODE == MODE_DEC ? max(a.bsplit, 1u) : 1u;
+    const uint32_t nq = nq0 * spl;
     // In a batch a packed reverse task may hold sources of several instances;
     // its sources are then searched one after the other, each inside its own
     // instance (their bits are disjoint, so the decrements add up to those of
@@ -979,7 +985,9 @@ __global__ __launch_bounds__(NT) void k_block_bfs(BfsArgs a)
         {
             uint32_t ww, ss;
             uint64_t bb;
-            task_source(a, MODE, a.in_q ? a.in_q[q] : q, wpre, (uint32_t)(tid & 63), ww, ss, bb);
+            const uint32_t grp = q / nq0, q0 = q - grp * nq0;
+            task_source(a, MODE, a.in_q ? a.in_q[q0] : q0, wpre, (uint32_t)(tid & 63), ww, ss, bb);
+            if (spl > 1) bb &= ((1ull << (64u / spl)) - 1ull) << (grp * (64u / spl));
             w = ww;
             if (tid < 64) { L.gsrc[tid] = ss; L.gbits[tid] = bb; }
         }

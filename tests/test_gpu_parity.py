@@ -164,6 +164,33 @@ def test_schedule_invariance_forward(im, case):
         assert o[3]["barrier_failures"] == 0
 
 
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6]], ids=["nethept_wc", "dense_p30", "hub_star"])
+def test_schedule_invariance_reverse_split(im, case):
+    # last-tier reverse tasks split into 1, 2 or 4 bit groups: identical
+    # gain vectors in every round
+    _, g, R, k, seed = case
+    d = _dev(im, g)
+    s_ref, g_ref, tr_ref, st = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    for split in (1, 2, 4):
+        ws = im.Workspace()
+        ws.set_rev_split(split)
+        ws.set_tier2_lanes(64)
+        seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
+        assert np.array_equal(seeds.cpu().numpy(), s_ref.astype(np.int64)), split
+        assert np.array_equal(gains.cpu().numpy(), g_ref.astype(np.int64)), split
+        tr = tr.cpu().numpy()
+        for t in range(k + 1):
+            assert np.array_equal(tr[t], tr_ref[t].astype(np.int64)), (split, t)
+        gs = ws.stats()
+        assert gs["trav_rev"] == st["trav_rev"] and gs["decrements"] == st["decrements"], split
+        reached_t2 = gs["reached_rev_t2"]
+        ws.close()
+    if case[0] == "dense_p30":
+        assert reached_t2 > 0   # the last tier did run reverse tasks
+    with pytest.raises(im.ImError):
+        im.Workspace().set_rev_split(3)
+
+
 def test_repeat_and_workspace_reuse(im):
     g1 = gg.workload_graph("nethept_wc")
     g2 = gg.workload_graph("tiny_uic")
