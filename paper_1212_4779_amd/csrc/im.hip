@@ -989,9 +989,9 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 const uint64_t e = i == i0 ? e0 : cur[i];
                 w = (uint32_t)(e >> 32);
                 uint32_t x = (uint32_t)e;
-                uint32_t hs = a.hub.slot[x];
                 rs = a.row[x];
                 deg = a.row[x + 1] - rs;
+                uint32_t hs = deg >= a.hub.min_deg ? a.hub.slot[x] : IM_EMPTY;
                 // bits gained since x was last expanded; later ones re-queue x
                 d = atomicExch((unsigned long long *)&a.pend[(uint64_t)w * a.n + x], 0ull);
                 if (hs != IM_EMPTY) {
@@ -1980,6 +1980,7 @@ static HubLists hub_lists(im_workspace *ws, int d)
     h.slot = ws->hslot[d];
     h.off = ws->hoff[d];
     h.adj = ws->hadj[d];
+    h.min_deg = ws->hub_deg ? ws->hub_deg : 0xFFFFFFFFu;   // the marking rule of k_hub_mark
     return h;
 }
 
@@ -3006,9 +3007,9 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
                 const uint64_t e = cur[i];
                 vw = (uint32_t)(e >> 32);
                 const uint32_t x = (uint32_t)e;
-                const uint32_t hs = a.hub.slot[x];
                 rs = a.row[x];
                 deg = a.row[x + 1] - rs;
+                const uint32_t hs = deg >= a.hub.min_deg ? a.hub.slot[x] : IM_EMPTY;
                 d = atomicExch((unsigned long long *)&a.pend[(uint64_t)vw * a.n + x], 0ull);
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, vw, d);

@@ -67,6 +67,7 @@ struct HubLists {
     const uint32_t *slot;   // [n], nullptr: no hub lists
     const uint32_t *off;    // [nhub][W][65]
     const uint32_t *adj;
+    uint32_t min_deg;       // nodes with fewer arcs have no lists (slot[x] is IM_EMPTY)
 };
 
 // Per-snapshot live lists of the other nodes (degree >= 2, below the hub
@@ -861,9 +862,11 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
             uint64_t d = 0;
             if (i < nf) {
                 uint32_t x = cur[i];
-                uint32_t hs = hub.slot ? hub.slot[x] : IM_EMPTY;
                 rs = row[x];
                 deg = row[x + 1] - rs;
+                // only a node with enough arcs can have lists: the others skip
+                // the load (one line less per expansion; hubs wait one more load)
+                uint32_t hs = (hub.slot && deg >= hub.min_deg) ? hub.slot[x] : IM_EMPTY;
                 // bits gained since the last expansion (later ones re-queue x)
                 d = atomicExch((unsigned long long *)&pend[(uint64_t)(x - base) * S], 0ull);
                 if (hs != IM_EMPTY) {
