@@ -1000,7 +1000,7 @@ __global__ __launch_bounds__(FWD_NT) void k_forward_coop(FwdArgs a)
                 } else {
                     uint32_t work, srs, saux;
                     uint64_t sdel;
-                    if (sparse_use(sparse_fetch(a.sp, a.n, w, x, d), deg, work, srs, sdel, saux)) {
+                    if (deg >= 2 && sparse_use(sparse_fetch(a.sp, a.n, w, x, d), deg, work, srs, sdel, saux)) {
                         deg = work; rs = srs; d = sdel; aux = saux;
                     }
                 }
@@ -3017,7 +3017,7 @@ __global__ __launch_bounds__(FWD_NT) void k_eval_coop(EvalArgs a)
                 } else {
                     uint32_t work, srs, saux;
                     uint64_t sdel;
-                    if (sparse_use(sparse_fetch(a.sp, a.n, vw % a.W, x, d), deg, work, srs, sdel, saux)) {
+                    if (deg >= 2 && sparse_use(sparse_fetch(a.sp, a.n, vw % a.W, x, d), deg, work, srs, sdel, saux)) {
                         deg = work; rs = srs; d = sdel; aux = saux;
                     }
                 }

@@ -872,7 +872,7 @@ __device__ void block_bfs_run(BlockLds<NT> &L, uint32_t src, uint64_t start,
                 if (hs != IM_EMPTY) {
                     hub_push(L.H, hs, 0u, d);
                     deg = 0; d = 0;
-                } else if (SPARSE) {
+                } else if (SPARSE && deg >= 2) {   // (no lists below 2 arcs: skip their loads)
                     uint32_t work, srs, saux;
                     uint64_t sdel;
                     if (sparse_use(sparse_fetch(sp, n, w, x, d), deg, work, srs, sdel, saux)) {
