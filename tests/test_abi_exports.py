@@ -33,3 +33,36 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(_native.ImGraph) == 40
     assert ctypes.sizeof(_native.ImStats) == 64 * 8
     assert ctypes.sizeof(_native.ImInstance) == 56
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    # every public struct's size and every field's offset, as the C compiler
+    # lays them out from include/im.h, against the binding's ctypes mirrors
+    import shutil
+    import subprocess
+    import pytest
+    from paper_1212_4779_amd import _native
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    mirrors = {"im_graph": _native.ImGraph, "im_instance": _native.ImInstance,
+               "im_stats": _native.ImStats, "im_tuning": _native.ImTuning,
+               "im_lazy_tuning": _native.ImLazyTuning, "im_profile": _native.ImProfile}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "im.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    build = subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                            str(exe)], capture_output=True, text=True)
+    assert build.returncode == 0, build.stderr[-2000:]
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
