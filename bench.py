@@ -67,10 +67,27 @@ def source_digest(files):
     return h.hexdigest()[:16]
 
 
-def load_traffic(phase, workload):
+T1_SHAPES = {0: "256, 4, 256, 192,", 1: "256, 2, 512, 384,", 2: "256, 1, 1024, 768,"}
+
+
+def kernel_signature(phase, schedule):
+    """The part of the launched kernel's name that the schedule decides (the
+    tier-1 shape and tier-2 lanes are template arguments)."""
+    mode = "0" if phase.startswith("init") else "1"
+    if phase == "forward":
+        return "k_forward_coop"
+    if phase.endswith("_t0"):
+        return f"k_lds_bfs<{mode}, 64, 8, 32, 24,"
+    if phase.endswith("_t1"):
+        return f"k_lds_bfs<{mode}, " + T1_SHAPES[int(schedule.get("tier1_shape", 0))]
+    return f"k_block_bfs<{mode}, {int(schedule.get('tier2_lanes', 256))}, 8,"
+
+
+def load_traffic(phase, workload, schedule):
     """HBM bytes per launch of `phase` from the committed rocprofv3 counter
-    summary (profiles/traffic.json), if it was taken on this workload and on
-    the current source of that kernel; else None."""
+    summary (profiles/traffic.json), if it was taken on this workload, on the
+    current source of that kernel and on the kernel this schedule launches;
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -81,6 +98,8 @@ def load_traffic(phase, workload):
     if not k:
         return None
     if k.get("source_digest") != source_digest(k.get("sources", [])):
+        return None
+    if kernel_signature(phase, schedule) not in k.get("kernel", ""):
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -298,7 +317,7 @@ def run_batch(args, log):
         "selection_ms": ms, "traversals_per_step": trav,
         "phase_ms": {p: round(prof[p][0], 4) for p in prof},
         "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, "batch512"),
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, "batch512", tuning),
                      "kernel": KERNEL_NAMES[dom], "phase": dom,
                      "algorithmic_bytes_per_launch": int(bpl), "avg_launch_ms": round(avg_ms, 4)},
         "schedule": tuning,
@@ -594,8 +613,8 @@ def main():
         per_kernel[ph] = {"kernel": KERNEL_NAMES[ph], "launches": nl, "ms": round(tms, 4),
                           "algorithmic_bytes_per_launch": int(kb[ph] / nl),
                           "achieved": round(a_gbs, 2), "frac": round(a_gbs / HBM_PEAK_GBS, 5),
-                          "traffic": load_traffic(ph, args.workload)}
-    traffic = load_traffic(dom, args.workload)
+                          "traffic": load_traffic(ph, args.workload, tuning)}
+    traffic = load_traffic(dom, args.workload, tuning)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dom], "phase": dom,
