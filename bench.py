@@ -83,11 +83,20 @@ def kernel_signature(phase, schedule):
     return f"k_block_bfs<{mode}, {int(schedule.get('tier2_lanes', 256))}, 8,"
 
 
+# options that change how much work a kernel instance does per launch (not
+# which instance runs): the last tier runs what tier 1 hands on, which its
+# table size (the tier-1 shape) decides; tier 1 takes every reverse task when
+# the reverse tasks start there; the split multiplies the last tier's tasks
+WORK_OPTIONS = {"init_t2": (("tier1_shape", 0),),
+                "rev_t1": (("rev_first_tier", 0),),
+                "rev_t2": (("tier1_shape", 0), ("rev_first_tier", 0), ("rev_split", 1))}
+
+
 def load_traffic(phase, workload, schedule):
     """HBM bytes per launch of `phase` from the committed rocprofv3 counter
     summary (profiles/traffic.json), if it was taken on this workload, on the
-    current source of that kernel and on the kernel this schedule launches;
-    else None."""
+    current source of that kernel, on the kernel this schedule launches and
+    with the same share of the work; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -101,6 +110,9 @@ def load_traffic(phase, workload, schedule):
         return None
     if kernel_signature(phase, schedule) not in k.get("kernel", ""):
         return None
+    for key, default in WORK_OPTIONS.get(phase, ()):
+        if int(schedule.get(key, default)) != int(t.get("schedule", {}).get(key, default)):
+            return None
     return k.get("hbm_bytes_per_launch")
 
 
@@ -499,8 +511,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--schedule", default=None,
-                    help="hub,tier1,lanes,slots,coop[,fwd_groups[,rev_split]]: use this engine schedule instead "
-                         "of autotuning")
+                    help="hub,tier1,lanes,slots,coop[,fwd_groups[,rev_split[,rev_first_tier]]]: use this "
+                         "engine schedule instead of autotuning")
     ap.add_argument("--once", action="store_true",
                     help="one selection and one 1 GiB read + 1 GiB write stream (counter profiling)")
     args = ap.parse_args()
@@ -546,15 +558,18 @@ def main():
         hub, t1, lanes, slots, coop = vals[:5]
         fwd = vals[5] if len(vals) > 5 else 16
         rev = vals[6] if len(vals) > 6 else 1
+        first = vals[7] if len(vals) > 7 else 0
         ws.set_forward_groups(fwd)
         ws.set_rev_split(rev)
+        ws.set_rev_first_tier(first)
         ws.set_hub_degree(hub)
         ws.set_tier1_shape(t1)
         ws.set_tier2_lanes(lanes)
         ws.set_max_slots(slots)
         ws.set_coop_gain(0 if coop else (1 << 62))
         tuning = {"hub_degree": hub, "tier1_shape": t1, "tier2_lanes": lanes, "max_slots": slots,
-                  "coop_forward": coop, "fwd_groups": fwd, "rev_split": rev, "tried": 0}
+                  "coop_forward": coop, "fwd_groups": fwd, "rev_split": rev, "rev_first_tier": first,
+                  "tried": 0}
     else:
         tuning = im.autotune(dg, R, seed, ws=ws)
     log(f"schedule: {tuning}")

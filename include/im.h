@@ -147,12 +147,17 @@ int im_workspace_destroy(im_workspace *ws);
  *     runs as this many tasks (1, default, 2 or 4), each with the sources of
  *     one group of the word's snapshot bits, whose decrements add up (a
  *     large search's levels spread over more workgroups; im_autotune picks
- *     1 or 2). */
+ *     1 or 2).
+ *   IM_OPT_REV_FIRST_TIER: the engine tier reverse tasks start on: 0
+ *     (default) or 1, which leaves out the tier-0 launch of every round's
+ *     reverse step (its workgroups hand most large tasks on anyway, and a
+ *     launch costs its longest task start to finish even in a round with
+ *     few tasks); im_autotune picks one. */
 enum { IM_OPT_HUB_DEGREE = 1, IM_OPT_COOP_GAIN = 2, IM_OPT_LAZY_ENGINE = 3, IM_OPT_MAX_SLOTS = 4,
        IM_OPT_TIER1_SHAPE = 5, IM_OPT_TIER2_LANES = 6, IM_OPT_SPARSE_LISTS = 7,
        IM_OPT_FWD_GROUPS = 8, IM_OPT_LEARNED_POLICY = 9, IM_OPT_PAIR_COINS = 10,
        IM_OPT_LIVE_EDGE = 11, IM_OPT_LAZY_BATCH = 12, IM_OPT_AFFECTED_GAIN = 13,
-       IM_OPT_EVAL_SPLIT = 14, IM_OPT_REV_SPLIT = 15 };
+       IM_OPT_EVAL_SPLIT = 14, IM_OPT_REV_SPLIT = 15, IM_OPT_REV_FIRST_TIER = 16 };
 int im_workspace_set(im_workspace *ws, int option, int64_t value);
 
 /* Counters of the last call on a workspace (synchronous: waits for the
@@ -307,8 +312,9 @@ int im_select_batch(const im_instance *inst, uint32_t count, uint32_t *seeds_out
  * most or in all rounds) and keeps the fastest; when the schedule uses the
  * cooperative forward search, it last times that search's width
  * (IM_OPT_FWD_GROUPS 16 or 32 workgroups per word) on the same trial, and
- * then the split of last-tier reverse tasks (IM_OPT_REV_SPLIT 1 or 2; the
- * batch tuner times that too, on its own trial).
+ * then the split of last-tier reverse tasks (IM_OPT_REV_SPLIT 1 or 2) and
+ * the tier reverse tasks start on (IM_OPT_REV_FIRST_TIER 0 or 1; the batch
+ * tuner times these two as well, on its own trial).
  * im_autotune caches its choice per graph signature (n, m, R and a checksum
  * of col and prob) for the life of the process; a cached choice is applied
  * without timing (out->tried = 0). When the environment variable
@@ -329,6 +335,7 @@ typedef struct im_tuning {
     int32_t  fwd_groups;   /* IM_OPT_FWD_GROUPS chosen (single graphs with the
                               cooperative forward search; else the workspace's) */
     int32_t  rev_split;    /* IM_OPT_REV_SPLIT chosen                          */
+    int32_t  rev_first_tier; /* IM_OPT_REV_FIRST_TIER chosen                   */
 } im_tuning;
 int im_autotune(const im_graph *g, uint32_t R, uint64_t seed, im_workspace *ws, void *stream,
                 im_tuning *out);

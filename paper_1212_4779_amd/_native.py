@@ -45,6 +45,7 @@ IM_OPT_LAZY_BATCH = 12
 IM_OPT_AFFECTED_GAIN = 13
 IM_OPT_EVAL_SPLIT = 14
 IM_OPT_REV_SPLIT = 15
+IM_OPT_REV_FIRST_TIER = 16
 
 
 class ImGraph(ctypes.Structure):
@@ -94,7 +95,7 @@ class ImTuning(ctypes.Structure):
                 ("tier2_lanes", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("coop_forward", ctypes.c_int32), ("ms", ctypes.c_float), ("tried", ctypes.c_uint32),
                 ("affected_gain", ctypes.c_uint64), ("fwd_groups", ctypes.c_int32),
-                ("rev_split", ctypes.c_int32)]
+                ("rev_split", ctypes.c_int32), ("rev_first_tier", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

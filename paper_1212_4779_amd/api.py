@@ -133,6 +133,10 @@ class Workspace:
         """Bit groups per last-tier reverse task (1, 2 or 4). No result changes."""
         N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_REV_SPLIT, int(groups)))
 
+    def set_rev_first_tier(self, tier):
+        """Engine tier the reverse tasks start on (0 or 1). No result changes."""
+        N.check(N.lib().im_workspace_set(self.handle, N.IM_OPT_REV_FIRST_TIER, int(tier)))
+
     def set_affected_gain(self, gain):
         """Rounds whose seed gain is below `gain` update the gains by the
         affected-set recompute instead of reverse decrements (0: never)."""

@@ -1384,6 +1384,7 @@ struct im_workspace {
     uint32_t lazy_batch = 4; // batch of im_select_lazy when it is called with batch = 0
     uint32_t eval_split = 0; // bit groups per kept evaluation search (0: the most of 8, 4, 2 that fit)
     uint32_t rev_split = 1;  // bit groups per last-tier reverse task
+    uint32_t rev_first = 0;  // engine tier reverse tasks start on (0 or 1)
     unsigned eval_grid = 0;
     uint64_t cap_eval = 0;
     uint64_t *e_reach = nullptr, *e_pend = nullptr, *e_fq0 = nullptr, *e_fq1 = nullptr,
@@ -2016,13 +2017,15 @@ static void run_tiers(BfsArgs a, im_workspace *ws, uint32_t *ctr, int ph0, hipSt
 {
     a.in_q = nullptr; a.in_n = nullptr;
     a.out_q = ws->ovf_q; a.out_n = ctr + 1; a.grab = ctr + 0; a.tier = 0;
-    {
+    // reverse tasks may start on tier 1, which then takes every task id
+    const bool skip0 = MODE == MODE_DEC && ws->rev_first == 1;
+    if (!skip0) {
         PhaseTimer pt(ws, ph0, s);
         auto k0 = k_lds_bfs<MODE, 64, T0_T, T0_CS, T0_LIM, T0_DMAX, T0_U, PRUNE>;
         static const unsigned g0 = per_cu(k0, 64);
         k0<<<(unsigned)ws->num_cu * g0, 64, 0, s>>>(a);
+        a.in_q = ws->ovf_q; a.in_n = ctr + 1;
     }
-    a.in_q = ws->ovf_q; a.in_n = ctr + 1;
     a.out_q = ws->ovf_q2; a.out_n = ctr + 3; a.grab = ctr + 2; a.tier = 1;
     {
         PhaseTimer pt(ws, ph0 + 1, s);
@@ -4043,6 +4046,10 @@ extern "C" int im_workspace_set(im_workspace *ws, int option, int64_t value)
             return im_fail(IM_EINVAL, "reverse split must be 1, 2 or 4");
         ws->rev_split = (uint32_t)value;
         return IM_OK;
+    case IM_OPT_REV_FIRST_TIER:
+        if (value != 0 && value != 1) return im_fail(IM_EINVAL, "reverse first tier must be 0 or 1");
+        ws->rev_first = (uint32_t)value;
+        return IM_OK;
     case IM_OPT_LAZY_BATCH:
         if (value < 1 || value > (int64_t)CELF_BMAX) return im_fail(IM_EINVAL, "lazy batch must be in [1, %u]", CELF_BMAX);
         ws->lazy_batch = (uint32_t)value;
@@ -4246,6 +4253,8 @@ extern "C" int im_plan_create_batch(const im_instance *inst, uint32_t count, uin
         p->ws->coop_gain = tuned->coop_gain;
         p->ws->sparse = tuned->sparse;
         p->ws->fwd_per_word = tuned->fwd_per_word;
+        p->ws->rev_split = tuned->rev_split;
+        p->ws->rev_first = tuned->rev_first;
     }
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
@@ -4339,7 +4348,7 @@ static std::vector<std::pair<TuneKey, im_tuning>> g_tune_cache;
 static std::mutex g_tune_mu;   // guards g_tune_cache and the cache file
 
 // The cache file named by IM_TUNE_CACHE (if set): one line per graph
-// signature, "im-tune-3 n m R sum hub tier1 lanes slots coop affected fwd split ms".
+// signature, "im-tune-4 n m R sum hub tier1 lanes slots coop affected fwd split first ms".
 // Lines that do not parse are ignored; the last line for a key wins.
 static const char *tune_file() { return getenv("IM_TUNE_CACHE"); }
 
@@ -4352,10 +4361,10 @@ static void tune_file_lookup(const TuneKey &key)
     char line[512];
     while (fgets(line, sizeof line, f)) {
         unsigned long long n, m, R, sum, aff;
-        int hub, t1, lanes, slots, coop, fwd, split;
+        int hub, t1, lanes, slots, coop, fwd, split, first;
         float ms;
-        if (sscanf(line, "im-tune-3 %llu %llu %llu %llu %d %d %d %d %d %llu %d %d %f", &n, &m, &R, &sum,
-                   &hub, &t1, &lanes, &slots, &coop, &aff, &fwd, &split, &ms) != 13)
+        if (sscanf(line, "im-tune-4 %llu %llu %llu %llu %d %d %d %d %d %llu %d %d %d %f", &n, &m, &R,
+                   &sum, &hub, &t1, &lanes, &slots, &coop, &aff, &fwd, &split, &first, &ms) != 14)
             continue;
         const TuneKey k{n, m, R, sum};
         if (!(k == key)) continue;
@@ -4363,7 +4372,7 @@ static void tune_file_lookup(const TuneKey &key)
         memset(&t, 0, sizeof t);
         t.hub_degree = hub; t.tier1_shape = t1; t.tier2_lanes = lanes; t.max_slots = slots;
         t.coop_forward = coop; t.affected_gain = aff; t.fwd_groups = fwd; t.rev_split = split;
-        t.ms = ms; t.tried = 0;
+        t.rev_first_tier = first; t.ms = ms; t.tried = 0;
         bool found = false;
         for (auto &kv : g_tune_cache)
             if (kv.first == k) { kv.second = t; found = true; }
@@ -4378,10 +4387,10 @@ static void tune_file_append(const TuneKey &k, const im_tuning &t)
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;   // the in-process cache still holds the choice
-    fprintf(f, "im-tune-3 %llu %llu %llu %llu %d %d %d %d %d %llu %d %d %.4f\n", (unsigned long long)k.n,
+    fprintf(f, "im-tune-4 %llu %llu %llu %llu %d %d %d %d %d %llu %d %d %d %.4f\n", (unsigned long long)k.n,
             (unsigned long long)k.m, (unsigned long long)k.R, (unsigned long long)k.sum, t.hub_degree,
             t.tier1_shape, t.tier2_lanes, t.max_slots, t.coop_forward,
-            (unsigned long long)t.affected_gain, t.fwd_groups, t.rev_split, t.ms);
+            (unsigned long long)t.affected_gain, t.fwd_groups, t.rev_split, t.rev_first_tier, t.ms);
     fclose(f);
 }
 
@@ -4443,6 +4452,7 @@ static int tune(im_workspace *ws, hipStream_t s, Prep prep, im_tuning *best)
     best->affected_gain = 0;
     best->fwd_groups = (int32_t)ws->fwd_per_word;
     best->rev_split = (int32_t)ws->rev_split;
+    best->rev_first_tier = (int32_t)ws->rev_first;
     return IM_OK;
 }
 
@@ -4534,9 +4544,12 @@ static int tune_knob(const uint32_t *cand, int ncand, im_workspace *ws, hipStrea
 // The width of the cooperative forward search (workgroups per snapshot
 // word): wider grids expand large frontiers faster, narrower ones pay less
 // per grid barrier. The split of last-tier reverse tasks into bit groups:
-// more workgroups per large search, more task starts.
+// more workgroups per large search, more task starts. The first tier of
+// the reverse step: tier 0 finishes small tasks in small tables, tier 1
+// saves a launch and the hand-over of the larger tasks.
 static const uint32_t kFwdGroups[] = {16, 32};
 static const uint32_t kRevSplits[] = {1, 2};
+static const uint32_t kRevFirst[] = {0, 1};
 
 template <typename Run>
 static int tune_fwd_and_split(im_workspace *ws, hipStream_t s, Run run, im_tuning *best, bool fwd)
@@ -4551,6 +4564,9 @@ static int tune_fwd_and_split(im_workspace *ws, hipStream_t s, Run run, im_tunin
     if ((rc = tune_knob(kRevSplits, 2, ws, s, run, [&](uint32_t g) { ws->rev_split = g; }, &v, best)))
         return rc;
     best->rev_split = (int32_t)v;
+    if ((rc = tune_knob(kRevFirst, 2, ws, s, run, [&](uint32_t t) { ws->rev_first = t; }, &v, best)))
+        return rc;
+    best->rev_first_tier = (int32_t)v;
     return IM_OK;
 }
 
@@ -4568,6 +4584,7 @@ static int tune_cached(const TuneKey &key, im_workspace *ws, im_tuning *out, boo
             ws->aff_gain = t.affected_gain;
             if (t.fwd_groups > 0) ws->fwd_per_word = (uint32_t)t.fwd_groups;
             if (t.rev_split > 0) ws->rev_split = (uint32_t)t.rev_split;
+            if (t.rev_first_tier == 0 || t.rev_first_tier == 1) ws->rev_first = (uint32_t)t.rev_first_tier;
             if (out) { *out = t; out->tried = 0; }
             *hit = true;
             return IM_OK;

@@ -5,7 +5,11 @@ profiles/traffic.json holds, per workload and phase, the HBM bytes per launch
 that rocprofv3's FETCH_SIZE + WRITE_SIZE counters gave for one kernel
 instance. The tier-1 shape and the tier-2 lane count are template arguments,
 so a different schedule launches a different kernel: the figure may be
-attached only when the schedule of the run selects the profiled instance.
+attached only when the schedule of the run selects the profiled instance
+and gives it the same share of the work: the last tier runs what tier 1
+hands on (its table size is the tier-1 shape), reverse tier 1 takes every
+reverse task when they start there, and last-tier reverse tasks may be split
+into bit groups.
 """
 import json
 import os
@@ -19,7 +23,8 @@ import bench  # noqa: E402
 
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 PHASES = ["init_t0", "init_t1", "init_t2", "forward", "rev_t0", "rev_t1", "rev_t2"]
-SCHEDULES = [{"tier1_shape": s, "tier2_lanes": l} for s in (0, 1, 2) for l in (64, 256, 1024)]
+SCHEDULES = [{"tier1_shape": s, "tier2_lanes": l, "rev_split": p, "rev_first_tier": f}
+             for s in (0, 1, 2) for l in (64, 256, 1024) for p in (1, 2) for f in (0, 1)]
 
 
 def _profiled():
@@ -64,10 +69,18 @@ def test_load_traffic_follows_the_schedule():
                 # the kernel's source changed since the counters were taken
                 assert bench.load_traffic(phase, wl, SCHEDULES[0]) is None
                 continue
+            prof = rec.get("schedule", {})
             for s in SCHEDULES:
                 got = bench.load_traffic(phase, wl, s)
-                if bench.kernel_signature(phase, s) in k["kernel"]:
-                    assert got == k["hbm_bytes_per_launch"]
+                same = bench.kernel_signature(phase, s) in k["kernel"]
+                if phase.endswith("_t2"):
+                    same = same and s["tier1_shape"] == prof.get("tier1_shape", 0)
+                if phase in ("rev_t1", "rev_t2"):
+                    same = same and s["rev_first_tier"] == prof.get("rev_first_tier", 0)
+                if phase == "rev_t2":
+                    same = same and s["rev_split"] == prof.get("rev_split", 1)
+                if same:
+                    assert got == k["hbm_bytes_per_launch"], (wl, phase, s)
                 else:
                     assert got is None, (wl, phase, s)
         assert bench.load_traffic("rev_t0", wl + "_other", SCHEDULES[0]) is None

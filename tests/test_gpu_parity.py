@@ -191,6 +191,34 @@ def test_schedule_invariance_reverse_split(im, case):
         im.Workspace().set_rev_split(3)
 
 
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[6]], ids=["nethept_wc", "dense_p30", "hub_star"])
+def test_schedule_invariance_reverse_first_tier(im, case):
+    # reverse tasks starting on tier 0 or on tier 1 (no tier-0 launch):
+    # identical gain vectors in every round, and the same decrements
+    _, g, R, k, seed = case
+    d = _dev(im, g)
+    s_ref, g_ref, tr_ref, st = oracle.select_du(g.row_ptr, g.col, g.prob, R, k, seed, trace=True)
+    for first in (0, 1):
+        ws = im.Workspace()
+        ws.set_rev_first_tier(first)
+        ws.profile_enable(["rev_t0", "rev_t1"])
+        seeds, gains, tr = im.select(d, R, k, seed, ws=ws, trace=True)
+        assert np.array_equal(seeds.cpu().numpy(), s_ref.astype(np.int64)), first
+        assert np.array_equal(gains.cpu().numpy(), g_ref.astype(np.int64)), first
+        tr = tr.cpu().numpy()
+        for t in range(k + 1):
+            assert np.array_equal(tr[t], tr_ref[t].astype(np.int64)), (first, t)
+        gs = ws.stats()
+        assert gs["trav_rev"] == st["trav_rev"] and gs["decrements"] == st["decrements"], first
+        prof = ws.profile()
+        if first == 1:
+            assert prof["rev_t0"][1] == 0 and gs["reached_rev_t0"] == 0   # no tier-0 launch
+            assert prof["rev_t1"][1] > 0
+        ws.close()
+    with pytest.raises(im.ImError):
+        im.Workspace().set_rev_first_tier(2)
+
+
 def test_repeat_and_workspace_reuse(im):
     g1 = gg.workload_graph("nethept_wc")
     g2 = gg.workload_graph("tiny_uic")

@@ -225,10 +225,10 @@ def test_autotune_choice_persists_in_the_cache_file(im, tmp_path):
     (t1, s1), (t2, s2) = outs
     assert t1["tried"] > 0 and t2["tried"] == 0
     keys = ("hub_degree", "tier1_shape", "tier2_lanes", "max_slots", "coop_forward", "affected_gain",
-            "fwd_groups", "rev_split")
+            "fwd_groups", "rev_split", "rev_first_tier")
     assert {k: t1[k] for k in keys} == {k: t2[k] for k in keys}
     lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("im-tune-3 2000 20000 64 ")
+    assert len(lines) == 1 and lines[0].startswith("im-tune-4 2000 20000 64 ")
     with open(os.path.join(GOLDEN, "tiny_uic.json")) as f:
         assert s1 == s2 == json.load(f)["seeds"]
 
