@@ -66,3 +66,44 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_binding_constants_match_the_header(tmp_path):
+    # every IM_* integer constant of the binding (status codes, limits,
+    # option ids) and the phase names' order, against the values the C
+    # compiler takes from include/im.h
+    import shutil
+    import subprocess
+    import pytest
+    from paper_1212_4779_amd import _native
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    consts = {k: v for k, v in vars(_native).items() if k.startswith("IM_") and isinstance(v, int)}
+    with open(os.path.join(ROOT, "include", "im.h")) as f:
+        header = f.read()
+    declared = set(re.findall(r"\b(IM_[A-Z0-9_]+)\b", header))
+    consts = {k: v for k, v in consts.items() if k in declared}
+    assert {"IM_OK", "IM_EINVAL", "IM_R_MAX", "IM_PH_MAX", "IM_OPT_REV_SPLIT",
+            "IM_OPT_REV_FIRST_TIER", "IM_NOALLOC_SCRATCH_BYTES"} <= set(consts)
+    phases = ["IM_PH_" + p.upper() for p in _native.PHASES]
+    assert set(phases) <= declared
+    lines = ["#include <stdio.h>", '#include "im.h"', "int main(void) {"]
+    for k in sorted(consts):
+        lines.append(f'printf("{k} %lld\\n", (long long)({k}));')
+    for i, k in enumerate(phases):
+        lines.append(f'printf("PHASE{i} %lld\\n", (long long)({k}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "consts"
+    build = subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                            str(exe)], capture_output=True, text=True)
+    assert build.returncode == 0, build.stderr[-2000:]
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {l.split()[0]: int(l.split()[1]) for l in out if l.strip()}
+    for k, v in consts.items():
+        assert got[k] == v, k
+    for i in range(len(phases)):
+        assert got[f"PHASE{i}"] == i, phases[i]
+    assert len(phases) == got["IM_PH_MAX"]
